@@ -1,0 +1,109 @@
+"""Pins for the oracle's spectral density and amplitude (Eqs. (8), (12)-(14)).
+
+Each test checks a property fixed by the paper or by mathematics, not the formula retyped:
+* the peak of chi is 1 (C normalises max chi = 1, the sentence after Eq. (13)), found by a
+  dense numerical search rather than the closed form;
+* chi(0) = 0 and the small-k log-log slope is alpha (Eq. (4), Eq. (14));
+* Eq. (12) reduces to the Euclidean norm at p = 2, a = b, to the L1 norm at p = 1 and to the
+  max norm as p -> infinity (the sentence after Eq. (12));
+* the amplitude is even, rotating the mask by 90 degrees swaps a and b, and with k0 = 0 the
+  band reduces to Eq. (13)'s exp(alpha ln K - K^2 / (2 sigma^2)) up to the constant C.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.spectral import superellipse_K
+
+
+def F(**kw):
+    base = dict(p=2.0, semi=(1.0, 1.0, 1.0), rot=0.0, alpha=2.0, k0=0.2, width=0.05)
+    base.update(kw)
+    return O.FilterParams(**base)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(alpha=4, k0=0.0, width=0.06217), dict(alpha=20, k0=0.0),
+                                dict(alpha=0.5, k0=0.3, width=0.02), dict(alpha=100, k0=0.0, width=0.06)])
+def test_peak_is_one(kw):
+    f = F(**kw)
+    K = np.linspace(1e-6, 3.0, 2_000_001)
+    lc = O.ln_chi_rel(K, f)
+    assert abs(np.max(lc)) < 1e-9
+    assert np.all(lc <= 1e-12)
+
+
+def test_chi_zero_at_origin_and_slope_alpha():
+    for alpha in (0.5, 2.0, 4.0, 6.0):
+        f = F(alpha=alpha, k0=0.2, width=0.05)
+        assert np.exp(O.ln_chi_rel(np.array([0.0]), f))[0] == 0.0
+        K1, K2 = 1e-9, 2e-9
+        slope = (O.ln_chi_rel(np.array([K2]), f) - O.ln_chi_rel(np.array([K1]), f)) / np.log(K2 / K1)
+        assert abs(slope[0] - alpha) < 1e-5
+
+
+def _grid(n=40):
+    k = np.linspace(-1, 1, n)
+    return [k.reshape(-1, 1), k.reshape(1, -1)]          # (ky, kx) axis order
+
+
+def test_norm_special_cases():
+    ky, kx = _grid()
+    K2, _, _ = superellipse_K([ky, kx], F(p=2.0))
+    np.testing.assert_allclose(K2, np.hypot(kx, ky), rtol=1e-14, atol=1e-15)
+    K1, _, _ = superellipse_K([ky, kx], F(p=1.0))
+    np.testing.assert_allclose(K1, np.abs(kx) + np.abs(ky), rtol=1e-14, atol=1e-15)
+    Kinf, _, _ = superellipse_K([ky, kx], F(p=400.0))
+    m = np.maximum(np.abs(kx), np.abs(ky))
+    assert np.all(np.abs(Kinf - m) <= 0.01 * m + 1e-15)
+    # anisotropy: a = 2 halves the x contribution
+    Ka, _, _ = superellipse_K([ky, kx], F(p=2.0, semi=(2.0, 1.0, 1.0)))
+    np.testing.assert_allclose(Ka, np.hypot(kx / 2, ky), rtol=1e-14, atol=1e-15)
+    # 3D: a third term (|kz|/c)^p
+    kz = np.linspace(-1, 1, 7).reshape(-1, 1, 1)
+    K3, _, _ = superellipse_K([kz, ky[None], kx[None]], F(p=2.0, semi=(1.0, 1.0, 3.0)))
+    np.testing.assert_allclose(K3, np.sqrt(kx[None] ** 2 + ky[None] ** 2 + (kz / 3) ** 2), rtol=1e-14)
+
+
+def test_amplitude_even_and_rotation_swaps_axes():
+    f = F(p=3.0, semi=(2.0, 1.0, 1.0), rot=0.37)
+    ky, kx = _grid(33)
+    Kp, _, _ = superellipse_K([ky, kx], f)
+    Km, _, _ = superellipse_K([-ky, -kx], f)
+    np.testing.assert_allclose(Kp, Km, rtol=1e-14)
+    g1 = F(p=3.0, semi=(2.0, 1.0, 1.0), rot=np.pi / 2)
+    g2 = F(p=3.0, semi=(1.0, 2.0, 1.0), rot=0.0)
+    K1, _, _ = superellipse_K([ky, kx], g1)
+    K2, _, _ = superellipse_K([ky, kx], g2)
+    np.testing.assert_allclose(K1, K2, rtol=1e-12)
+
+
+def test_k0_zero_reduces_to_eq13():
+    f = F(p=1.0, alpha=20.0, k0=0.0, width=0.06)
+    K = np.linspace(1e-3, 1.5, 5001)
+    raw = np.exp(f.alpha * np.log(K) - K ** 2 / (2 * f.width ** 2))
+    chi = np.exp(O.ln_chi_rel(K, f))
+    ratio = chi / raw
+    np.testing.assert_allclose(ratio, ratio[0], rtol=1e-9)
+
+
+def test_hsym_only_differs_on_rotated_nyquist_planes():
+    dims = (12, 16)
+    f0 = F(p=3.0, semi=(2.0, 1.0, 1.0), rot=0.0, k0=0.6, width=0.3)
+    np.testing.assert_array_equal(O.amplitude_sym(dims, f0), O.amplitude_half(dims, f0))
+    f1 = f0.replace(rot=0.4)
+    Hs, H = O.amplitude_sym(dims, f1), O.amplitude_half(dims, f1)
+    diff = Hs != H
+    diff[6, :] = False          # m_y = n_y / 2
+    diff[:, 8] = False          # m_x = n_x / 2
+    assert not diff.any()
+    assert (Hs[6, 1:8] != H[6, 1:8]).any()
+
+
+def test_degenerate_filter_raises():
+    # a band far narrower than the lattice step, centred between lattice shells
+    # (|kappa| = 0.5303 and 0.5590 on a 16^2 grid): every mode has ln chi < -80
+    f = F(p=2.0, alpha=2.0, k0=0.545, width=1e-4)
+    with pytest.raises(O.DegenerateFilter):
+        O.amplitude_half((16, 16), f)
+    O.amplitude_half((16, 16), f.replace(width=0.02))

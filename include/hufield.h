@@ -1,0 +1,158 @@
+/*
+ * hufield: generator of anisotropic hyperuniform continuous random fields on gfx950.
+ *
+ * The method is the single-shot spectral filter of Zhong & Mao (arXiv 2509.08675):
+ *   white noise -> forward FFT -> multiply by A = sqrt(chi)            (Sec. II.B, Eq. (8))
+ *   chi(k) = C exp[alpha ln K - (K - k0)^2 / (2 w^2)], K the superellipse norm
+ *                                                                      (Eqs. (12)-(13); k0 = 0 is Eq. (13))
+ *   -> inverse FFT to a real field                                     (Eq. (9))
+ *   -> f <- sigma_f (f - <f>) / sqrt(Var f)                           (Eq. (15))
+ *   -> sign map f -> +-1 and binned power spectra                      (Sec. II.B end, Sec. III figures)
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Grid: hu_dims.n[0] is the slowest axis and n[ndim-1] = n_x the fastest (row-major).  2D is
+ *   (n_y, n_x), 3D is (n_z, n_y, n_x).  Each n must be 2^k (4..2048) or 3*2^k (6..768), and n_x/2
+ *   must also be one of the supported lengths (so n_x >= 4).
+ * Wavenumbers: kappa_i = 2 m~_i / n_i in units of the Nyquist wavenumber (m~ the signed index).
+ * Noise: voxel i (row-major linear index within a field) takes normal z_{i mod 4} of the
+ *   Philox4x32-10 block i // 4 with key (seed lo, seed hi) and counter (block lo, block hi, 0, 0);
+ *   uniforms u = (2*(x >> 9) + 1) 2^-24 and Box-Muller on (u0,u1), (u2,u3).
+ * Transforms: forward kernel exp(-i k.x), unnormalised.
+ * Variance: population (ddof = 0).  Sign map: f >= 0 -> +1, else -1.
+ * Spectrum: P(k) = |DFT(g)(k)|^2 / N.  Bins: radial r = floor(R |kappa|) (exact integer rule,
+ *   edges go up), angular (2D only) A bins over [0, pi) after folding k -> -k; slot
+ *   r * A + a, plus one last slot (index R * A) for the corner modes with |kappa| >= 1.  Each
+ *   half-spectrum mode counts with multiplicity 2, or 1 where m_x is 0 or n_x/2.
+ *
+ * Memory: every array argument is DEVICE memory owned by the caller unless marked "host".
+ *   The library keeps per-process read-only tables (twiddles, bin edges) that it allocates on
+ *   first use of a size; apart from those it never allocates.  Workspace is caller-provided
+ *   and its required size comes from hu_workspace_size.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  All work is enqueued
+ *   asynchronously; outputs are valid once the stream has been synchronised.  No call
+ *   synchronises the stream or reads device memory back to the host.
+ * Errors: every argument is validated on the host before any launch; on error nothing is
+ *   enqueued and a negative HU_ERR_* code is returned (hu_strerror names it).  HIP launch
+ *   errors are returned as HU_ERR_HIP; errors of earlier asynchronous work surface there too.
+ *   A filter with no support on the lattice (max ln chi < -80) cannot be detected on the host
+ *   without a pass over the lattice, so it is reported in the stats output (flag = 1) and the
+ *   field is then all zeros.
+ * Determinism: fields, sign maps and counts are bit-reproducible; FP64 bin sums and the
+ *   variance are accumulated with FP64 atomics and may differ in the last bits between runs.
+ */
+#ifndef HUFIELD_H
+#define HUFIELD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HU_OK = 0,
+  HU_ERR_ARG = -1,        /* null pointer, non-positive parameter, bad batch or bin count */
+  HU_ERR_SIZE = -2,       /* grid size outside the supported set */
+  HU_ERR_ALIGN = -3,      /* array not aligned to 16 bytes (workspace: 256 bytes) */
+  HU_ERR_WORKSPACE = -4,  /* workspace smaller than hu_workspace_size */
+  HU_ERR_DEGENERATE = -5, /* reserved: returned by host-side helpers for a filter with no lattice support */
+  HU_ERR_HIP = -6,        /* a HIP runtime call failed */
+  HU_ERR_UNSUPPORTED = -7 /* valid request that this build does not implement */
+};
+
+enum { HU_F32 = 0, HU_I8 = 1 };
+
+/* Operations for hu_workspace_size. */
+enum { HU_OP_GEN_FIELD = 0, HU_OP_PIPELINE = 1, HU_OP_POWER_SPECTRUM = 2, HU_OP_LOSS = 3 };
+
+typedef struct hu_dims {
+  int32_t ndim;   /* 2 or 3 */
+  int32_t n[3];   /* n[0] slowest ... n[ndim-1] = n_x fastest */
+} hu_dims;
+
+/* Filter parameters (Eqs. (12)-(13) and Eq. (15)); all in Nyquist units. */
+typedef struct hu_filter {
+  double p;        /* superellipse exponent, > 0 (Eq. (12)) */
+  double semi[3];  /* semi-axes a (x), b (y), c (z), > 0; c unused in 2D */
+  double rot;      /* mask rotation, radians, counter-clockwise in (kappa_x, kappa_y); about z in 3D */
+  double alpha;    /* small-k exponent, > 0 (Eqs. (13)-(14)) */
+  double k0;       /* band centre, >= 0 (0 gives Eq. (13) exactly) */
+  double width;    /* Gaussian band width w, > 0 (sigma of Eq. (13)) */
+  double sigma_f;  /* target standard deviation of the field, > 0 (Eq. (15)) */
+} hu_filter;
+
+typedef struct hu_bins {
+  int32_t n_radial;   /* R >= 1 */
+  int32_t n_angular;  /* A >= 1; A > 1 only for 2D grids */
+} hu_bins;
+
+/* Outputs of hu_pipeline; a NULL member skips that output (and the work only it needs). */
+typedef struct hu_outputs {
+  float* field;        /* [B][N] FP32 normalised field */
+  int8_t* pm1;         /* [B][N] sign map, +1 / -1 */
+  double* stats;       /* [B][4] mu_raw, var_raw, max ln chi over the lattice, degenerate flag (0/1) */
+  uint64_t* counts;    /* [B][2] n_pos = #(+1), n_near = #(|f| < near_tol * sigma_f) */
+  double* cont_sum;    /* [B][R*A+1] binned spectrum of the normalised continuous field */
+  uint64_t* cont_cnt;  /* [B][R*A+1] modes per bin (with multiplicity) */
+  double* pm1_sum;     /* [B][R*A+1] binned spectrum of the +-1 field */
+  uint64_t* pm1_cnt;   /* [B][R*A+1] */
+} hu_outputs;
+
+/* Size in bytes of the workspace that `op` needs for `batch` fields of `dims` with `bins`
+ * (bins may be NULL when the op uses none).  Returns HU_OK and writes *bytes (host). */
+int hu_workspace_size(int op, hu_dims dims, int32_t batch, const hu_bins* bins, size_t* bytes);
+
+/* Generate `batch` normalised fields on `dims` with one filter and per-field seeds
+ * (Sec. II.B pipeline, Eqs. (8), (9), (12), (13), (15)).
+ *   filt   host pointer to the filter parameters
+ *   seeds  host array of `batch` 64-bit seeds
+ *   field  [B][N] FP32 output; stats [B][4] as in hu_outputs (may be NULL)
+ *   cont_bins  host pointer, or NULL to skip the continuous spectrum; cont_sum/cont_cnt then unused
+ *   work   device workspace of at least hu_workspace_size(HU_OP_GEN_FIELD, ...) bytes */
+int hu_gen_field(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds,
+                 float* field, double* stats, const hu_bins* cont_bins, double* cont_sum,
+                 uint64_t* cont_cnt, void* work, size_t work_bytes, void* stream);
+
+/* Sign map of `batch` FP32 fields (the +-1 two-phase medium of Sec. II.B, last paragraphs):
+ * out = +1 where field >= 0 else -1; counts [B][2] = (n_pos, n_near) with
+ * n_near = #(|field| < near_tol), or counts = NULL.  Needs no workspace. */
+int hu_threshold(hu_dims dims, int32_t batch, const float* field, int8_t* out, uint64_t* counts,
+                 float near_tol, void* stream);
+
+/* Binned power spectrum P = |DFT(x)|^2 / N of `batch` real fields x (dtype HU_F32 or HU_I8),
+ * the spectral densities shown in the figure rows of Sec. III.  sum [B][R*A+1] FP64,
+ * cnt [B][R*A+1] (or NULL).  Workspace: hu_workspace_size(HU_OP_POWER_SPECTRUM, ...). */
+int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype, hu_bins bins,
+                      double* sum, uint64_t* cnt, void* work, size_t work_bytes, void* stream);
+
+/* The whole hot path in one call: field, sign map with counts, continuous and +-1 spectra,
+ * fused so that normalisation, threshold and the first transform of the +-1 field share one
+ * pass.  near_tol is relative to sigma_f (1e-5 is the parity convention).
+ * Workspace: hu_workspace_size(HU_OP_PIPELINE, ...). */
+int hu_pipeline(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds,
+                hu_bins bins, float near_tol, const hu_outputs* out, void* work, size_t work_bytes,
+                void* stream);
+
+const char* hu_strerror(int code);
+
+/* Raw Philox4x32-10 words and the derived FP32 normals for blocks first .. first+count-1 under
+ * `seed` (the noise stream of every entry point).  words [4*count] uint32 and normals
+ * [4*count] FP32, either may be NULL.  For parity tests. */
+int hu_debug_philox(uint64_t seed, uint64_t first, uint64_t count, uint32_t* words, float* normals,
+                    void* stream);
+
+/* Kernel timing with HIP events recorded on the launch stream around every kernel the library
+ * enqueues.  hu_profile_enable(1) resets the counters and starts recording; hu_profile_read
+ * fills up to `cap` entries (host arrays) with each kernel family's name, launch count and
+ * summed milliseconds, and returns the number of families.  hu_profile_read synchronises on
+ * the recorded events. */
+int hu_profile_enable(int on);
+int hu_profile_read(char (*names)[48], int64_t* launches, double* total_ms, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HUFIELD_H */

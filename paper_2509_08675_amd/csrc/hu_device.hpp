@@ -1,0 +1,392 @@
+// Device building blocks for the hyperuniform-field kernels (gfx950, wave64).
+//
+//  * complex helpers and radix-2/3/4/8/16 DFTs held in registers;
+//  * Stockham autosort stages: butterfly j reads elements j + r L/R, applies the twiddles
+//    exp(-+ 2 pi i r (j mod Ns) / (Ns R)), and writes (j / Ns) Ns R + (j mod Ns) + r Ns, so the last
+//    stage leaves the transform in natural order in the same j + r L/R register pattern the
+//    first stage reads; stages exchange through LDS;
+//  * Philox4x32-10 (Salmon et al., SC'11) and Box-Muller for the white noise;
+//  * the superellipse filter amplitude of Eqs. (12)-(13) (with band centre k0) in FP32;
+//  * the exact integer radial / FP64 angular bin index.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hu {
+
+// ---------------------------------------------------------------------------------------------
+// complex arithmetic on float2
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// multiply by exp(-+ i 2 pi m / 16) for the compile-time m
+template <int M, bool INV>
+__device__ __forceinline__ float2 mul_w16(float2 a) {
+  constexpr double PI = 3.14159265358979323846;
+  constexpr int m = M % 16;
+  if constexpr (m == 0) return a;
+  if constexpr (m == 4) return mul_mi<INV>(a);
+  if constexpr (m == 8) return make_float2(-a.x, -a.y);
+  if constexpr (m == 12) return mul_mi<!INV>(a);
+  // generic constant twiddle; the constants are FP64 expressions rounded once to FP32
+  constexpr float c = (float)(m == 1 ? 0.92387953251128675613 : m == 2 ? 0.70710678118654752440
+                              : m == 3 ? 0.38268343236508977173 : m == 5 ? -0.38268343236508977173
+                              : m == 6 ? -0.70710678118654752440 : m == 7 ? -0.92387953251128675613
+                              : m == 9 ? -0.92387953251128675613 : m == 10 ? -0.70710678118654752440
+                              : m == 11 ? -0.38268343236508977173 : m == 13 ? 0.38268343236508977173
+                              : m == 14 ? 0.70710678118654752440 : 0.92387953251128675613);
+  constexpr float s = (float)(m == 1 ? 0.38268343236508977173 : m == 2 ? 0.70710678118654752440
+                              : m == 3 ? 0.92387953251128675613 : m == 5 ? 0.92387953251128675613
+                              : m == 6 ? 0.70710678118654752440 : m == 7 ? 0.38268343236508977173
+                              : m == 9 ? -0.38268343236508977173 : m == 10 ? -0.70710678118654752440
+                              : m == 11 ? -0.92387953251128675613 : m == 13 ? -0.92387953251128675613
+                              : m == 14 ? -0.70710678118654752440 : -0.38268343236508977173);
+  (void)PI;
+  // forward: exp(-i t) = (c, -s); inverse: (c, +s), with (c, s) = (cos t, sin t)
+  const float sy = INV ? s : -s;
+  return make_float2(a.x * c - a.y * sy, a.x * sy + a.y * c);
+}
+
+// ---------------------------------------------------------------------------------------------
+// small DFTs in registers, natural order in and out
+// ---------------------------------------------------------------------------------------------
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a0, float2& a1) {
+  float2 t = a0;
+  a0 = cadd(t, a1);
+  a1 = csub(t, a1);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  float2 t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
+  const float h = 0.86602540378443864676f;  // sqrt(3)/2
+  float2 t = cadd(a1, a2), u = csub(a1, a2);
+  float2 m = make_float2(a0.x - 0.5f * t.x, a0.y - 0.5f * t.y);
+  float2 v = cscale(mul_mi<INV>(u), h);
+  a0 = cadd(a0, t);
+  a1 = cadd(m, v);
+  a2 = csub(m, v);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* a) {
+  // even / odd split: E = DFT4(a0,a2,a4,a6), O = DFT4(a1,a3,a5,a7), X_k = E_k + w8^k O_k
+  float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  float2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  o1 = mul_w16<2, INV>(o1);
+  o2 = mul_w16<4, INV>(o2);
+  o3 = mul_w16<6, INV>(o3);
+  a[0] = cadd(e0, o0); a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1); a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2); a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3); a[7] = csub(e3, o3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(float2* a) {
+  // 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+  float2 y[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    float2 b0 = a[n2], b1 = a[4 + n2], b2 = a[8 + n2], b3 = a[12 + n2];
+    dft4<INV>(b0, b1, b2, b3);
+    y[n2 * 4 + 0] = b0; y[n2 * 4 + 1] = b1; y[n2 * 4 + 2] = b2; y[n2 * 4 + 3] = b3;
+  }
+  // twiddles w16^(n2 k1)
+  y[1 * 4 + 1] = mul_w16<1, INV>(y[1 * 4 + 1]);
+  y[1 * 4 + 2] = mul_w16<2, INV>(y[1 * 4 + 2]);
+  y[1 * 4 + 3] = mul_w16<3, INV>(y[1 * 4 + 3]);
+  y[2 * 4 + 1] = mul_w16<2, INV>(y[2 * 4 + 1]);
+  y[2 * 4 + 2] = mul_w16<4, INV>(y[2 * 4 + 2]);
+  y[2 * 4 + 3] = mul_w16<6, INV>(y[2 * 4 + 3]);
+  y[3 * 4 + 1] = mul_w16<3, INV>(y[3 * 4 + 1]);
+  y[3 * 4 + 2] = mul_w16<6, INV>(y[3 * 4 + 2]);
+  y[3 * 4 + 3] = mul_w16<9, INV>(y[3 * 4 + 3]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    float2 b0 = y[0 * 4 + k1], b1 = y[1 * 4 + k1], b2 = y[2 * 4 + k1], b3 = y[3 * 4 + k1];
+    dft4<INV>(b0, b1, b2, b3);
+    a[k1] = b0; a[k1 + 4] = b1; a[k1 + 8] = b2; a[k1 + 12] = b3;
+  }
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* a) {
+  if constexpr (R == 2) dft2<INV>(a[0], a[1]);
+  else if constexpr (R == 3) dft3<INV>(a[0], a[1], a[2]);
+  else if constexpr (R == 4) dft4<INV>(a[0], a[1], a[2], a[3]);
+  else if constexpr (R == 8) dft8<INV>(a);
+  else if constexpr (R == 16) dft16<INV>(a);
+  else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Stockham plans.  Plan<L>: E elements per thread, P = L / E threads per transform, radix list
+// fwd (first radix first) and its reverse.  Every radix divides E.
+// ---------------------------------------------------------------------------------------------
+template <int... Rs>
+struct Radices {};
+
+template <int L>
+struct Plan;
+#define HU_PLAN(LEN, EPT, ...)                         \
+  template <>                                          \
+  struct Plan<LEN> {                                   \
+    static constexpr int E = EPT;                      \
+    static constexpr int P = LEN / EPT;                \
+    using fwd = Radices<__VA_ARGS__>;                  \
+  };
+HU_PLAN(2, 2, 2)
+HU_PLAN(3, 3, 3)
+HU_PLAN(4, 4, 4)
+HU_PLAN(6, 6, 3, 2)
+HU_PLAN(8, 8, 8)
+HU_PLAN(12, 12, 3, 4)
+HU_PLAN(16, 16, 16)
+HU_PLAN(24, 24, 3, 8)
+HU_PLAN(32, 16, 8, 4)
+HU_PLAN(48, 12, 3, 4, 4)
+HU_PLAN(64, 16, 16, 4)
+HU_PLAN(96, 24, 3, 4, 8)
+HU_PLAN(128, 16, 16, 8)
+HU_PLAN(192, 24, 3, 8, 8)
+HU_PLAN(256, 16, 16, 16)
+HU_PLAN(384, 24, 3, 8, 8, 2)
+HU_PLAN(512, 16, 8, 8, 8)
+HU_PLAN(768, 24, 3, 8, 8, 4)
+HU_PLAN(1024, 16, 16, 8, 8)
+HU_PLAN(1536, 24, 3, 8, 8, 8)
+HU_PLAN(2048, 16, 16, 16, 8)
+#undef HU_PLAN
+
+template <int R0, int... Rs>
+struct FirstR { static constexpr int value = R0; };
+template <int R0, int... Rs>
+struct LastR { static constexpr int value = LastR<Rs...>::value; };
+template <int R0>
+struct LastR<R0> { static constexpr int value = R0; };
+
+template <typename A, typename B>
+struct RevImpl;
+template <int... Done>
+struct RevImpl<Radices<>, Radices<Done...>> { using type = Radices<Done...>; };
+template <int R0, int... Rs, int... Done>
+struct RevImpl<Radices<R0, Rs...>, Radices<Done...>> {
+  using type = typename RevImpl<Radices<Rs...>, Radices<R0, Done...>>::type;
+};
+template <typename A>
+using Reverse = typename RevImpl<A, Radices<>>::type;
+
+template <typename A>
+struct RadInfo;
+template <int... Rs>
+struct RadInfo<Radices<Rs...>> {
+  static constexpr int first = FirstR<Rs...>::value;
+  static constexpr int last = LastR<Rs...>::value;
+};
+
+// One Stockham stage on the registers of thread p: butterflies j = p + P b, b < E/R.
+template <int L, int R, int NS, int P, int E, bool INV>
+__device__ __forceinline__ void stage_compute(float2 (&v)[E], int p, const float2* __restrict__ tw) {
+#pragma unroll
+  for (int b = 0; b < E / R; ++b) {
+    if constexpr (NS > 1) {
+      const int j = p + P * b;
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[r * k * (L / (NS * R))];
+        if (INV) w.y = -w.y;
+        v[b * R + r] = cmul(v[b * R + r], w);
+      }
+    }
+    dft<R, INV>(&v[b * R]);
+  }
+}
+
+template <int L, int R, int NS, int P, int E>
+__device__ __forceinline__ void stage_store(const float2 (&v)[E], float2* lds, int p) {
+#pragma unroll
+  for (int b = 0; b < E / R; ++b) {
+    const int j = p + P * b;
+    const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[base + r * NS] = v[b * R + r];
+  }
+}
+
+template <int L, int R, int P, int E>
+__device__ __forceinline__ void stage_load(float2 (&v)[E], const float2* lds, int p) {
+#pragma unroll
+  for (int b = 0; b < E / R; ++b) {
+    const int j = p + P * b;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b * R + r] = lds[j + r * (L / R)];
+  }
+}
+
+// Element index held in register slot i for a transform whose first / last stage has radix R.
+template <int L, int R, int P>
+__device__ __forceinline__ int slot_index(int i, int p) {
+  return p + P * (i / R) + (i % R) * (L / R);
+}
+
+template <int L, int P, int E, bool INV, int NS, int R, int... Rest>
+__device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int p, const float2* __restrict__ tw) {
+  stage_compute<L, R, NS, P, E, INV>(v, p, tw);
+  if constexpr (sizeof...(Rest) > 0) {
+    constexpr int R2 = FirstR<Rest...>::value;
+    __syncthreads();
+    stage_store<L, R, NS, P, E>(v, lds, p);
+    __syncthreads();
+    stage_load<L, R2, P, E>(v, lds, p);
+    fft_stages<L, P, E, INV, NS * R, Rest...>(v, lds, p, tw);
+  }
+}
+
+template <int L, int P, int E, bool INV, int... Rs>
+__device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[E], float2* lds, int p,
+                                        const float2* __restrict__ tw) {
+  fft_stages<L, P, E, INV, 1, Rs...>(v, lds, p, tw);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Philox4x32-10 and Box-Muller
+// ---------------------------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox4x32_10(uint64_t block, uint64_t seed) {
+  uint32_t c0 = (uint32_t)block, c1 = (uint32_t)(block >> 32), c2 = 0u, c3 = 0u;
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+// u = (2 (x >> 9) + 1) 2^-24: an odd multiple of 2^-24, exact in FP32
+__device__ __forceinline__ float word_to_uniform(uint32_t x) {
+  return (float)((x >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
+}
+
+__device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, float& z0, float& z1) {
+  const float u0 = word_to_uniform(w0), u1 = word_to_uniform(w1);
+  const float r = sqrtf(-2.0f * logf(u0));
+  float s, c;
+  sincospif(2.0f * u1, &s, &c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+__device__ __forceinline__ void noise4(uint64_t block, uint64_t seed, float (&z)[4]) {
+  const U4 w = philox4x32_10(block, seed);
+  box_muller(w.x, w.y, z[0], z[1]);
+  box_muller(w.z, w.w, z[2], z[3]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Filter amplitude (Eqs. (12)-(13) with band centre k0) in FP32
+// ---------------------------------------------------------------------------------------------
+struct FiltDev {
+  float cr, sr;          // cos / sin of the rotation
+  float ia, ib, ic;      // 1 / semi-axes
+  float p, ip;           // p and 1/p
+  float alpha, k0;
+  float inv2w2;          // 1 / (2 w^2)
+  float lnchimax;        // ln chi at K* (continuum peak)
+  int rotated;           // rot != 0 (H_sym differs from H on x / y Nyquist planes)
+};
+
+// ln chi (relative to its peak) at the (unrotated) wavenumber (kx, ky, kz); -inf-like at K = 0.
+__device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, float kz) {
+  const float kxr = f.cr * kx + f.sr * ky;
+  const float kyr = -f.sr * kx + f.cr * ky;
+  const float ux = fabsf(kxr) * f.ia, uy = fabsf(kyr) * f.ib, uz = fabsf(kz) * f.ic;
+  const float um = fmaxf(ux, fmaxf(uy, uz));
+  if (!(um > 0.0f)) return -1.0e30f;
+  const float ium = 1.0f / um;
+  // sum (u_i / u_max)^p, each ratio in [0, 1]; exp2(p log2 r) with r = 0 -> 0
+  float S = 0.0f;
+  const float rx = ux * ium, ry = uy * ium, rz = uz * ium;
+  S += (rx > 0.0f) ? exp2f(f.p * __log2f(rx)) : 0.0f;
+  S += (ry > 0.0f) ? exp2f(f.p * __log2f(ry)) : 0.0f;
+  S += (rz > 0.0f) ? exp2f(f.p * __log2f(rz)) : 0.0f;
+  const float lnK = __logf(um) + __logf(S) * f.ip;
+  const float K = __expf(lnK);
+  const float d = K - f.k0;
+  return f.alpha * lnK - d * d * f.inv2w2 - f.lnchimax;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bin index: exact integer radial rule, FP64 angular edges tested with separately rounded
+// products.  q = signed index scaled to the common denominator D = lcm(n_i).
+// ---------------------------------------------------------------------------------------------
+struct BinDev {
+  int nr, na;
+  long long D2;          // D^2
+  long long fourR2;      // 4 R^2
+  const double* ex;      // angular edge unit vectors, na - 1 of them
+  const double* ey;
+};
+
+#pragma clang fp contract(off)
+__device__ __forceinline__ bool edge_le(const BinDev& b, int j, double qx, double qy) {
+  // angle(e_j) <= angle(q) for j in 1..na-1 (edges stored from index 0)
+  const double t1 = b.ex[j - 1] * qy;
+  const double t2 = b.ey[j - 1] * qx;
+  return (t1 - t2) >= 0.0;
+}
+
+__device__ __forceinline__ int bin_index(const BinDev& b, long long s, long long qx, long long qy) {
+  // s = sum of q_i^2; radial r = max{r : r^2 D^2 <= 4 R^2 s}
+  const long long rhs = b.fourR2 * s;
+  long long r = (long long)sqrt((double)rhs / (double)b.D2);
+  if (r * r * b.D2 > rhs) --r;
+  if ((r + 1) * (r + 1) * b.D2 <= rhs) ++r;
+  if (r >= b.nr) return b.nr * b.na;
+  int a = 0;
+  if (b.na > 1 && s != 0) {
+    if (qy < 0) { qy = -qy; qx = -qx; }
+    const double dx = (double)qx, dy = (double)qy;
+    // estimate from atan2, then settle on the exact edge tests
+    float ang = atan2f((float)dy, (float)dx);                 // [0, pi]
+    int g = (int)(ang * (float)b.na * 0.31830988618379067f);
+    g = g < 0 ? 0 : (g > b.na - 1 ? b.na - 1 : g);
+    while (g < b.na - 1 && edge_le(b, g + 1, dx, dy)) ++g;
+    while (g > 0 && !edge_le(b, g, dx, dy)) --g;
+    a = g;
+  }
+  return (int)r * b.na + a;
+}
+#pragma clang fp contract(on)
+
+}  // namespace hu

@@ -1,0 +1,298 @@
+"""Python binding of libhufield.so (the C-ABI in include/hufield.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels of the library.
+PyTorch supplies device memory and the current stream.  There is no CPU fallback: if the
+library is not built, importing this module raises ImportError.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhufield.so")
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError("libhufield.so is not built (run: python -m paper_2509_08675_amd.build); "
+                      "the hyperuniform-field path has no CPU fallback")
+
+_lib = ctypes.CDLL(_LIB_PATH)
+
+HU_OK, HU_ERR_ARG, HU_ERR_SIZE, HU_ERR_ALIGN, HU_ERR_WORKSPACE, HU_ERR_DEGENERATE, HU_ERR_HIP, \
+    HU_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+HU_F32, HU_I8 = 0, 1
+HU_OP_GEN_FIELD, HU_OP_PIPELINE, HU_OP_POWER_SPECTRUM, HU_OP_LOSS = 0, 1, 2, 3
+
+
+class hu_dims(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3)]
+
+
+class hu_filter(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_double), ("semi", ctypes.c_double * 3), ("rot", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("k0", ctypes.c_double), ("width", ctypes.c_double),
+                ("sigma_f", ctypes.c_double)]
+
+
+class hu_bins(ctypes.Structure):
+    _fields_ = [("n_radial", ctypes.c_int32), ("n_angular", ctypes.c_int32)]
+
+
+class hu_outputs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("field", "pm1", "stats", "counts", "cont_sum", "cont_cnt", "pm1_sum", "pm1_cnt")]
+
+
+_vp, _sz, _i32, _u64, _f32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_uint64, ctypes.c_float
+_P = ctypes.POINTER
+
+_lib.hu_workspace_size.argtypes = [ctypes.c_int, hu_dims, _i32, _P(hu_bins), _P(_sz)]
+_lib.hu_gen_field.argtypes = [hu_dims, _i32, _P(hu_filter), _P(_u64), _vp, _vp, _P(hu_bins), _vp, _vp, _vp, _sz,
+                              _vp]
+_lib.hu_threshold.argtypes = [hu_dims, _i32, _vp, _vp, _vp, _f32, _vp]
+_lib.hu_power_spectrum.argtypes = [hu_dims, _i32, _vp, _i32, hu_bins, _vp, _vp, _vp, _sz, _vp]
+_lib.hu_pipeline.argtypes = [hu_dims, _i32, _P(hu_filter), _P(_u64), hu_bins, _f32, _P(hu_outputs), _vp, _sz, _vp]
+_lib.hu_strerror.argtypes = [ctypes.c_int]
+_lib.hu_strerror.restype = ctypes.c_char_p
+_lib.hu_debug_philox.argtypes = [_u64, _u64, _u64, _vp, _vp, _vp]
+_lib.hu_profile_enable.argtypes = [ctypes.c_int]
+_lib.hu_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline",
+           "hu_debug_philox", "hu_profile_enable", "hu_profile_read"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class HuError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+        self.code = code
+
+
+class DegenerateFilter(RuntimeError):
+    """The filter has no support on the lattice (max ln chi < -80), reported by the kernels."""
+
+
+def strerror(code):
+    return _lib.hu_strerror(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != HU_OK:
+        raise HuError(rc, what)
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+def lib_handle():
+    return _lib
+
+
+# ---------------------------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------------------------
+def make_dims(dims):
+    dims = tuple(int(n) for n in dims)
+    d = hu_dims()
+    d.ndim = len(dims)
+    for i, n in enumerate(dims):
+        d.n[i] = n
+    return d
+
+
+def make_filter(f):
+    """hu_filter from a dict (keys p, semi, rot, alpha, k0, width, sigma_f) or an object with those attributes."""
+    get = (lambda k, dflt=None: f.get(k, dflt)) if isinstance(f, dict) else (lambda k, dflt=None: getattr(f, k, dflt))
+    h = hu_filter()
+    h.p = float(get("p"))
+    semi = tuple(get("semi", (1.0, 1.0, 1.0))) + (1.0,) * 3
+    for i in range(3):
+        h.semi[i] = float(semi[i])
+    h.rot = float(get("rot", 0.0))
+    h.alpha = float(get("alpha"))
+    h.k0 = float(get("k0", 0.0))
+    h.width = float(get("width"))
+    h.sigma_f = float(get("sigma_f", 1.0))
+    return h
+
+
+def make_bins(bins):
+    b = hu_bins()
+    b.n_radial, b.n_angular = int(bins[0]), int(bins[1]) if len(bins) > 1 else 1
+    return b
+
+
+def _seeds(seeds):
+    arr = (_u64 * len(seeds))()
+    for i, s in enumerate(seeds):
+        arr[i] = int(s) & 0xFFFFFFFFFFFFFFFF
+    return arr
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace_size(op, dims, batch, bins=None):
+    out = _sz()
+    b = make_bins(bins) if bins is not None else None
+    _check(_lib.hu_workspace_size(int(op), make_dims(dims), int(batch), ctypes.byref(b) if b else None,
+                                  ctypes.byref(out)), "hu_workspace_size")
+    return int(out.value)
+
+
+def alloc_workspace(op, dims, batch, bins=None, device="cuda"):
+    n = workspace_size(op, dims, batch, bins)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def _nb(bins):
+    return int(bins[0]) * (int(bins[1]) if len(bins) > 1 else 1) + 1
+
+
+def u64_view(t):
+    """Host numpy uint64 view of a device int64 tensor written as uint64 by the library."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+# ---------------------------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------------------------
+def gen_field(dims, filt, seeds, cont_bins=None, device="cuda", work=None, out=None):
+    """Normalised fields [B, *dims] (FP32) plus stats [B, 4] and, if cont_bins, the continuous
+    spectrum (sum [B, nb] FP64, cnt [B, nb] uint64-in-int64)."""
+    dims = tuple(int(n) for n in dims)
+    B = len(seeds)
+    field = out if out is not None else torch.empty((B,) + dims, dtype=torch.float32, device=device)
+    stats = torch.empty((B, 4), dtype=torch.float64, device=device)
+    cs = cc = None
+    b = None
+    if cont_bins is not None:
+        nb = _nb(cont_bins)
+        cs = torch.empty((B, nb), dtype=torch.float64, device=device)
+        cc = torch.empty((B, nb), dtype=torch.int64, device=device)
+        b = make_bins(cont_bins)
+    if work is None:
+        work = alloc_workspace(HU_OP_GEN_FIELD, dims, B, cont_bins, device)
+    h = make_filter(filt)
+    _check(_lib.hu_gen_field(make_dims(dims), B, ctypes.byref(h), _seeds(seeds), _ptr(field), _ptr(stats),
+                             ctypes.byref(b) if b else None, _ptr(cs), _ptr(cc), _ptr(work), work.numel(),
+                             _stream(field.device)), "hu_gen_field")
+    return dict(field=field, stats=stats, cont_sum=cs, cont_cnt=cc)
+
+
+def threshold(field, near_tol=1e-5, out=None, counts=True):
+    """Sign map of fields [B, *dims] (FP32, on device): +1 where field >= 0 else -1 (int8), and
+    counts [B, 2] = (n_pos, #(|field| < near_tol))."""
+    dims = tuple(field.shape[1:])
+    B = field.shape[0]
+    t = out if out is not None else torch.empty(field.shape, dtype=torch.int8, device=field.device)
+    cnt = torch.empty((B, 2), dtype=torch.int64, device=field.device) if counts else None
+    _check(_lib.hu_threshold(make_dims(dims), B, _ptr(field), _ptr(t), _ptr(cnt), float(near_tol),
+                             _stream(field.device)), "hu_threshold")
+    return t, cnt
+
+
+def power_spectrum(x, bins, work=None):
+    """Binned periodogram of real fields x [B, *dims] (float32 or int8 on device):
+    sum [B, nb] FP64 and cnt [B, nb]."""
+    dims = tuple(x.shape[1:])
+    B = x.shape[0]
+    if x.dtype == torch.float32:
+        dt = HU_F32
+    elif x.dtype == torch.int8:
+        dt = HU_I8
+    else:
+        raise TypeError("power_spectrum takes float32 or int8 fields")
+    nb = _nb(bins)
+    s = torch.empty((B, nb), dtype=torch.float64, device=x.device)
+    c = torch.empty((B, nb), dtype=torch.int64, device=x.device)
+    if work is None:
+        work = alloc_workspace(HU_OP_POWER_SPECTRUM, dims, B, bins, x.device)
+    _check(_lib.hu_power_spectrum(make_dims(dims), B, _ptr(x), dt, make_bins(bins), _ptr(s), _ptr(c), _ptr(work),
+                                  work.numel(), _stream(x.device)), "hu_power_spectrum")
+    return s, c
+
+
+class PipelineBuffers:
+    """Preallocated outputs and workspace for repeated hu_pipeline calls on one configuration."""
+
+    def __init__(self, dims, batch, bins, device="cuda", want=("field", "pm1", "stats", "counts", "cont", "pm1_spec")):
+        dims = tuple(int(n) for n in dims)
+        self.dims, self.batch, self.bins = dims, int(batch), tuple(bins)
+        nb = _nb(bins)
+        dev = device
+        self.field = torch.empty((batch,) + dims, dtype=torch.float32, device=dev) if "field" in want else None
+        self.pm1 = torch.empty((batch,) + dims, dtype=torch.int8, device=dev) if "pm1" in want else None
+        self.stats = torch.empty((batch, 4), dtype=torch.float64, device=dev) if "stats" in want else None
+        self.counts = torch.empty((batch, 2), dtype=torch.int64, device=dev) if "counts" in want else None
+        if "cont" in want:
+            self.cont_sum = torch.empty((batch, nb), dtype=torch.float64, device=dev)
+            self.cont_cnt = torch.empty((batch, nb), dtype=torch.int64, device=dev)
+        else:
+            self.cont_sum = self.cont_cnt = None
+        if "pm1_spec" in want:
+            self.pm1_sum = torch.empty((batch, nb), dtype=torch.float64, device=dev)
+            self.pm1_cnt = torch.empty((batch, nb), dtype=torch.int64, device=dev)
+        else:
+            self.pm1_sum = self.pm1_cnt = None
+        self.work = alloc_workspace(HU_OP_PIPELINE, dims, batch, bins, dev)
+        o = hu_outputs()
+        for name in ("field", "pm1", "stats", "counts", "cont_sum", "cont_cnt", "pm1_sum", "pm1_cnt"):
+            setattr(o, name, None if getattr(self, name) is None else getattr(self, name).data_ptr())
+        self._out = o
+        self._dims = make_dims(dims)
+        self._bins = make_bins(bins)
+
+
+def pipeline(bufs, filt, seeds, near_tol=1e-5):
+    """The whole hot path into preallocated PipelineBuffers (asynchronous on the current stream)."""
+    if len(seeds) != bufs.batch:
+        raise ValueError("need one seed per field")
+    h = make_filter(filt)
+    dev = bufs.work.device
+    _check(_lib.hu_pipeline(bufs._dims, bufs.batch, ctypes.byref(h), _seeds(seeds), bufs._bins, float(near_tol),
+                            ctypes.byref(bufs._out), _ptr(bufs.work), bufs.work.numel(), _stream(dev)),
+           "hu_pipeline")
+    return bufs
+
+
+def check_degenerate(stats):
+    """Raise DegenerateFilter if any field's stats flag says the filter has no lattice support."""
+    st = stats.detach().cpu().numpy()
+    bad = np.nonzero(st[:, 3] != 0)[0]
+    if bad.size:
+        raise DegenerateFilter("filter has no support on the lattice for fields %s (max ln chi %s)"
+                               % (bad.tolist(), st[bad, 2].tolist()))
+
+
+def debug_philox(seed, first, count, device="cuda"):
+    """Raw Philox words [count, 4] (uint32 bits in int32) and the FP32 normals [count, 4]."""
+    w = torch.empty((count, 4), dtype=torch.int32, device=device)
+    z = torch.empty((count, 4), dtype=torch.float32, device=device)
+    _check(_lib.hu_debug_philox(int(seed), int(first), int(count), _ptr(w), _ptr(z), _stream(w.device)),
+           "hu_debug_philox")
+    return w, z
+
+
+def profile_enable(on=True):
+    _check(_lib.hu_profile_enable(1 if on else 0), "hu_profile_enable")
+
+
+def profile_read(cap=64):
+    names = (ctypes.c_char * 48 * cap)()
+    launches = (ctypes.c_int64 * cap)()
+    ms = (ctypes.c_double * cap)()
+    n = _lib.hu_profile_read(names, launches, ms, cap)
+    if n < 0:
+        raise HuError(n, "hu_profile_read")
+    out = {}
+    for i in range(min(n, cap)):
+        out[bytes(names[i]).split(b"\0", 1)[0].decode()] = (int(launches[i]), float(ms[i]))
+    return out

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the same seeded inputs.
+
+Tolerances (from the precision policy: FP32 transforms with FP64-generated twiddles, FP64
+statistics and bin accumulation):
+* Philox words bit-exact; FP32 normals within 2e-6 (absolute, |z| <= 5.8) of the FP64 ones;
+* field max |f_gpu - f_oracle| <= 1e-5 * RMS;
+* sign map bit-exact except at sites with |f_oracle| < 1e-5 * RMS, whose number is reported;
+* raw mean / variance rtol 1e-5 (mean against the variance scale);
+* bin counts exact; continuous bins rtol 1e-4 per bin (absolute floor 1e-7 of the largest bin);
+  +-1 bins rtol 1e-5 when no site flips (else bounded by the flips);
+* standalone spectrum of identical inputs rtol 1e-5; standalone threshold exact.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2509_08675_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_08675_amd import hufield
+    return hufield
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------------------------
+# noise
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("seed,first,count", [(0, 0, 4096), (1, 12345, 1000), ((1 << 32) + 5, (1 << 32) - 7, 64),
+                                              (0xDEADBEEFCAFEF00D, 999, 333)])
+def test_philox_bit_exact(hf, seed, first, count):
+    _say("philox", seed, first, count)
+    w, z = hf.debug_philox(seed, first, count)
+    torch.cuda.synchronize()
+    got = w.cpu().numpy().view(np.uint32)
+    ref = O.philox4x32_10(np.arange(first, first + count, dtype=np.uint64), seed).T
+    np.testing.assert_array_equal(got, ref)
+    u = O.uniforms_from_words(ref.T)
+    z0, z1 = O.box_muller(u[0], u[1])
+    z2, z3 = O.box_muller(u[2], u[3])
+    zr = np.stack([z0, z1, z2, z3], axis=1)
+    assert np.max(np.abs(z.cpu().numpy().astype(np.float64) - zr)) < 2e-6
+
+
+# ---------------------------------------------------------------------------------------------
+# whole pipeline vs oracle
+# ---------------------------------------------------------------------------------------------
+def _filt(**kw):
+    return W.filt(**kw)
+
+
+PIPE_CASES = [
+    ("c1_128x128", (128, 128), W.C1["filt"], (64, 1), [0]),
+    ("2d_8x8", (8, 8), _filt(p=2, semi=(1, 1), alpha=2, k0=0.4, width=0.2), (4, 1), [3]),
+    ("2d_12x6_radix3", (12, 6), _filt(p=3, semi=(2, 1), rot=0.4, alpha=2, k0=0.4, width=0.3), (6, 4), [5, 6]),
+    ("2d_96x64_rot", (96, 64), _filt(p=4, semi=(3, 1), rot=math.pi / 6, alpha=4, k0=0.2, width=0.04), (32, 36), [1, 2, 3]),
+    ("2d_32x256_aniso", (32, 256), _filt(p=1.5, semi=(1, 2), rot=1.0, alpha=6, k0=0.25, width=0.05), (48, 12), [9]),
+    ("2d_512x128", (512, 128), _filt(p=8, semi=(1, 1), rot=0.0, alpha=2, k0=0.1, width=0.02), (128, 36), [4, 5]),
+    ("3d_16cube", (16, 16, 16), _filt(p=6, semi=(1, 2, 3), alpha=2, k0=0.3, width=0.1), (16, 1), [1, 2]),
+    ("3d_12x24x32_rot", (12, 24, 32), _filt(p=2.5, semi=(2, 1, 1.5), rot=0.7, alpha=4, k0=0.3, width=0.1), (20, 1), [7]),
+    ("3d_64cube", (64, 64, 64), W.C3["filt"], (128, 1), [1]),
+    ("3d_96x48x24", (96, 48, 24), _filt(p=4, semi=(1, 1.5, 2), rot=0.3, alpha=2, k0=0.2, width=0.06), (64, 1), [11]),
+]
+
+
+def _compare_pipeline(hf, name, dims, filt, bins, seeds):
+    _say("pipeline", name, dims, bins, seeds)
+    B = len(seeds)
+    bufs = hf.PipelineBuffers(dims, B, bins)
+    hf.pipeline(bufs, filt, seeds)
+    torch.cuda.synchronize()
+    hf.check_degenerate(bufs.stats)
+    nr, na = bins
+    fp = O.FilterParams(**filt)
+    report = {}
+    for i, s in enumerate(seeds):
+        ref = O.pipeline(dims, fp, s, nr, na)
+        f = bufs.field[i].double().cpu().numpy()
+        rms = math.sqrt(float(np.mean(ref["f"] ** 2)))
+        err = float(np.max(np.abs(f - ref["f"]))) / rms
+        assert err <= 1e-5, (name, s, err)
+        st = bufs.stats[i].cpu().numpy()
+        assert abs(st[0] - ref["mu"]) <= 1e-5 * math.sqrt(ref["var"]), (st[0], ref["mu"])
+        assert abs(st[1] - ref["var"]) <= 1e-5 * ref["var"], (st[1], ref["var"])
+        assert st[3] == 0.0
+        t = bufs.pm1[i].cpu().numpy()
+        near = np.abs(ref["f"]) < 1e-5 * rms
+        diff = t != ref["t"]
+        assert not np.any(diff & ~near), (name, s, int(np.sum(diff & ~near)))
+        flips = int(np.sum(diff))
+        cnt = hf.u64_view(bufs.counts[i])
+        assert abs(int(cnt[0]) - ref["n_pos"]) <= flips
+        # continuous spectrum
+        cs = bufs.cont_sum[i].cpu().numpy()
+        cc = hf.u64_view(bufs.cont_cnt[i])
+        np.testing.assert_array_equal(cc, ref["cont_cnt"])
+        np.testing.assert_allclose(cs, ref["cont_sum"], rtol=1e-4, atol=1e-7 * ref["cont_sum"].max())
+        # +-1 spectrum
+        ps = bufs.pm1_sum[i].cpu().numpy()
+        pc = hf.u64_view(bufs.pm1_cnt[i])
+        np.testing.assert_array_equal(pc, ref["pm1_cnt"])
+        N = int(np.prod(dims))
+        if flips == 0:
+            np.testing.assert_allclose(ps, ref["pm1_sum"], rtol=1e-5, atol=1e-6 * ref["pm1_sum"].max())
+        else:
+            # m flipped sites change each |T(k)|^2 / N by at most (4 m |T| + 4 m^2) / N
+            assert np.max(np.abs(ps - ref["pm1_sum"])) <= 2 * N * (4 * flips * math.sqrt(N) + 4 * flips ** 2) / N
+        assert abs(ps.sum() - N) < 1e-4 * N
+        report[s] = dict(err=err, flips=flips)
+    _say("  ", report)
+
+
+@pytest.mark.parametrize("name,dims,filt,bins,seeds", PIPE_CASES, ids=[c[0] for c in PIPE_CASES])
+def test_pipeline_matches_oracle(hf, name, dims, filt, bins, seeds):
+    _compare_pipeline(hf, name, dims, filt, bins, seeds)
+
+
+def test_gen_field_matches_pipeline_field(hf):
+    dims, filt = (64, 96), _filt(p=3, semi=(2, 1), rot=0.5, alpha=4, k0=0.2, width=0.05)
+    _say("gen_field vs pipeline", dims)
+    out = hf.gen_field(dims, filt, [5, 6], cont_bins=(32, 6))
+    bufs = hf.PipelineBuffers(dims, 2, (32, 6))
+    hf.pipeline(bufs, filt, [5, 6])
+    torch.cuda.synchronize()
+    assert torch.equal(out["field"], bufs.field)
+    assert torch.equal(out["cont_cnt"], bufs.cont_cnt)
+    np.testing.assert_allclose(out["cont_sum"].cpu().numpy(), bufs.cont_sum.cpu().numpy(), rtol=1e-12)
+
+
+def test_repeat_runs_are_bit_identical(hf):
+    dims, filt = (128, 64), _filt(p=4, semi=(3, 1), rot=0.3, alpha=4, k0=0.2, width=0.04)
+    _say("determinism", dims)
+    b1 = hf.PipelineBuffers(dims, 3, (16, 8))
+    hf.pipeline(b1, filt, [1, 2, 3])
+    f1, t1 = b1.field.clone(), b1.pm1.clone()
+    hf.pipeline(b1, filt, [1, 2, 3])
+    torch.cuda.synchronize()
+    assert torch.equal(f1, b1.field) and torch.equal(t1, b1.pm1)
+
+
+def test_degenerate_filter_is_flagged(hf):
+    dims = (16, 16)
+    _say("degenerate", dims)
+    bad = _filt(p=2, semi=(1, 1), alpha=2, k0=0.545, width=1e-4)
+    out = hf.gen_field(dims, bad, [1])
+    torch.cuda.synchronize()
+    with pytest.raises(hf.DegenerateFilter):
+        hf.check_degenerate(out["stats"])
+    assert torch.count_nonzero(out["field"]).item() == 0
+
+
+# ---------------------------------------------------------------------------------------------
+# standalone threshold and spectrum on identical inputs
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [(64, 64), (48, 96), (16, 24, 32), (256, 256)])
+def test_threshold_standalone(hf, dims):
+    _say("threshold", dims)
+    x = np.stack([W.random_field(dims, s) for s in (1, 2)])
+    x[0].flat[:5] = [0.0, -0.0, 1e-7, -1e-7, 5e-6]
+    xt = torch.from_numpy(x).cuda()
+    t, cnt = hf.threshold(xt, near_tol=1e-5)
+    torch.cuda.synchronize()
+    for i in range(2):
+        tr, npos, nnear = O.threshold(x[i].astype(np.float64), near_tol=1e-5)
+        np.testing.assert_array_equal(t[i].cpu().numpy(), tr)
+        c = hf.u64_view(cnt[i])
+        assert int(c[0]) == npos and int(c[1]) == nnear
+
+
+@pytest.mark.parametrize("dims,bins,kind", [((64, 64), (32, 36), "pm1"), ((96, 48), (24, 4), "f32"),
+                                            ((32, 32, 32), (40, 1), "pm1"), ((24, 48, 16), (16, 1), "f32"),
+                                            ((2048, 2048), (128, 36), "pm1")])
+def test_power_spectrum_standalone(hf, dims, bins, kind):
+    _say("power_spectrum", dims, bins, kind)
+    if kind == "pm1":
+        x = np.stack([W.random_pm1(dims, s) for s in (3, 4)])
+    else:
+        x = np.stack([W.random_field(dims, s) for s in (3, 4)])
+    s, c = hf.power_spectrum(torch.from_numpy(x).cuda(), bins)
+    torch.cuda.synchronize()
+    for i in range(2):
+        rs, rc = O.power_spectrum(x[i].astype(np.float64), *bins)
+        np.testing.assert_array_equal(hf.u64_view(c[i]), rc)
+        np.testing.assert_allclose(s[i].cpu().numpy(), rs, rtol=1e-5, atol=1e-6 * rs.max())
+
+
+# ---------------------------------------------------------------------------------------------
+# full benchmark sizes, in the benchmark's launch configuration, sampled fields vs the oracle
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg,sample", [(W.C2, [0, 15]), (W.C3, [0])], ids=["c2_2048sq_x16", "c3_256cube_x4"])
+def test_full_size_sampled(hf, cfg, sample):
+    dims, bins, seeds = cfg["dims"], cfg["bins"], cfg["seeds"]
+    _say("full size", cfg["name"])
+    bufs = hf.PipelineBuffers(dims, len(seeds), bins)
+    hf.pipeline(bufs, cfg["filt"], seeds)
+    torch.cuda.synchronize()
+    hf.check_degenerate(bufs.stats)
+    fp = O.FilterParams(**cfg["filt"])
+    N = int(np.prod(dims))
+    for i in sample:
+        ref = O.pipeline(dims, fp, seeds[i], *bins)
+        f = bufs.field[i].double().cpu().numpy()
+        rms = math.sqrt(float(np.mean(ref["f"] ** 2)))
+        err = float(np.max(np.abs(f - ref["f"]))) / rms
+        t = bufs.pm1[i].cpu().numpy()
+        near = np.abs(ref["f"]) < 1e-5 * rms
+        diff = t != ref["t"]
+        _say("   field", i, "max err/rms %.3e" % err, "flips", int(diff.sum()), "near sites", int(near.sum()))
+        assert err <= 1e-5
+        assert not np.any(diff & ~near)
+        np.testing.assert_array_equal(hf.u64_view(bufs.cont_cnt[i]), ref["cont_cnt"])
+        np.testing.assert_allclose(bufs.cont_sum[i].cpu().numpy(), ref["cont_sum"], rtol=1e-4,
+                                   atol=1e-7 * ref["cont_sum"].max())
+        ps = bufs.pm1_sum[i].cpu().numpy()
+        flips = int(diff.sum())
+        if flips == 0:
+            np.testing.assert_allclose(ps, ref["pm1_sum"], rtol=1e-5, atol=1e-6 * ref["pm1_sum"].max())
+        assert abs(ps.sum() - N) < 1e-4 * N
+    # properties on every field: Eq. (15) moments and Parseval of the +-1 spectrum
+    for i in range(len(seeds)):
+        f = bufs.field[i].double()
+        assert abs(f.mean().item()) < 1e-5 and abs(f.var(unbiased=False).item() - 1.0) < 1e-5
+        assert abs(bufs.pm1_sum[i].sum().item() - N) < 1e-4 * N

@@ -1,0 +1,102 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* libhufield.so loads and exports every function that include/hufield.h declares;
+* workspace sizes follow the documented layout;
+* argument validation returns the documented error codes before anything touches a GPU.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hufield.h")
+LIB = os.path.join(ROOT, "paper_2509_08675_amd", "libhufield.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhufield.so not built")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\**\s+\**(hu_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline", "hu_workspace_size",
+              "hu_strerror", "hu_debug_philox"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.fixture(scope="module")
+def hf():
+    from paper_2509_08675_amd import hufield
+    return hufield
+
+
+def test_strerror(hf):
+    assert hf.strerror(0) == "ok"
+    assert "workspace" in hf.strerror(hf.HU_ERR_WORKSPACE)
+
+
+def test_workspace_sizes(hf):
+    # 2D 2048^2 x 16: half spectrum 16 * 2048 * 1025 complex64 plus statistics
+    n = hf.workspace_size(hf.HU_OP_PIPELINE, (2048, 2048), 16, (128, 36))
+    spec = 16 * 2048 * 1025 * 8
+    assert spec <= n < spec + (1 << 20)
+    m = hf.workspace_size(hf.HU_OP_POWER_SPECTRUM, (256, 256, 256), 4, (128, 1))
+    assert m >= 4 * 256 * 256 * 129 * 8
+    # batches above 64 fields are processed in chunks of 64 that reuse the workspace
+    assert hf.workspace_size(hf.HU_OP_PIPELINE, (64, 64), 200, (8, 1)) == \
+        hf.workspace_size(hf.HU_OP_PIPELINE, (64, 64), 64, (8, 1))
+
+
+@pytest.mark.parametrize("dims,code", [((100, 128), -2), ((4096, 64), -2), ((64, 2), -2), ((64,), -1),
+                                       ((8, 8, 8, 8), -1), ((1536, 64), -2), ((64, 96), 0), ((768, 12), 0)])
+def test_size_validation(hf, dims, code):
+    out = ctypes.c_size_t()
+    d = hf.hu_dims()
+    d.ndim = len(dims)
+    for i, n in enumerate(dims[:3]):
+        d.n[i] = n
+    rc = hf.lib_handle().hu_workspace_size(hf.HU_OP_PIPELINE, d, 1, None, ctypes.byref(out))
+    assert rc == code
+
+
+def test_argument_errors_before_any_launch(hf):
+    lib = hf.lib_handle()
+    d = hf.make_dims((64, 64))
+    seeds = (ctypes.c_uint64 * 1)(1)
+    good = hf.make_filter(dict(p=2, semi=(1, 1, 1), rot=0, alpha=2, k0=0.2, width=0.05))
+    fake = ctypes.c_void_p(1 << 20)           # never dereferenced: validation fails first
+    for bad in (dict(p=0.0), dict(alpha=-1.0), dict(width=0.0), dict(k0=-0.1), dict(sigma_f=float("nan"))):
+        f = hf.make_filter({**dict(p=2, semi=(1, 1, 1), rot=0, alpha=2, k0=0.2, width=0.05), **bad})
+        rc = lib.hu_gen_field(d, 1, ctypes.byref(f), seeds, fake, None, None, None, None, fake, 1 << 30, None)
+        assert rc == hf.HU_ERR_ARG
+    # workspace too small
+    rc = lib.hu_gen_field(d, 1, ctypes.byref(good), seeds, fake, None, None, None, None, fake, 16, None)
+    assert rc == hf.HU_ERR_WORKSPACE
+    # misaligned field pointer
+    rc = lib.hu_gen_field(d, 1, ctypes.byref(good), seeds, ctypes.c_void_p((1 << 20) + 4), None, None, None, None,
+                          fake, 1 << 30, None)
+    assert rc == hf.HU_ERR_ALIGN
+    # angular bins are 2D only
+    b = hf.make_bins((16, 4))
+    rc = lib.hu_power_spectrum(hf.make_dims((8, 8, 8)), 1, fake, hf.HU_F32, b, fake, None, fake, 1 << 30, None)
+    assert rc == hf.HU_ERR_ARG
+    rc = lib.hu_power_spectrum(d, 1, fake, 7, hf.make_bins((16, 1)), fake, None, fake, 1 << 30, None)
+    assert rc == hf.HU_ERR_ARG
+    # zero batch, null seeds
+    rc = lib.hu_gen_field(d, 0, ctypes.byref(good), seeds, fake, None, None, None, None, fake, 1 << 30, None)
+    assert rc == hf.HU_ERR_ARG
+    rc = lib.hu_gen_field(d, 1, ctypes.byref(good), None, fake, None, None, None, None, fake, 1 << 30, None)
+    assert rc == hf.HU_ERR_ARG

@@ -1,0 +1,214 @@
+"""Throughput benchmark of the hyperuniform-field hot path on one MI355X.
+
+One step = one call of the whole hot path (white noise, forward FFT, superellipse filter,
+inverse FFT, normalisation, sign threshold, continuous and +-1 binned spectra) over one batch:
+16 fields on a 2048 x 2048 grid, 128 x 36 bins.  Inputs are synthetic (seeds 1..16, the filter
+parameters of the workload), outputs and workspace are preallocated in HBM before timing.
+
+Prints ONE JSON line.  Besides the headline value it carries
+  roofline      the dominant kernel's algorithmic bytes per launch / its mean duration
+                (HIP events recorded on the launch stream inside the timed region);
+  cpu_baseline  the FP64 oracle timed on this host on a bounded sample of the same workload;
+  pipeline_roofline_frac  compulsory bytes of the whole pipeline / step time / 8 TB/s;
+  plain_form    the same work as one call per field, and the batched speedup over it;
+  also          the 3D 256^3 x 4 workload measured the same way.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for scaling PMC byte counters)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(dims, batch):
+    """Compulsory HBM bytes per launch of each kernel family and of the whole pipeline.
+
+    Per field, one traversal of the FP32 half spectrum is 8 Nh bytes; the noise is generated in
+    registers (never stored); the +-1 map is int8.  2D: 6 traversals + 5N; 3D: 12 traversals + 5N."""
+    N = math.prod(dims)
+    Nh = N // dims[-1] * (dims[-1] // 2 + 1)
+    t = 8 * Nh * batch
+    fam = {
+        "rows_r2c_noise": t,               # write the half spectrum
+        "cols_y_fwd": 2 * t,               # read + write (3D)
+        "cols_filter": 2 * t,              # read + write
+        "cols_y_inv": 2 * t,
+        "rows_c2r_thresh": 2 * t + 5 * N * batch,   # read S, write S(+-1), field f32 and map int8
+        "cols_bin": t,                     # read only
+    }
+    if len(dims) == 2:
+        total = 6 * t + 5 * N * batch
+    else:
+        total = 12 * t + 5 * N * batch
+    return fam, total
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2509_08675_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("workloads", {}).get(workload, {}).get(kernel)
+
+
+def time_pipeline(hf, torch, cfg, steps, warmup, plain=False):
+    dims, seeds, bins = cfg["dims"], cfg["seeds"], cfg["bins"]
+    B = len(seeds)
+    if plain:
+        bufs = [hf.PipelineBuffers(dims, 1, bins) for _ in range(B)]
+
+        def step():
+            for i, b in enumerate(bufs):
+                hf.pipeline(b, cfg["filt"], [seeds[i]])
+    else:
+        bufs = hf.PipelineBuffers(dims, B, bins)
+
+        def step():
+            hf.pipeline(bufs, cfg["filt"], seeds)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # per-kernel durations: HIP events on the launch stream around every kernel, separate loop
+    hf.profile_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    prof = hf.profile_read()
+    hf.profile_enable(False)
+    check = bufs if not plain else bufs[0]
+    hf.check_degenerate(check.stats)
+    return el, prof
+
+
+def roofline_obj(cfg, prof, steps, workload):
+    fam_bytes, total = algorithmic_bytes(cfg["dims"], len(cfg["seeds"]))
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    name, (launches, ms) = dom
+    per_launch_ms = ms / launches
+    achieved = fam_bytes.get(name, 0) / (per_launch_ms * 1e-3) / 1e9
+    traffic = pmc_traffic(workload, name)
+    return dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                algorithmic_bytes_per_launch=fam_bytes.get(name, 0), mean_launch_ms=round(per_launch_ms, 5),
+                kernels={k: dict(launches=v[0], mean_ms=round(v[1] / v[0], 5),
+                                 gbs=round(fam_bytes.get(k, 0) / (v[1] / v[0] * 1e-3) / 1e9, 1))
+                         for k, v in prof.items()}), total
+
+
+def cpu_baseline(cfg, nfields):
+    """The FP64 oracle, as it stands, on `nfields` of the workload's fields (single-threaded
+    numpy; pocketfft runs on one core)."""
+    import numpy as np
+    import oracle
+    fp = oracle.FilterParams(**cfg["filt"])
+    t0 = time.perf_counter()
+    for s in cfg["seeds"][:nfields]:
+        oracle.pipeline(cfg["dims"], fp, s, *cfg["bins"])
+    el = time.perf_counter() - t0
+    vox = nfields * math.prod(cfg["dims"])
+    return dict(value=round(vox / el, 1), unit="voxels/s", cores=1, kind="oracle",
+                sample="%d of the %d fields of %s, whole pipeline (field, threshold, both spectra), FP64"
+                       % (nfields, len(cfg["seeds"]), "x".join(map(str, cfg["dims"]))),
+                seconds=round(el, 2))
+
+
+def copy_calibration(torch):
+    n = 1 << 28     # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes_each_way=4 * n, launches=5)), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+    from paper_2509_08675_amd import hufield as hf
+    from paper_2509_08675_amd.workloads import C2, C3
+
+    cfg = C2
+    el, prof = time_pipeline(hf, torch, cfg, args.steps, args.warmup)
+    ms = el / args.steps * 1e3
+    vox = len(cfg["seeds"]) * math.prod(cfg["dims"])
+    roof, total = roofline_obj(cfg, prof, args.steps, cfg["name"])
+    line = dict(
+        metric="field voxels/s (2048^2 2D, 256^3 3D, FP32) + % HBM roofline vs plain form",
+        value=round(vox / (ms * 1e-3), 1), unit="voxels/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload=cfg["name"], dims=list(cfg["dims"]), batch=len(cfg["seeds"]), bins=list(cfg["bins"]),
+                    filter=cfg["filt"], outputs="field f32, +-1 int8, counts, continuous and +-1 spectra"),
+        roofline=roof,
+        pipeline_roofline_frac=round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        pipeline_bytes_min=total,
+    )
+    pel, _ = time_pipeline(hf, torch, cfg, max(args.steps // 5, 3), 2, plain=True)
+    pms = pel / max(args.steps // 5, 3) * 1e3
+    line["plain_form"] = dict(desc="one pipeline call per field (16 calls)", ms_per_step=round(pms, 4),
+                              value=round(vox / (pms * 1e-3), 1), batched_speedup=round(pms / ms, 3))
+    if not args.no_3d:
+        el3, prof3 = time_pipeline(hf, torch, C3, max(args.steps // 2, 5), 3)
+        ms3 = el3 / max(args.steps // 2, 5) * 1e3
+        vox3 = len(C3["seeds"]) * math.prod(C3["dims"])
+        roof3, total3 = roofline_obj(C3, prof3, args.steps, C3["name"])
+        line["also"] = {C3["name"]: dict(value=round(vox3 / (ms3 * 1e-3), 1), unit="voxels/s",
+                                         ms_per_step=round(ms3, 4),
+                                         pipeline_roofline_frac=round(total3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                         roofline=roof3)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, 2)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

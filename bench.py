@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the batched 2D workload (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling PMC byte counters)")
     return ap.parse_args()
@@ -136,15 +138,18 @@ def roofline_obj(cfg, prof, steps, workload):
                          for k, v in prof.items()}), total
 
 
-def cpu_baseline(cfg, nfields):
-    """The FP64 oracle, as it stands, on `nfields` of the workload's fields (single-threaded
-    numpy; pocketfft runs on one core)."""
-    import numpy as np
+def cpu_baseline(cfg, budget_s=12.0):
+    """The FP64 oracle, as it stands, on the workload's fields in order until `budget_s` seconds
+    have passed or all are done (single-threaded numpy; pocketfft runs on one core)."""
     import oracle
     fp = oracle.FilterParams(**cfg["filt"])
     t0 = time.perf_counter()
-    for s in cfg["seeds"][:nfields]:
+    nfields = 0
+    for s in cfg["seeds"]:
         oracle.pipeline(cfg["dims"], fp, s, *cfg["bins"])
+        nfields += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
     el = time.perf_counter() - t0
     vox = nfields * math.prod(cfg["dims"])
     return dict(value=round(vox / el, 1), unit="voxels/s", cores=1, kind="oracle",
@@ -192,6 +197,9 @@ def main():
         pipeline_roofline_frac=round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         pipeline_bytes_min=total,
     )
+    if args.main_only:
+        print(json.dumps(line), flush=True)
+        return
     pel, _ = time_pipeline(hf, torch, cfg, max(args.steps // 5, 3), 2, plain=True)
     pms = pel / max(args.steps // 5, 3) * 1e3
     line["plain_form"] = dict(desc="one pipeline call per field (16 calls)", ms_per_step=round(pms, 4),
@@ -206,7 +214,7 @@ def main():
                                          pipeline_roofline_frac=round(total3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                          roofline=roof3)}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, 2)
+        line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)
 
 

@@ -102,6 +102,17 @@ int get_edges(int na, const double** ex, const double** ey) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// bin geometry per (device, grid, bins): the bin of every half-spectrum mode as a u16 table
+// (column-major for the axis-0 passes; kept when it is at most 64 MiB, else bins are computed in
+// the kernels) and the per-bin mode counts, built once by a kernel on the caller's stream.
+// ---------------------------------------------------------------------------------------------
+struct BinGeo {
+  uint16_t* table;
+  unsigned long long* counts;
+};
+std::map<std::vector<long long>, BinGeo> g_bingeo;
+
+// ---------------------------------------------------------------------------------------------
 // profiling: events around every launch while enabled
 // ---------------------------------------------------------------------------------------------
 struct ProfRec {
@@ -183,6 +194,7 @@ int make_geom(const hu_dims& d, Geom* g) {
   g->nxh = g->nx / 2 + 1;
   g->nrows = g->N / g->nx;
   g->Nh = g->nrows * g->nxh;
+  if (g->N >= (1LL << 31)) return HU_ERR_SIZE;      // in-field offsets are 32-bit
   return HU_OK;
 }
 
@@ -210,7 +222,7 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t spec, partials, fstats, counters, total;
+  size_t spec, partials, fstats, total;
   int tiles;
 };
 
@@ -225,8 +237,6 @@ Layout layout(const Geom& g, int batch, bool need_stats) {
     off += up256((size_t)batch * L.tiles * 4 * sizeof(double));
     L.fstats = off;
     off += up256((size_t)batch * 8 * sizeof(double));
-    L.counters = off;
-    off += up256((size_t)batch * sizeof(unsigned));
   }
   L.total = off;
   return L;
@@ -258,7 +268,10 @@ Axis0Geom axis0(const Geom& g) {
   a.ny = g.nd == 3 ? g.n[1] : 0;
   a.nx = g.nx;
   a.nxh = g.nxh;
-  a.ncol = g.Nh / g.n[0];
+  a.ncol = (int)(g.Nh / g.n[0]);
+  a.kap0 = (float)(2.0 / g.n[0]);
+  a.kapy = g.nd == 3 ? (float)(2.0 / g.n[1]) : 0.0f;
+  a.kapx = (float)(2.0 / g.nx);
   a.dfac_0 = g.D / g.n[0];
   a.dfac_y = g.nd == 3 ? g.D / g.n[1] : 0;
   a.dfac_x = g.D / g.nx;
@@ -269,6 +282,7 @@ int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd) {
   bd->nr = b.n_radial;
   bd->na = b.n_angular;
   bd->D2 = g.D * g.D;
+  bd->invD2 = (float)(1.0 / (double)(g.D * g.D));
   bd->fourR2 = 4LL * b.n_radial * b.n_radial;
   return get_edges(b.n_angular, &bd->ex, &bd->ey);
 }
@@ -283,8 +297,46 @@ int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd) {
     if ((expr) != hipSuccess) return HU_ERR_HIP; \
   } while (0)
 
-// The generator's pass sequence for one chunk of <= MAX_CHUNK fields whose outputs and workspace
-// pointers are already offset to the chunk.  Pass order (3D; 2D skips the y passes):
+int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t st, BinGeo* out) {
+  std::vector<long long> key = {current_device(), g.nd, g.n[0], g.n[1], g.nd == 3 ? g.n[2] : 0,
+                                bins.n_radial, bins.n_angular};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_bingeo.find(key);
+    if (it != g_bingeo.end()) {
+      *out = it->second;
+      return HU_OK;
+    }
+  }
+  const int nb = bins.n_radial * bins.n_angular + 1;
+  BinGeo geo{nullptr, nullptr};
+  HU_HIP(hipMalloc(&geo.counts, sizeof(unsigned long long) * nb));
+  if ((size_t)g.Nh * sizeof(uint16_t) <= ((size_t)64 << 20)) HU_HIP(hipMalloc(&geo.table, sizeof(uint16_t) * g.Nh));
+  HU_HIP(launch_zero_u64(reinterpret_cast<uint64_t*>(geo.counts), nb, st));
+  BinGeomArgs ba{};
+  ba.Nh = g.Nh;
+  ba.gm = axis0(g);
+  ba.bd = bd;
+  ba.nb = nb;
+  ba.table = geo.table;
+  ba.counts = geo.counts;
+  HU_HIP(launch_bin_geom(ba, st));
+  HU_HIP(hipStreamSynchronize(st));          // complete before any stream can use it
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_bingeo.find(key);
+  if (it != g_bingeo.end()) {                // another thread built it meanwhile
+    (void)hipFree(geo.counts);
+    if (geo.table) (void)hipFree(geo.table);
+    *out = it->second;
+    return HU_OK;
+  }
+  g_bingeo.emplace(key, geo);
+  *out = geo;
+  return HU_OK;
+}
+
+// The generator's pass sequence for one chunk of <= MAX_CHUNK fields whose outputs are already
+// offset to the chunk.  Pass order (3D; 2D skips the y passes):
 //   rows_r2c(noise) -> cols(y, fwd) -> cols_filter(z) -> cols(y, inv) -> rows_c2r
 //   [-> cols(y, fwd) -> cols_bin(z)]   for the +-1 spectrum
 int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, const hu_bins* bins,
@@ -297,14 +349,18 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
   if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
   const int nb = bins ? bins->n_radial * bins->n_angular + 1 : 0;
   BinDev bd{};
-  if (bins) HU_TRY(make_bindev(g, *bins, &bd));
+  BinGeo geo{nullptr, nullptr};
+  if (bins) {
+    HU_TRY(make_bindev(g, *bins, &bd));
+    HU_TRY(get_bingeo(g, *bins, bd, st, &geo));
+  }
 
   float2* spec = reinterpret_cast<float2*>(work + lay.spec);
   double* partials = reinterpret_cast<double*>(work + lay.partials);
   double* fstats = reinterpret_cast<double*>(work + lay.fstats);
-  unsigned* counters = reinterpret_cast<unsigned*>(work + lay.counters);
+  const uint32_t* cnt_src = reinterpret_cast<const uint32_t*>(geo.counts);
 
-  // pass A: noise -> R2C rows; block 0 of each field clears that field's accumulators
+  // pass A: noise -> R2C rows; block 0 of each field sets up that field's accumulators
   RowsArgs ra{};
   ra.spec = spec;
   ra.Nh = g.Nh;
@@ -313,23 +369,23 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
   for (int i = 0; i < B; ++i) ra.seeds[i] = seeds[i];
   ra.tw = tw_row;
   ra.tw2 = tw2_row;
-  int zs = 0;
-  ra.zero[zs++] = ZeroSpan{counters, 1};
-  if (o.cont_sum) ra.zero[zs++] = ZeroSpan{reinterpret_cast<uint32_t*>(o.cont_sum), 2 * nb};
-  if (o.cont_cnt) ra.zero[zs++] = ZeroSpan{reinterpret_cast<uint32_t*>(o.cont_cnt), 2 * nb};
-  if (o.pm1_sum) ra.zero[zs++] = ZeroSpan{reinterpret_cast<uint32_t*>(o.pm1_sum), 2 * nb};
-  if (o.pm1_cnt) ra.zero[zs++] = ZeroSpan{reinterpret_cast<uint32_t*>(o.pm1_cnt), 2 * nb};
-  if (o.counts) ra.zero[zs++] = ZeroSpan{reinterpret_cast<uint32_t*>(o.counts), 4};
-  ra.zero_spans = zs;
+  int fs = 0;
+  if (o.cont_sum) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.cont_sum), nullptr, 2 * nb};
+  if (o.cont_cnt) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.cont_cnt), cnt_src, 2 * nb};
+  if (o.pm1_sum) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_sum), nullptr, 2 * nb};
+  if (o.pm1_cnt) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_cnt), cnt_src, 2 * nb};
+  if (o.counts) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.counts), nullptr, 4};
+  ra.fill_spans = fs;
   HU_HIP(timed("rows_r2c_noise", st, [&] { return launch_rows_r2c(Lrow, SRC_NOISE, ra, B, st); }));
 
   ColsArgs cy{};
   if (g.nd == 3) {
     cy.spec = spec;
     cy.Nh = g.Nh;
-    cy.ncol = (long long)g.n[0] * g.nxh;
+    cy.ncol = g.n[0] * g.nxh;
     cy.inner = g.nxh;
     cy.tw = tw_1;
+    cy.sc = col_sched(g.n[1], cy.ncol, B);
     HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, cy, B, st); }));
   }
 
@@ -338,18 +394,25 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
   fa.Nh = g.Nh;
   fa.N = g.N;
   fa.gm = axis0(g);
+  fa.sc = col_sched(g.n[0], fa.gm.ncol, B);
   fa.filt = filt_dev(f);
   fa.bd = bd;
   fa.nb = o.cont_sum ? nb : 0;
+  fa.table = geo.table;
   fa.tw = tw_0;
   fa.partials = partials;
-  fa.counters = counters;
-  fa.fstats = fstats;
-  fa.stats = o.stats;
   fa.cont_sum = o.cont_sum;
-  fa.cont_cnt = o.cont_cnt;
-  fa.sigma_f = f.sigma_f;
   HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], fa, B, st); }));
+  FinalizeArgs fz{};
+  fz.partials = partials;
+  fz.ntiles = fa.sc.ntiles;
+  fz.N = g.N;
+  fz.sigma_f = f.sigma_f;
+  fz.fstats = fstats;
+  fz.stats = o.stats;
+  fz.cont_sum = o.cont_sum;
+  fz.nb = nb;
+  HU_HIP(timed("finalize", st, [&] { return launch_finalize(fz, B, st); }));
 
   if (g.nd == 3) HU_HIP(timed("cols_y_inv", st, [&] { return launch_cols(g.n[1], true, cy, B, st); }));
 
@@ -374,11 +437,12 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
     ba.Nh = g.Nh;
     ba.N = g.N;
     ba.gm = axis0(g);
+    ba.sc = col_sched(g.n[0], ba.gm.ncol, B);
     ba.bd = bd;
     ba.nb = nb;
+    ba.table = geo.table;
     ba.tw = tw_0;
     ba.sum = o.pm1_sum;
-    ba.cnt = o.pm1_cnt;
     HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], ba, B, st); }));
   }
   return HU_OK;
@@ -507,6 +571,8 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
   if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
   BinDev bd{};
   HU_TRY(make_bindev(g, bins, &bd));
+  BinGeo geo{nullptr, nullptr};
+  HU_TRY(get_bingeo(g, bins, bd, st, &geo));
   float2* spec = reinterpret_cast<float2*>(reinterpret_cast<char*>(work) + lay.spec);
   const size_t esz = dtype == HU_F32 ? 4 : 1;
   for (int f0 = 0; f0 < batch; f0 += MAX_CHUNK) {
@@ -521,14 +587,20 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
     ra.tw2 = tw2_row;
     double* s = sum + (long long)f0 * nb;
     uint64_t* c = cnt ? cnt + (long long)f0 * nb : nullptr;
-    int zs = 0;
-    ra.zero[zs++] = ZeroSpan{reinterpret_cast<uint32_t*>(s), 2 * nb};
-    if (c) ra.zero[zs++] = ZeroSpan{reinterpret_cast<uint32_t*>(c), 2 * nb};
-    ra.zero_spans = zs;
+    int fs = 0;
+    ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(s), nullptr, 2 * nb};
+    if (c) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(c), reinterpret_cast<const uint32_t*>(geo.counts), 2 * nb};
+    ra.fill_spans = fs;
     const int src = dtype == HU_F32 ? SRC_F32 : SRC_I8;
     HU_HIP(timed("rows_r2c_load", st, [&] { return launch_rows_r2c(Lrow, src, ra, B, st); }));
     if (g.nd == 3) {
-      ColsArgs cy{spec, g.Nh, (long long)g.n[0] * g.nxh, g.nxh, tw_1};
+      ColsArgs cy{};
+      cy.spec = spec;
+      cy.Nh = g.Nh;
+      cy.ncol = g.n[0] * g.nxh;
+      cy.inner = g.nxh;
+      cy.tw = tw_1;
+      cy.sc = col_sched(g.n[1], cy.ncol, B);
       HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, cy, B, st); }));
     }
     BinArgs ba{};
@@ -536,11 +608,12 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
     ba.Nh = g.Nh;
     ba.N = g.N;
     ba.gm = axis0(g);
+    ba.sc = col_sched(g.n[0], ba.gm.ncol, B);
     ba.bd = bd;
     ba.nb = nb;
+    ba.table = geo.table;
     ba.tw = tw_0;
     ba.sum = s;
-    ba.cnt = c;
     HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], ba, B, st); }));
   }
   return HU_OK;

@@ -1,0 +1,165 @@
+// Spectrum binning passes and small utility kernels.
+//
+//   cols_bin    forward FFT along axis 0 and the binned periodogram |X|^2 / N of the +-1 field
+//               (or of any real input), read only;
+//   bin_geom    once per grid and bin layout: the bin of every half-spectrum mode (optionally
+//               stored as a table, column-major for the axis-0 passes) and the per-bin mode counts;
+//   threshold   the standalone sign map with counts;
+//   debug_philox  raw Philox words and normals for the parity tests.
+#include "hu_common.hpp"
+
+namespace hu {
+
+template <int L>
+__global__ void __launch_bounds__(ColTile<L>::T) k_cols_bin(BinArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L>::C, T = ColTile<L>::T;
+  constexpr int LP = ColTile<L>::LP;
+  using Rad = typename Plan<L>::fwd;
+  constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
+  extern __shared__ float2 lds[];
+  int b;
+  long long tile;
+  if (!map_tile(a.sc, b, tile)) return;
+  const int tid = threadIdx.x;
+  const int c = tid % C, p = tid / C;
+  const int g = (int)tile * C + c;
+  const bool valid = g < a.gm.ncol;
+  const int ncol = a.gm.ncol;
+  const float2* base = a.spec + (long long)b * a.Nh + g;
+  float2 v[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s)
+    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] : make_float2(0.f, 0.f);
+  fft_run<L, P, E, false>(Rad{}, v, lds + c * L, p, a.tw);
+  const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
+  float* pw = reinterpret_cast<float*>(lds);
+  double* hs = reinterpret_cast<double*>(pw + ((C * LP + 1) & ~1));
+  __syncthreads();                                  // the exchange buffer is free from here
+#pragma unroll
+  for (int s = 0; s < E; ++s)
+    pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = wm * (v[s].x * v[s].x + v[s].y * v[s].y);
+  for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
+  __syncthreads();
+  if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, a.bd, a.gm, g, p);
+  __syncthreads();
+  hist_flush(hs, a.nb, 1.0 / (double)a.N, a.sum + (long long)b * a.nb, tid, T);
+}
+
+template <int L>
+static hipError_t launch_cols_bin_L(const BinArgs& a, hipStream_t st) {
+  constexpr int T = ColTile<L>::T;
+  hipLaunchKernelGGL((k_cols_bin<L>), dim3(sched_blocks(a.sc)), dim3(T), col_lds_bytes_t<L>(a.nb), st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_bin(int L, const BinArgs& a, int batch, hipStream_t st) {
+  (void)batch;
+  switch (L) {
+#define X(LL) case LL: return launch_cols_bin_L<LL>(a, st);
+    HU_COL_LENGTHS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// bin geometry: grid-stride over the Nh modes in half-spectrum order (m_0 slowest, column g
+// fastest); LDS-privatised u32 counts, flushed with 64-bit atomics (integers: deterministic).
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_bin_geom(BinGeomArgs a) {
+  extern __shared__ unsigned hcnt[];
+  for (int i = threadIdx.x; i < a.nb; i += 256) hcnt[i] = 0u;
+  __syncthreads();
+  const long long ncol = a.gm.ncol;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.Nh; i += (long long)gridDim.x * 256) {
+    const int g = (int)(i % ncol);
+    const int e = (int)(i / ncol);
+    const ColCoord cc = col_coord(a.gm, g);
+    const int bi = mode_bin(a.bd, a.gm, cc, e);
+    if (a.table) a.table[g * (long long)a.gm.n0 + e] = (uint16_t)bi;
+    atomicAdd(hcnt + bi, (unsigned)cc.wm);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.nb; i += 256)
+    if (hcnt[i]) atomicAdd(a.counts + i, (unsigned long long)hcnt[i]);
+}
+
+hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st) {
+  long long blocks = (a.Nh + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_bin_geom, dim3((unsigned)blocks), dim3(256), (size_t)a.nb * sizeof(unsigned), st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// standalone threshold: grid-stride over N values of each field
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_threshold(ThreshArgs a) {
+  __shared__ unsigned red[2][4];
+  const int b = blockIdx.y;
+  const float* f = a.field + (long long)b * a.N;
+  int8_t* t = a.out + (long long)b * a.N;
+  unsigned np = 0, nn = 0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.N; i += (long long)gridDim.x * 256) {
+    const float x = f[i];
+    const bool pos = x >= 0.0f;
+    t[i] = pos ? (int8_t)1 : (int8_t)-1;
+    np += pos;
+    nn += fabsf(x) < a.near_tol;
+  }
+  np = wave_usum(np);
+  nn = wave_usum(nn);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = np; red[1][threadIdx.x >> 6] = nn; }
+  __syncthreads();
+  if (threadIdx.x == 0 && a.counts) {
+    atomicAdd((unsigned long long*)(a.counts + 2 * b + 0),
+              (unsigned long long)(red[0][0] + red[0][1] + red[0][2] + red[0][3]));
+    atomicAdd((unsigned long long*)(a.counts + 2 * b + 1),
+              (unsigned long long)(red[1][0] + red[1][1] + red[1][2] + red[1][3]));
+  }
+}
+
+hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st) {
+  long long blocks = (a.N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_threshold, dim3((unsigned)blocks, batch), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_u64(uint64_t* p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+hipError_t launch_zero_u64(uint64_t* p, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+__global__ void k_debug_philox(uint64_t seed, uint64_t first, uint64_t count, uint32_t* words, float* normals) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const U4 w = philox4x32_10(first + i, seed);
+  if (words) {
+    words[4 * i + 0] = w.x; words[4 * i + 1] = w.y; words[4 * i + 2] = w.z; words[4 * i + 3] = w.w;
+  }
+  if (normals) {
+    float z0, z1, z2, z3;
+    box_muller(w.x, w.y, z0, z1);
+    box_muller(w.z, w.w, z2, z3);
+    normals[4 * i + 0] = z0; normals[4 * i + 1] = z1; normals[4 * i + 2] = z2; normals[4 * i + 3] = z3;
+  }
+}
+
+hipError_t launch_debug_philox(uint64_t seed, uint64_t first, uint64_t count, uint32_t* words, float* normals,
+                               hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_debug_philox, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, seed, first, count,
+                     words, normals);
+  return hipGetLastError();
+}
+
+}  // namespace hu

@@ -1,0 +1,77 @@
+// Plain complex transform along a strided axis (the y axis of 3D grids), forward or inverse, in
+// place.  Element e of column g lives at (g / inner) * (L * inner) + (g % inner) + e * inner; a
+// workgroup transforms C adjacent columns, P threads per column, E elements per thread.
+#include "hu_common.hpp"
+
+namespace hu {
+
+template <int L, bool INV>
+__global__ void __launch_bounds__(ColTile<L>::T) k_cols(ColsArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L>::C;
+  using Rad = typename Plan<L>::fwd;
+  constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
+  extern __shared__ float2 lds[];
+  int b;
+  long long tile;
+  if (!map_tile(a.sc, b, tile)) return;
+  const int tid = threadIdx.x;
+  const int c = tid % C, p = tid / C;
+  const int g = (int)tile * C + c;
+  const bool valid = g < a.ncol;
+  const int inner = a.inner;
+  const unsigned go = (unsigned)g / (unsigned)inner;
+  float2* base = a.spec + (long long)b * a.Nh + (unsigned)(go * (L * inner) + (g - go * inner));
+  float2 v[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s)
+    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] : make_float2(0.f, 0.f);
+  fft_run<L, P, E, INV>(Rad{}, v, lds + c * L, p, a.tw);
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < E; ++s) base[(unsigned)(slot_index<L, RL, P>(s, p) * inner)] = v[s];
+  }
+}
+
+template <int L>
+static ColSched col_sched_L(long long ncol, int batch) {
+  constexpr int C = ColTile<L>::C;
+  ColSched s;
+  s.ntiles = (int)((ncol + C - 1) / C);
+  // tiles narrower than a 128-byte line (16 complex) share lines with their neighbours
+  s.G = C >= 16 ? 1 : 16 / C;
+  if (s.G > s.ntiles) s.G = 1;
+  s.ntiles_pad = (s.ntiles + s.G - 1) / s.G * s.G;
+  s.batch = batch;
+  return s;
+}
+
+ColSched col_sched(int L, long long ncol, int batch) {
+  switch (L) {
+#define X(LL) case LL: return col_sched_L<LL>(ncol, batch);
+    HU_COL_LENGTHS(X)
+#undef X
+    default: return ColSched{0, 0, 1, 0};
+  }
+}
+
+int col_tiles(int L, long long ncol) { return col_sched(L, ncol, 1).ntiles; }
+
+template <int L, bool INV>
+static hipError_t launch_cols_L(const ColsArgs& a, hipStream_t st) {
+  constexpr int C = ColTile<L>::C, T = ColTile<L>::T;
+  hipLaunchKernelGGL((k_cols<L, INV>), dim3(sched_blocks(a.sc)), dim3(T), (size_t)C * L * sizeof(float2), st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols(int L, bool inv, const ColsArgs& a, int batch, hipStream_t st) {
+  (void)batch;
+  switch (L) {
+#define X(LL) \
+  case LL: return inv ? launch_cols_L<LL, true>(a, st) : launch_cols_L<LL, false>(a, st);
+    HU_COL_LENGTHS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace hu

@@ -1,0 +1,237 @@
+// Device helpers shared by the row and column passes: tile shapes, reductions, the real-to-complex
+// split twist, the XCD-aware tile schedule, per-column wavenumber pieces, the symmetrised filter
+// amplitude and the run-length bin accumulation.
+#pragma once
+
+#include "hu_device.hpp"
+#include "hu_internal.hpp"
+
+// column lengths (n along a non-x axis) and row half-lengths (n_x / 2) with compiled kernels
+#define HU_COL_LENGTHS(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048)
+
+namespace hu {
+
+// ---------------------------------------------------------------------------------------------
+// tile widths: transforms per workgroup
+// ---------------------------------------------------------------------------------------------
+template <int L>
+struct RowTile {
+  static constexpr int P = Plan<L>::P;
+  static constexpr int c0 = 256 / P > 0 ? 256 / P : 1;
+  static constexpr int cl = 8192 / (L + 1) > 0 ? 8192 / (L + 1) : 1;
+  static constexpr int C = c0 < cl ? c0 : cl;
+  static constexpr int T = C * P;
+};
+
+template <int L>
+struct ColTile {
+  static constexpr int P = Plan<L>::P;
+  static constexpr int a = 8192 / L < 32 ? 8192 / L : 32;
+  static constexpr int b = 64 / P > a ? 64 / P : a;
+  static constexpr int C = b * P > 1024 ? 1024 / P : b;
+  static constexpr int T = C * P;
+  // padded power-value layout for run-length binning: 4 floats after every 16
+  static constexpr int LP = L + (L / 16) * 4 + 4;
+};
+
+__host__ __device__ constexpr int pw_index(int e) { return e + (e >> 4) * 4; }
+
+// ---------------------------------------------------------------------------------------------
+// block reductions
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ unsigned wave_usum(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// R2C split twist: from Z = FFT_L(x[2n] + i x[2n+1]) held in LDS (natural order), write
+// X[k] = (Z[k] + Z*[L-k])/2 - (i/2) e^{-2 pi i k / 2L} (Z[k] - Z*[L-k]), k = 0..L, to `out`.
+// ---------------------------------------------------------------------------------------------
+template <int L, int P, int E>
+__device__ __forceinline__ void r2c_twist_store(const float2* lz, const float2* __restrict__ tw2, float2* out,
+                                                int p, bool valid) {
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int k = p + P * i;
+    const float2 zk = lz[k];
+    const float2 zm = cconj(lz[(L - k) % L]);
+    const float2 A = cadd(zk, zm), B = csub(zk, zm);
+    const float2 X = cscale(cadd(A, mul_mi<false>(cmul(tw2[k], B))), 0.5f);
+    if (valid) out[k] = X;
+    if (k == 0 && valid) out[L] = make_float2(zk.x - zk.y, 0.0f);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// XCD-aware tile schedule.  Workgroups are dispatched round-robin over the 8 XCDs (id mod 8), and
+// each XCD has its own L2.  Column tiles narrower than a 128-byte line share lines with their
+// G - 1 neighbours; those G tiles are given ids id, id + 8, ..., id + 8 (G-1), i.e. the same XCD
+// in consecutive dispatch rounds, so the line is fetched once into that XCD's L2.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool map_tile(const ColSched& s, int& b, long long& tile) {
+  const unsigned id = blockIdx.x;
+  const unsigned xcd = id & 7u, round = id >> 3;
+  const unsigned j = round % (unsigned)s.G;
+  const long long grp = (long long)(round / (unsigned)s.G) * 8 + xcd;
+  const long long lin = grp * s.G + j;
+  b = (int)(lin / s.ntiles_pad);
+  tile = lin % s.ntiles_pad;
+  return b < s.batch && tile < s.ntiles;
+}
+
+// workgroups launched for a schedule: whole groups of 8 G ids
+inline unsigned sched_blocks(const ColSched& s) {
+  const long long unit = 8LL * s.G;
+  const long long n = (long long)s.batch * s.ntiles_pad;
+  return (unsigned)(((n + unit - 1) / unit) * unit);
+}
+
+// ---------------------------------------------------------------------------------------------
+// per-column pieces of the axis-0 passes
+// ---------------------------------------------------------------------------------------------
+struct ColCoord {
+  int mx;            // half-spectrum x index (>= 0)
+  int my;            // y index (3D only)
+  float kx_c;        // canonical kappa_x (-1 at the x Nyquist index)
+  float ky;          // canonical kappa_y (3D only)
+  bool nyq_x, nyq_y; // x / y component on a Nyquist index (3D y)
+  long long qx, qy;  // bin integers (3D: qy is the y component)
+  long long sfix;    // sum of the fixed q_i^2
+  float wm;          // multiplicity 1 or 2
+};
+
+__device__ __forceinline__ ColCoord col_coord(const Axis0Geom& gm, int g) {
+  ColCoord cc;
+  if (gm.ndim == 2) {
+    cc.mx = g;
+    cc.my = 0;
+  } else {
+    cc.my = (int)((unsigned)g / (unsigned)gm.nxh);
+    cc.mx = g - cc.my * gm.nxh;
+  }
+  cc.nyq_x = (2 * cc.mx == gm.nx);
+  cc.kx_c = cc.nyq_x ? -1.0f : (float)cc.mx * gm.kapx;
+  cc.wm = (cc.mx == 0 || cc.nyq_x) ? 1.0f : 2.0f;
+  cc.qx = (long long)cc.mx * gm.dfac_x;
+  if (gm.ndim == 3) {
+    const int mt = cc.my < gm.ny / 2 ? cc.my : cc.my - gm.ny;
+    cc.nyq_y = (2 * cc.my == gm.ny);
+    cc.ky = (float)mt * gm.kapy;
+    cc.qy = (long long)mt * gm.dfac_y;
+    cc.sfix = cc.qx * cc.qx + cc.qy * cc.qy;
+  } else {
+    cc.nyq_y = false;
+    cc.ky = 0.0f;
+    cc.qy = 0;
+    cc.sfix = cc.qx * cc.qx;
+  }
+  return cc;
+}
+
+// symmetrised amplitude at axis-0 index e of column cc (Eq. (8) with Eqs. (12)-(13));
+// also returns ln chi (unsymmetrised) for the support check
+template <int NDIM>
+__device__ __forceinline__ float amp_sym(const FiltDev& f, const Axis0Geom& gm, const ColCoord& cc, int e,
+                                         float& lnc) {
+  const int mt = e < gm.n0 / 2 ? e : e - gm.n0;
+  const float k0c = (float)mt * gm.kap0;         // canonical kappa along axis 0 (-1 at Nyquist)
+  const bool nyq0 = (2 * e == gm.n0);
+  float kx = cc.kx_c, ky, kz;
+  bool ny_y;
+  if constexpr (NDIM == 2) { ky = k0c; kz = 0.0f; ny_y = nyq0; }
+  else { ky = cc.ky; kz = k0c; ny_y = cc.nyq_y; }
+  lnc = ln_chi<NDIM>(f, kx, ky, kz);
+  float H = amp_from_lnchi(lnc);
+  if (f.rotated && (cc.nyq_x || ny_y)) {
+    // partner -m: by evenness, the canonical kappa with its Nyquist components negated
+    const float kx2 = cc.nyq_x ? -kx : kx, ky2 = ny_y ? -ky : ky;
+    const float l2 = ln_chi<NDIM>(f, kx2, ky2, kz);
+    H = 0.5f * (H + amp_from_lnchi(l2));
+  }
+  return H;
+}
+
+__device__ __forceinline__ int mode_bin(const BinDev& bd, const Axis0Geom& gm, const ColCoord& cc, int e) {
+  const int mt = e < gm.n0 / 2 ? e : e - gm.n0;
+  const long long q0 = (long long)mt * gm.dfac_0;
+  const long long s = cc.sfix + q0 * q0;
+  // 2D: angle of (q_x, q_y = q0); 3D: radial only
+  return bin_index(bd, s, cc.qx, gm.ndim == 2 ? q0 : 0);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Run-length binning.  The per-mode power values w |X|^2 of the C columns sit in LDS (padded
+// layout pw_index).  Thread (c, p) walks the E consecutive modes e = p E .. p E + E - 1 of its
+// column, reads their bins (precomputed table, column-major [g][L], or computed), sums in FP64
+// while the bin stays the same and adds each run to the LDS histogram with one atomic.
+// ---------------------------------------------------------------------------------------------
+template <int L, int E>
+__device__ __forceinline__ void bin_runs(const float* pw, double* hs, const uint16_t* __restrict__ table,
+                                         const BinDev& bd, const Axis0Geom& gm, int g, int p) {
+  const int e0 = p * E;
+  int bins[E];
+  if (table) {
+    const uint16_t* t = table + (unsigned)(g * L + e0);
+    if constexpr ((L % 8) == 0 && (E % 8) == 0) {
+#pragma unroll
+      for (int q = 0; q < E / 8; ++q) {
+        const uint4 w = *reinterpret_cast<const uint4*>(t + 8 * q);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          bins[8 * q + 2 * h] = (int)(ws[h] & 0xFFFFu);
+          bins[8 * q + 2 * h + 1] = (int)(ws[h] >> 16);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) bins[i] = t[i];
+    }
+  } else {
+    const ColCoord cc = col_coord(gm, g);
+#pragma unroll
+    for (int i = 0; i < E; ++i) bins[i] = mode_bin(bd, gm, cc, e0 + i);
+  }
+  int cur = bins[0];
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const double v = (double)pw[pw_index(e0 + i)];
+    if (bins[i] != cur) {
+      atomicAdd(hs + cur, acc);
+      cur = bins[i];
+      acc = 0.0;
+    }
+    acc += v;
+  }
+  atomicAdd(hs + cur, acc);
+}
+
+__device__ __forceinline__ void hist_flush(const double* hs, int nb, double scale, double* out_sum, int tid, int T) {
+  for (int i = tid; i < nb; i += T) {
+    const double v = hs[i];
+    if (v != 0.0) atomicAdd(out_sum + i, v * scale);
+  }
+}
+
+template <int L>
+__host__ __device__ constexpr size_t col_lds_bytes_t(int nb) {
+  // exchange buffer, or the padded power values plus the FP64 histogram
+  return (size_t)ColTile<L>::C * L * 8 > (size_t)ColTile<L>::C * ColTile<L>::LP * 4 + (size_t)nb * 8 + 8
+             ? (size_t)ColTile<L>::C * L * 8
+             : (size_t)ColTile<L>::C * ColTile<L>::LP * 4 + (size_t)nb * 8 + 8;
+}
+
+}  // namespace hu

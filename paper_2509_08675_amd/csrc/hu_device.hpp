@@ -283,10 +283,14 @@ __device__ __forceinline__ U4 philox4x32_10(uint64_t block, uint64_t seed) {
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    // one 32x32 -> 64-bit product per multiplier (a single v_mad_u64_u32 each)
+    const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+    const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -298,13 +302,15 @@ __device__ __forceinline__ float word_to_uniform(uint32_t x) {
   return (float)((x >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
 }
 
+// Box-Muller on the hardware transcendentals: v_log_f32 (log2), v_sqrt_f32 and v_sin_f32 /
+// v_cos_f32, whose argument is in revolutions, so sin(2 pi u) is one instruction.  Over all 2^23
+// possible uniforms they stay within 1.3e-7 of the FP64 values (absolute for sin / cos, relative
+// for ln u and sqrt(-2 ln u)), the accuracy of the library FP32 routines.
 __device__ __forceinline__ void box_muller(uint32_t w0, uint32_t w1, float& z0, float& z1) {
   const float u0 = word_to_uniform(w0), u1 = word_to_uniform(w1);
-  const float r = sqrtf(-2.0f * logf(u0));
-  float s, c;
-  sincospif(2.0f * u1, &s, &c);
-  z0 = r * c;
-  z1 = r * s;
+  const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u0));  // -2 ln 2 log2 u
+  z0 = r * __builtin_amdgcn_cosf(u1);
+  z1 = r * __builtin_amdgcn_sinf(u1);
 }
 
 __device__ __forceinline__ void noise4(uint64_t block, uint64_t seed, float (&z)[4]) {
@@ -326,25 +332,44 @@ struct FiltDev {
   int rotated;           // rot != 0 (H_sym differs from H on x / y Nyquist planes)
 };
 
-// ln chi (relative to its peak) at the (unrotated) wavenumber (kx, ky, kz); -inf-like at K = 0.
+// raw hardware log2 / exp2 (v_log_f32, v_exp_f32)
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ln chi (relative to its peak) at the (unrotated) wavenumber (kx, ky, kz), kz = 0 in 2D:
+//   u_i = |kappa'_i| / a_i,  K = u_max (sum_i (u_i / u_max)^p)^(1/p)   (Eq. (12), scaled form)
+//   ln chi = alpha ln K - (K - k0)^2 / (2 w^2) - ln chi(K*)            (Eq. (13) with band centre k0)
+// The largest ratio is 1, so only the other one (2D) or two (3D) need a power.
+template <int NDIM>
 __device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, float kz) {
   const float kxr = f.cr * kx + f.sr * ky;
   const float kyr = -f.sr * kx + f.cr * ky;
-  const float ux = fabsf(kxr) * f.ia, uy = fabsf(kyr) * f.ib, uz = fabsf(kz) * f.ic;
-  const float um = fmaxf(ux, fmaxf(uy, uz));
-  if (!(um > 0.0f)) return -1.0e30f;
-  const float ium = 1.0f / um;
-  // sum (u_i / u_max)^p, each ratio in [0, 1]; exp2(p log2 r) with r = 0 -> 0
-  float S = 0.0f;
-  const float rx = ux * ium, ry = uy * ium, rz = uz * ium;
-  S += (rx > 0.0f) ? exp2f(f.p * __log2f(rx)) : 0.0f;
-  S += (ry > 0.0f) ? exp2f(f.p * __log2f(ry)) : 0.0f;
-  S += (rz > 0.0f) ? exp2f(f.p * __log2f(rz)) : 0.0f;
-  const float lnK = __logf(um) + __logf(S) * f.ip;
-  const float K = __expf(lnK);
+  const float ux = fabsf(kxr) * f.ia, uy = fabsf(kyr) * f.ib;
+  float um, S;
+  if constexpr (NDIM == 2) {
+    um = fmaxf(ux, uy);
+    const float un = fminf(ux, uy);
+    if (!(um > 0.0f)) return -1.0e30f;
+    const float r = un * __builtin_amdgcn_rcpf(um);
+    S = 1.0f + (r > 0.0f ? hw_exp2(f.p * hw_log2(r)) : 0.0f);
+  } else {
+    const float uz = fabsf(kz) * f.ic;
+    um = fmaxf(ux, fmaxf(uy, uz));
+    if (!(um > 0.0f)) return -1.0e30f;
+    const float lo = fminf(ux, fminf(uy, uz));
+    const float mid = __builtin_amdgcn_fmed3f(ux, uy, uz);
+    const float inv = __builtin_amdgcn_rcpf(um);
+    const float r1 = mid * inv, r2 = lo * inv;
+    S = 1.0f + (r1 > 0.0f ? hw_exp2(f.p * hw_log2(r1)) : 0.0f) + (r2 > 0.0f ? hw_exp2(f.p * hw_log2(r2)) : 0.0f);
+  }
+  const float log2K = hw_log2(um) + hw_log2(S) * f.ip;
+  const float K = hw_exp2(log2K);
   const float d = K - f.k0;
-  return f.alpha * lnK - d * d * f.inv2w2 - f.lnchimax;
+  return f.alpha * (log2K * 0.69314718055994531f) - d * d * f.inv2w2 - f.lnchimax;
 }
+
+// exp(x / 2) for ln chi -> amplitude
+__device__ __forceinline__ float amp_from_lnchi(float lnc) { return hw_exp2(lnc * 0.72134752044448170368f); }
 
 // ---------------------------------------------------------------------------------------------
 // Bin index: exact integer radial rule, FP64 angular edges tested with separately rounded
@@ -353,6 +378,7 @@ __device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, fl
 struct BinDev {
   int nr, na;
   long long D2;          // D^2
+  float invD2;           // 1 / D^2 (estimate only; the rule itself is exact in integers)
   long long fourR2;      // 4 R^2
   const double* ex;      // angular edge unit vectors, na - 1 of them
   const double* ey;
@@ -369,7 +395,7 @@ __device__ __forceinline__ bool edge_le(const BinDev& b, int j, double qx, doubl
 __device__ __forceinline__ int bin_index(const BinDev& b, long long s, long long qx, long long qy) {
   // s = sum of q_i^2; radial r = max{r : r^2 D^2 <= 4 R^2 s}
   const long long rhs = b.fourR2 * s;
-  long long r = (long long)sqrt((double)rhs / (double)b.D2);
+  long long r = (long long)__builtin_amdgcn_sqrtf((float)rhs * b.invD2);
   if (r * r * b.D2 > rhs) --r;
   if ((r + 1) * (r + 1) * b.D2 <= rhs) ++r;
   if (r >= b.nr) return b.nr * b.na;

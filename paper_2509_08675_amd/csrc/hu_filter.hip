@@ -1,0 +1,181 @@
+// The fused axis-0 pass of the generator: forward FFT along the slowest axis, multiplication by
+// the symmetrised amplitude H_sym = sqrt(chi) (Eq. (8) with Eqs. (12)-(13)), the FP64 Parseval
+// statistics of Eq. (15), the continuous-field spectrum bins, and the inverse FFT along the same
+// axis -- one read and one write of the half spectrum.  Each workgroup leaves its partial sums;
+// k_finalize turns them into (mu, var, scale, offset) in a fixed order and rescales the
+// continuous bins to the normalised field.
+#include "hu_common.hpp"
+
+namespace hu {
+
+template <int L, int NDIM>
+__global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L>::C, T = ColTile<L>::T;
+  constexpr int LP = ColTile<L>::LP;
+  using Rad = typename Plan<L>::fwd;
+  using RadI = Reverse<Rad>;
+  constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
+  extern __shared__ float2 lds[];
+  __shared__ double red_d[T / 64], red_d0[T / 64];
+  __shared__ float red_f[T / 64];
+  int b;
+  long long tile;
+  if (!map_tile(a.sc, b, tile)) return;
+  const int tid = threadIdx.x;
+  const int c = tid % C, p = tid / C;
+  const int g = (int)tile * C + c;
+  const bool valid = g < a.gm.ncol;
+  const int ncol = a.gm.ncol;
+  float2* base = a.spec + (long long)b * a.Nh + g;      // 32-bit offsets within the field
+  float2 v[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s)
+    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] : make_float2(0.f, 0.f);
+  fft_run<L, P, E, false>(Rad{}, v, lds + c * L, p, a.tw);
+
+  // ---- filter and per-thread statistics
+  const bool do_bins = a.cont_sum != nullptr;
+  const ColCoord cc = col_coord(a.gm, valid ? g : 0);
+  double gsum = 0.0, f0 = 0.0;
+  float lmax = -1.0e30f;
+  float pwv[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s) {
+    const int e = slot_index<L, RL, P>(s, p);
+    float lnc;
+    const float H = amp_sym<NDIM>(a.filt, a.gm, cc, e, lnc);
+    const float2 F = cscale(v[s], H);
+    v[s] = F;
+    const float m2 = cc.wm * (F.x * F.x + F.y * F.y);
+    pwv[s] = valid ? m2 : 0.0f;
+    if (valid) {
+      gsum += (double)m2;
+      lmax = fmaxf(lmax, lnc);
+      if (g == 0 && e == 0) f0 = (double)F.x;
+    }
+  }
+  // ---- continuous-spectrum histogram (run-length over contiguous modes of each column)
+  if (do_bins) {
+    float* pw = reinterpret_cast<float*>(lds);
+    double* hs = reinterpret_cast<double*>(pw + ((C * LP + 1) & ~1));
+    __syncthreads();                              // the exchange buffer is free from here
+#pragma unroll
+    for (int s = 0; s < E; ++s) pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = pwv[s];
+    for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
+    __syncthreads();
+    if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, a.bd, a.gm, g, p);
+    __syncthreads();
+    hist_flush(hs, a.nb, 1.0, a.cont_sum + (long long)b * a.nb, tid, T);
+  }
+  // ---- workgroup statistics -> partials[b][tile] (reduced by k_finalize after this kernel)
+  gsum = wave_sum(gsum);
+  lmax = wave_max(lmax);
+  f0 = wave_sum(f0);
+  if ((tid & 63) == 0) { red_d[tid >> 6] = gsum; red_f[tid >> 6] = lmax; red_d0[tid >> 6] = f0; }
+  __syncthreads();
+  if (tid == 0) {
+    double gs = 0.0, fz = 0.0;
+    float lm = -1.0e30f;
+    for (int w = 0; w < T / 64; ++w) { gs += red_d[w]; fz += red_d0[w]; lm = fmaxf(lm, red_f[w]); }
+    double* part = a.partials + ((long long)b * a.sc.ntiles + tile) * 4;
+    part[0] = gs;
+    part[1] = fz;
+    part[2] = (double)lm;
+    part[3] = 0.0;
+  }
+
+  // ---- inverse transform along axis 0 (first radix = last forward radix: no exchange needed)
+  fft_run<L, P, E, true>(RadI{}, v, lds + c * L, p, a.tw);
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < E; ++s) base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] = v[s];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// finalize: one workgroup per field turns the filter pass's partials into mu, var and the
+// normalisation constants (Eq. (15) via Parseval) with a fixed-order reduction, and rescales
+// the continuous-field bins to the spectrum of the normalised field.
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
+  __shared__ double sg[256], sf[256];
+  __shared__ float sm[256];
+  __shared__ double fac;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const double* part = a.partials + (long long)b * a.ntiles * 4;
+  double G = 0.0, F0 = 0.0;
+  float lm = -1.0e30f;
+  for (int w = tid; w < a.ntiles; w += 256) {
+    G += part[4 * w + 0];
+    F0 += part[4 * w + 1];
+    lm = fmaxf(lm, (float)part[4 * w + 2]);
+  }
+  sg[tid] = G;
+  sf[tid] = F0;
+  sm[tid] = lm;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      sg[tid] += sg[tid + o];
+      sf[tid] += sf[tid + o];
+      sm[tid] = fmaxf(sm[tid], sm[tid + o]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double N = (double)a.N;
+    const double Gt = sg[0];
+    const double mu = sf[0] / N;                  // Re F(0) / N
+    const double var = Gt / (N * N) - mu * mu;    // Parseval, population variance
+    const double lmx = (double)sm[0];
+    const bool degenerate = !(lmx >= -80.0) || !(var > 0.0);
+    const double sd = degenerate ? 1.0 : sqrt(var);
+    double* fs = a.fstats + (long long)b * 8;
+    fs[0] = mu;
+    fs[1] = var;
+    fs[2] = lmx;
+    fs[3] = degenerate ? 1.0 : 0.0;
+    fs[4] = degenerate ? 0.0 : a.sigma_f / (N * sd);              // scale of the unnormalised inverse
+    fs[5] = degenerate ? 0.0 : -a.sigma_f * mu / sd;               // offset
+    fs[6] = degenerate ? 0.0 : a.sigma_f * a.sigma_f / (N * var);  // continuous-spectrum factor
+    fs[7] = Gt;
+    if (a.stats) {
+      double* st = a.stats + (long long)b * 4;
+      st[0] = mu; st[1] = var; st[2] = lmx; st[3] = fs[3];
+    }
+    fac = fs[6];
+  }
+  __syncthreads();
+  if (a.cont_sum) {
+    double* cs = a.cont_sum + (long long)b * a.nb;
+    for (int i = tid; i < a.nb; i += 256) cs[i] *= fac;
+  }
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_cols_filter_L(const FilterArgs& a, hipStream_t st) {
+  constexpr int T = ColTile<L>::T;
+  const size_t lds = a.cont_sum ? col_lds_bytes_t<L>(a.nb) : (size_t)ColTile<L>::C * L * sizeof(float2);
+  if (a.gm.ndim == 2)
+    hipLaunchKernelGGL((k_cols_filter<L, 2>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_cols_filter<L, 3>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_filter(int L, const FilterArgs& a, int batch, hipStream_t st) {
+  (void)batch;
+  switch (L) {
+#define X(LL) case LL: return launch_cols_filter_L<LL>(a, st);
+    HU_COL_LENGTHS(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace hu

@@ -11,9 +11,18 @@ namespace hu {
 enum { SRC_NOISE = 0, SRC_F32 = 1, SRC_I8 = 2 };
 constexpr int MAX_CHUNK = 64;   // fields per launch (seeds travel in the kernel arguments)
 
-struct ZeroSpan {
-  uint32_t* ptr;    // first word of field 0
+// Accumulator set-up done by block 0 of each field in the first pass: dst[b * per_field + i] is
+// set to src[i] (the same per-field block for every field, e.g. precomputed bin counts) or 0.
+struct FillSpan {
+  uint32_t* dst;
+  const uint32_t* src;
   int per_field;    // 32-bit words per field
+};
+
+// Column-pass schedule: ntiles tiles per field, padded to a multiple of G (tiles sharing a
+// 128-byte line), for `batch` fields; grid = ceil(batch * ntiles_pad / (8 G)) * 8 G workgroups.
+struct ColSched {
+  int ntiles, ntiles_pad, G, batch;
 };
 
 struct RowsArgs {
@@ -23,15 +32,16 @@ struct RowsArgs {
   const void* src;         // real input for the load variants, [B][N]
   const float2* tw;        // exp(-2 pi i t / L), t < L
   const float2* tw2;       // exp(-2 pi i k / 2L), k < L
-  ZeroSpan zero[6];
-  int zero_spans;
+  FillSpan fill[6];
+  int fill_spans;
 };
 
 struct ColsArgs {
+  ColSched sc;
   float2* spec;
   long long Nh;
-  long long ncol;          // transforms per field
-  long long inner;         // element stride (complex) along the axis
+  int ncol;                // transforms per field
+  int inner;               // element stride (complex) along the axis
   const float2* tw;
 };
 
@@ -40,36 +50,55 @@ struct Axis0Geom {
   int n0;                  // length of axis 0
   int ny;                  // n_y (3D)
   int nx, nxh;
-  long long ncol;          // Nh / n0
+  int ncol;                // Nh / n0 (columns of the axis-0 passes)
+  float kap0, kapy, kapx;  // 2 / n_i: wavenumber step in Nyquist units
   long long dfac_0, dfac_y, dfac_x;   // D / n_i, D = lcm of the dims
 };
 
 struct FilterArgs {
+  ColSched sc;
   float2* spec;
   long long Nh, N;
   Axis0Geom gm;
   FiltDev filt;
   BinDev bd;
   int nb;                  // bins + 1 (corner slot)
+  const uint16_t* table;   // bin of each mode, [ncol][n0], or null (computed)
   const float2* tw;
-  double* partials;        // [B][tiles][4]
-  unsigned* counters;      // [B]
+  double* partials;        // [B][tiles][4]: sum w |F|^2, Re F(0), max ln chi
+  double* cont_sum;        // [B][nb] raw sums of w |F|^2, or null (counts are filled from the geometry)
+};
+
+struct FinalizeArgs {
+  const double* partials;  // [B][ntiles][4]
+  int ntiles;
+  long long N;
+  double sigma_f;
   double* fstats;          // [B][8] mu, var, max ln chi, flag, scale, offset, spectrum factor, G
   double* stats;           // [B][4] user copy or null
-  double* cont_sum;        // [B][nb] or null
-  uint64_t* cont_cnt;
-  double sigma_f;
+  double* cont_sum;        // [B][nb] rescaled in place, or null
+  int nb;
 };
 
 struct BinArgs {
+  ColSched sc;
   const float2* spec;
   long long Nh, N;
   Axis0Geom gm;
   BinDev bd;
   int nb;
+  const uint16_t* table;
   const float2* tw;
   double* sum;
-  uint64_t* cnt;
+};
+
+struct BinGeomArgs {
+  long long Nh;
+  Axis0Geom gm;
+  BinDev bd;
+  int nb;
+  uint16_t* table;         // [ncol][n0] or null
+  unsigned long long* counts;   // [nb], zeroed before the launch
 };
 
 struct RowsZArgs {
@@ -95,9 +124,12 @@ struct ThreshArgs {
 hipError_t launch_rows_r2c(int L, int src, const RowsArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols(int L, bool inv, const ColsArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols_filter(int L, const FilterArgs& a, int batch, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols_bin(int L, const BinArgs& a, int batch, hipStream_t st);
 hipError_t launch_rows_c2r(int L, bool thresh, const RowsZArgs& a, int batch, hipStream_t st);
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st);
+hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st);
+ColSched col_sched(int L, long long ncol, int batch);
 hipError_t launch_zero_u64(uint64_t* p, long long n, hipStream_t st);
 hipError_t launch_debug_philox(uint64_t seed, uint64_t first, uint64_t count, uint32_t* words, float* normals,
                                hipStream_t st);

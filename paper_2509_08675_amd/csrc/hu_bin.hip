@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_bin(BinArgs a) {
 #pragma unroll
   for (int s = 0; s < E; ++s)
     v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] : make_float2(0.f, 0.f);
-  fft_run<L, P, E, false>(Rad{}, v, lds + c * L, p, a.tw);
+  fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
   const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
   float* pw = reinterpret_cast<float*>(lds);
   double* hs = reinterpret_cast<double*>(pw + ((C * LP + 1) & ~1));

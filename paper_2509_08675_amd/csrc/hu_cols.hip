@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols(ColsArgs a) {
 #pragma unroll
   for (int s = 0; s < E; ++s)
     v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] : make_float2(0.f, 0.f);
-  fft_run<L, P, E, INV>(Rad{}, v, lds + c * L, p, a.tw);
+  fft_run<L, P, E, INV>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < E; ++s) base[(unsigned)(slot_index<L, RL, P>(s, p) * inner)] = v[s];
@@ -59,7 +59,7 @@ int col_tiles(int L, long long ncol) { return col_sched(L, ncol, 1).ntiles; }
 template <int L, bool INV>
 static hipError_t launch_cols_L(const ColsArgs& a, hipStream_t st) {
   constexpr int C = ColTile<L>::C, T = ColTile<L>::T;
-  hipLaunchKernelGGL((k_cols<L, INV>), dim3(sched_blocks(a.sc)), dim3(T), (size_t)C * L * sizeof(float2), st, a);
+  hipLaunchKernelGGL((k_cols<L, INV>), dim3(sched_blocks(a.sc)), dim3(T), col_xchg_bytes<L>(), st, a);
   return hipGetLastError();
 }
 

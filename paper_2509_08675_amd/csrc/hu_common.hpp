@@ -18,7 +18,7 @@ template <int L>
 struct RowTile {
   static constexpr int P = Plan<L>::P;
   static constexpr int c0 = 256 / P > 0 ? 256 / P : 1;
-  static constexpr int cl = 8192 / (L + 1) > 0 ? 8192 / (L + 1) : 1;
+  static constexpr int cl = 8192 / Region<L>::value > 0 ? 8192 / Region<L>::value : 1;
   static constexpr int C = c0 < cl ? c0 : cl;
   static constexpr int T = C * P;
 };
@@ -26,7 +26,7 @@ struct RowTile {
 template <int L>
 struct ColTile {
   static constexpr int P = Plan<L>::P;
-  static constexpr int a = 8192 / L < 32 ? 8192 / L : 32;
+  static constexpr int a = 8192 / L < 32 ? 8192 / L : 32;   // 64 KB of exchange buffer (unpadded)
   static constexpr int b = 64 / P > a ? 64 / P : a;
   static constexpr int C = b * P > 1024 ? 1024 / P : b;
   static constexpr int T = C * P;
@@ -65,8 +65,8 @@ __device__ __forceinline__ void r2c_twist_store(const float2* lz, const float2* 
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int k = p + P * i;
-    const float2 zk = lz[k];
-    const float2 zm = cconj(lz[(L - k) % L]);
+    const float2 zk = lz[lidx(k)];
+    const float2 zm = cconj(lz[lidx((L - k) % L)]);
     const float2 A = cadd(zk, zm), B = csub(zk, zm);
     const float2 X = cscale(cadd(A, mul_mi<false>(cmul(tw2[k], B))), 0.5f);
     if (valid) out[k] = X;
@@ -227,10 +227,15 @@ __device__ __forceinline__ void hist_flush(const double* hs, int nb, double scal
 }
 
 template <int L>
+__host__ __device__ constexpr size_t col_xchg_bytes() {
+  return (size_t)ColTile<L>::C * Region<L>::value * 8;
+}
+
+template <int L>
 __host__ __device__ constexpr size_t col_lds_bytes_t(int nb) {
   // exchange buffer, or the padded power values plus the FP64 histogram
-  return (size_t)ColTile<L>::C * L * 8 > (size_t)ColTile<L>::C * ColTile<L>::LP * 4 + (size_t)nb * 8 + 8
-             ? (size_t)ColTile<L>::C * L * 8
+  return col_xchg_bytes<L>() > (size_t)ColTile<L>::C * ColTile<L>::LP * 4 + (size_t)nb * 8 + 8
+             ? col_xchg_bytes<L>()
              : (size_t)ColTile<L>::C * ColTile<L>::LP * 4 + (size_t)nb * 8 + 8;
 }
 

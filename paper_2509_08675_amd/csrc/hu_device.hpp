@@ -227,6 +227,16 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[E], int p, const float
   }
 }
 
+// LDS layout of an exchange region: one padding element after every 16, so that the strided
+// stores of the early Stockham stages (stride R complex) fall on distinct banks.
+__host__ __device__ constexpr int lidx(int i) { return i + (i >> 4); }
+// complex elements per exchange region of a length-L transform (padding plus 8 so that
+// neighbouring regions start on different banks)
+template <int L>
+struct Region {
+  static constexpr int value = L + (L >> 4) + 8;
+};
+
 template <int L, int R, int NS, int P, int E>
 __device__ __forceinline__ void stage_store(const float2 (&v)[E], float2* lds, int p) {
 #pragma unroll
@@ -234,7 +244,7 @@ __device__ __forceinline__ void stage_store(const float2 (&v)[E], float2* lds, i
     const int j = p + P * b;
     const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[base + r * NS] = v[b * R + r];
+    for (int r = 0; r < R; ++r) lds[lidx(base + r * NS)] = v[b * R + r];
   }
 }
 
@@ -244,7 +254,7 @@ __device__ __forceinline__ void stage_load(float2 (&v)[E], const float2* lds, in
   for (int b = 0; b < E / R; ++b) {
     const int j = p + P * b;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[b * R + r] = lds[j + r * (L / R)];
+    for (int r = 0; r < R; ++r) v[b * R + r] = lds[lidx(j + r * (L / R))];
   }
 }
 

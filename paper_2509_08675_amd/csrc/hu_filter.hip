@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
 #pragma unroll
   for (int s = 0; s < E; ++s)
     v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] : make_float2(0.f, 0.f);
-  fft_run<L, P, E, false>(Rad{}, v, lds + c * L, p, a.tw);
+  fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
 
   // ---- filter and per-thread statistics
   const bool do_bins = a.cont_sum != nullptr;
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
   }
 
   // ---- inverse transform along axis 0 (first radix = last forward radix: no exchange needed)
-  fft_run<L, P, E, true>(RadI{}, v, lds + c * L, p, a.tw);
+  fft_run<L, P, E, true>(RadI{}, v, lds + c * Region<L>::value, p, a.tw);
   if (valid) {
 #pragma unroll
     for (int s = 0; s < E; ++s) base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] = v[s];
@@ -160,7 +160,7 @@ hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st) {
 template <int L>
 static hipError_t launch_cols_filter_L(const FilterArgs& a, hipStream_t st) {
   constexpr int T = ColTile<L>::T;
-  const size_t lds = a.cont_sum ? col_lds_bytes_t<L>(a.nb) : (size_t)ColTile<L>::C * L * sizeof(float2);
+  const size_t lds = a.cont_sum ? col_lds_bytes_t<L>(a.nb) : col_xchg_bytes<L>();
   if (a.gm.ndim == 2)
     hipLaunchKernelGGL((k_cols_filter<L, 2>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
   else

@@ -16,6 +16,7 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L>::C, T = RowTile<L>::T;
   using Rad = typename Plan<L>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
+  constexpr int RS = Region<L>::value;
   extern __shared__ float2 lds[];
   float* ldsf = reinterpret_cast<float*>(lds);
   const int tid = threadIdx.x;
@@ -34,44 +35,48 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
     }
   }
 
-  // ---- the C real rows into LDS (as floats)
+  // ---- the C real rows into LDS: sample x of row c goes to float 2 lidx(x / 2) + (x & 1) of region c
   const long long v0 = row0 * nx;
   const long long rows_here = (a.nrows - row0) < C ? (a.nrows - row0) : C;
-  const long long v1 = v0 + rows_here * nx;
+  const int nv = (int)(rows_here * nx);
   if constexpr (SRC == SRC_NOISE) {
     // voxel i of the field takes normal i mod 4 of Philox block i / 4
     const uint64_t seed = a.seeds[b];
-    const long long m0 = v0 >> 2, m1 = (v1 + 3) >> 2;
+    const long long m0 = v0 >> 2, m1 = (v0 + nv + 3) >> 2;
     for (long long m = m0 + tid; m < m1; m += T) {
       float z[4];
       noise4((uint64_t)m, seed, z);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const long long v = 4 * m + q;
-        if (v >= v0 && v < v1) ldsf[v - v0] = z[q];
+        const int v = (int)(4 * m + q - v0);
+        if (v >= 0 && v < nv) {
+          const int rc = v / (2 * L), x = v - rc * (2 * L);
+          ldsf[2 * (rc * RS + lidx(x >> 1)) + (x & 1)] = z[q];
+        }
       }
     }
   } else {
     const long long base = (long long)b * a.N + v0;
-    for (long long i = tid; i < C * nx; i += T) {
+    for (int i = tid; i < C * 2 * L; i += T) {
       float x = 0.0f;
-      if (i < v1 - v0) {
+      if (i < nv) {
         if constexpr (SRC == SRC_F32) x = reinterpret_cast<const float*>(a.src)[base + i];
         else x = (float)reinterpret_cast<const int8_t*>(a.src)[base + i];
       }
-      ldsf[i] = x;
+      const int rc = i / (2 * L), xx = i - rc * (2 * L);
+      ldsf[2 * (rc * RS + lidx(xx >> 1)) + (xx & 1)] = x;
     }
   }
   __syncthreads();
 
   float2 v[E];
-  float2* lrow = lds + c * L;
+  float2* lrow = lds + c * RS;
 #pragma unroll
-  for (int s = 0; s < E; ++s) v[s] = lrow[slot_index<L, R1, P>(s, p)];
+  for (int s = 0; s < E; ++s) v[s] = lrow[lidx(slot_index<L, R1, P>(s, p))];
   fft_run<L, P, E, false>(Rad{}, v, lrow, p, a.tw);
   __syncthreads();
 #pragma unroll
-  for (int s = 0; s < E; ++s) lrow[slot_index<L, RL, P>(s, p)] = v[s];
+  for (int s = 0; s < E; ++s) lrow[lidx(slot_index<L, RL, P>(s, p))] = v[s];
   __syncthreads();
   float2* out = a.spec + (long long)b * a.Nh + row * (L + 1);
   r2c_twist_store<L, P, E>(lrow, a.tw2, out, p, valid);
@@ -85,6 +90,7 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
   using RadF = Reverse<Rad>;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
   constexpr int LS = L + 1;
+  constexpr int RS = Region<L>::value;
   extern __shared__ float2 lds[];
   __shared__ unsigned red_u[2][T / 64 > 0 ? T / 64 : 1];
   const int tid = threadIdx.x;
@@ -92,7 +98,7 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
   const int b = blockIdx.y;
   const long long row = (long long)blockIdx.x * C + c;
   const bool valid = row < a.nrows;
-  float2* lrow = lds + c * LS;
+  float2* lrow = lds + c * RS;
   float2* srow = a.spec + (long long)b * a.Nh + row * LS;
 
   // ---- the half row X[0..L] into LDS; X[0] and X[L] are real after the other axes' inverses
@@ -101,16 +107,16 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
     const int k = p + P * i;
     float2 x = valid ? srow[k] : make_float2(0.f, 0.f);
     if (k == 0) x.y = 0.0f;
-    lrow[k] = x;
+    lrow[lidx(k)] = x;
   }
-  if (p == 0) lrow[L] = valid ? make_float2(srow[L].x, 0.0f) : make_float2(0.f, 0.f);
+  if (p == 0) lrow[lidx(L)] = valid ? make_float2(srow[L].x, 0.0f) : make_float2(0.f, 0.f);
   __syncthreads();
   // ---- pre-twist: Z[k] = (X[k] + X*[L-k]) + i e^{+2 pi i k / 2L} (X[k] - X*[L-k])
   float2 v[E];
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int k = slot_index<L, R1, P>(s, p);
-    const float2 xk = lrow[k], xc = cconj(lrow[L - k]);
+    const float2 xk = lrow[lidx(k)], xc = cconj(lrow[lidx(L - k)]);
     v[s] = cadd(cadd(xk, xc), mul_mi<true>(cmul(cconj(a.tw2[k]), csub(xk, xc))));
   }
   fft_run<L, P, E, true>(Rad{}, v, lrow, p, a.tw);
@@ -152,7 +158,7 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
     __syncthreads();
     constexpr int RLF = RadInfo<RadF>::last;
 #pragma unroll
-    for (int s = 0; s < E; ++s) lrow[slot_index<L, RLF, P>(s, p)] = v[s];
+    for (int s = 0; s < E; ++s) lrow[lidx(slot_index<L, RLF, P>(s, p))] = v[s];
     __syncthreads();
     r2c_twist_store<L, P, E>(lrow, a.tw2, srow, p, valid);
     if (tid == 0 && a.counts) {
@@ -172,7 +178,7 @@ template <int L, int SRC>
 static hipError_t launch_rows_r2c_L(const RowsArgs& a, int batch, hipStream_t st) {
   constexpr int C = RowTile<L>::C, T = RowTile<L>::T;
   dim3 grid(ceil_div_u(a.nrows, C), batch);
-  hipLaunchKernelGGL((k_rows_r2c<L, SRC>), grid, dim3(T), (size_t)C * L * sizeof(float2), st, a);
+  hipLaunchKernelGGL((k_rows_r2c<L, SRC>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2), st, a);
   return hipGetLastError();
 }
 
@@ -193,7 +199,7 @@ template <int L, bool THRESH>
 static hipError_t launch_rows_c2r_L(const RowsZArgs& a, int batch, hipStream_t st) {
   constexpr int C = RowTile<L>::C, T = RowTile<L>::T;
   dim3 grid(ceil_div_u(a.nrows, C), batch);
-  hipLaunchKernelGGL((k_rows_c2r<L, THRESH>), grid, dim3(T), (size_t)C * (L + 1) * sizeof(float2), st, a);
+  hipLaunchKernelGGL((k_rows_c2r<L, THRESH>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2), st, a);
   return hipGetLastError();
 }
 

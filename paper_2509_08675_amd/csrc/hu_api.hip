@@ -174,6 +174,8 @@ struct Geom {
   int nx, nxh;
   long long N, Nh, nrows;
   long long D;
+  int tiled;        // 2D: half spectrum in column groups of 4 (TW = 4); 3D: row-major
+  long long Nhp;    // per-field half-spectrum storage (padded to whole column groups in 2D)
 };
 
 long long lcm_ll(long long a, long long b) { return a / std::gcd(a, b) * b; }
@@ -194,6 +196,8 @@ int make_geom(const hu_dims& d, Geom* g) {
   g->nxh = g->nx / 2 + 1;
   g->nrows = g->N / g->nx;
   g->Nh = g->nrows * g->nxh;
+  g->tiled = d.ndim == 2 ? 1 : 0;
+  g->Nhp = g->tiled ? g->nrows * ((g->nxh + 3) / 4 * 4) : g->Nh;
   if (g->N >= (1LL << 31)) return HU_ERR_SIZE;      // in-field offsets are 32-bit
   return HU_OK;
 }
@@ -230,7 +234,7 @@ Layout layout(const Geom& g, int batch, bool need_stats) {
   Layout L{};
   size_t off = 0;
   L.spec = off;
-  off += up256((size_t)batch * g.Nh * sizeof(float2));
+  off += up256((size_t)batch * g.Nhp * sizeof(float2));
   L.tiles = col_tiles(g.n[0], g.Nh / g.n[0]);
   if (need_stats) {
     L.partials = off;
@@ -269,6 +273,7 @@ Axis0Geom axis0(const Geom& g) {
   a.nx = g.nx;
   a.nxh = g.nxh;
   a.ncol = (int)(g.Nh / g.n[0]);
+  a.inner0 = g.tiled ? 4 : a.ncol;
   a.kap0 = (float)(2.0 / g.n[0]);
   a.kapy = g.nd == 3 ? (float)(2.0 / g.n[1]) : 0.0f;
   a.kapx = (float)(2.0 / g.nx);
@@ -363,7 +368,8 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
   // pass A: noise -> R2C rows; block 0 of each field sets up that field's accumulators
   RowsArgs ra{};
   ra.spec = spec;
-  ra.Nh = g.Nh;
+  ra.Nh = g.Nhp;
+  ra.tiled = g.tiled;
   ra.N = g.N;
   ra.nrows = g.nrows;
   for (int i = 0; i < B; ++i) ra.seeds[i] = seeds[i];
@@ -381,7 +387,7 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
   ColsArgs cy{};
   if (g.nd == 3) {
     cy.spec = spec;
-    cy.Nh = g.Nh;
+    cy.Nh = g.Nhp;
     cy.ncol = g.n[0] * g.nxh;
     cy.inner = g.nxh;
     cy.tw = tw_1;
@@ -391,7 +397,7 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
 
   FilterArgs fa{};
   fa.spec = spec;
-  fa.Nh = g.Nh;
+  fa.Nh = g.Nhp;
   fa.N = g.N;
   fa.gm = axis0(g);
   fa.sc = col_sched(g.n[0], fa.gm.ncol, B);
@@ -418,7 +424,8 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
 
   RowsZArgs za{};
   za.spec = spec;
-  za.Nh = g.Nh;
+  za.Nh = g.Nhp;
+  za.tiled = g.tiled;
   za.N = g.N;
   za.nrows = g.nrows;
   za.tw = tw_row;
@@ -434,7 +441,7 @@ int run_chunk(const Geom& g, int B, const hu_filter& f, const uint64_t* seeds, c
     if (g.nd == 3) HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, cy, B, st); }));
     BinArgs ba{};
     ba.spec = spec;
-    ba.Nh = g.Nh;
+    ba.Nh = g.Nhp;
     ba.N = g.N;
     ba.gm = axis0(g);
     ba.sc = col_sched(g.n[0], ba.gm.ncol, B);
@@ -579,7 +586,8 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
     const int B = batch - f0 < MAX_CHUNK ? batch - f0 : MAX_CHUNK;
     RowsArgs ra{};
     ra.spec = spec;
-    ra.Nh = g.Nh;
+    ra.Nh = g.Nhp;
+  ra.tiled = g.tiled;
     ra.N = g.N;
     ra.nrows = g.nrows;
     ra.src = reinterpret_cast<const char*>(x) + (size_t)f0 * g.N * esz;
@@ -596,7 +604,7 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
     if (g.nd == 3) {
       ColsArgs cy{};
       cy.spec = spec;
-      cy.Nh = g.Nh;
+      cy.Nh = g.Nhp;
       cy.ncol = g.n[0] * g.nxh;
       cy.inner = g.nxh;
       cy.tw = tw_1;
@@ -605,7 +613,7 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
     }
     BinArgs ba{};
     ba.spec = spec;
-    ba.Nh = g.Nh;
+    ba.Nh = g.Nhp;
     ba.N = g.N;
     ba.gm = axis0(g);
     ba.sc = col_sched(g.n[0], ba.gm.ncol, B);

@@ -24,12 +24,13 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_bin(BinArgs a) {
   const int c = tid % C, p = tid / C;
   const int g = (int)tile * C + c;
   const bool valid = g < a.gm.ncol;
-  const int ncol = a.gm.ncol;
-  const float2* base = a.spec + (long long)b * a.Nh + g;
+  const int inner = a.gm.inner0;
+  const unsigned go = (unsigned)g / (unsigned)inner;
+  const float2* base = a.spec + (long long)b * a.Nh + (unsigned)(go * (L * inner) + (g - go * inner));
   float2 v[E];
 #pragma unroll
   for (int s = 0; s < E; ++s)
-    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] : make_float2(0.f, 0.f);
+    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] : make_float2(0.f, 0.f);
   fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
   const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
   float* pw = reinterpret_cast<float*>(lds);

@@ -38,8 +38,9 @@ static ColSched col_sched_L(long long ncol, int batch) {
   ColSched s;
   s.ntiles = (int)((ncol + C - 1) / C);
   // tiles narrower than a 128-byte line (16 complex) share lines with their neighbours
-  s.G = C >= 16 ? 1 : 16 / C;
-  if (s.G > s.ntiles) s.G = 1;
+  // one workgroup per tile (every layout gives each tile whole 128-byte line runs); the
+  // same-XCD grouping of neighbouring tiles is kept for G > 1
+  s.G = 1;
   s.ntiles_pad = (s.ntiles + s.G - 1) / s.G * s.G;
   s.batch = batch;
   return s;

@@ -25,12 +25,13 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
   const int c = tid % C, p = tid / C;
   const int g = (int)tile * C + c;
   const bool valid = g < a.gm.ncol;
-  const int ncol = a.gm.ncol;
-  float2* base = a.spec + (long long)b * a.Nh + g;      // 32-bit offsets within the field
+  const int inner = a.gm.inner0;
+  const unsigned go = (unsigned)g / (unsigned)inner;
+  float2* base = a.spec + (long long)b * a.Nh + (unsigned)(go * (L * inner) + (g - go * inner));
   float2 v[E];
 #pragma unroll
   for (int s = 0; s < E; ++s)
-    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] : make_float2(0.f, 0.f);
+    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] : make_float2(0.f, 0.f);
   fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
 
   // ---- filter and per-thread statistics
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
   fft_run<L, P, E, true>(RadI{}, v, lds + c * Region<L>::value, p, a.tw);
   if (valid) {
 #pragma unroll
-    for (int s = 0; s < E; ++s) base[(unsigned)(slot_index<L, R1, P>(s, p) * ncol)] = v[s];
+    for (int s = 0; s < E; ++s) base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] = v[s];
   }
 }
 

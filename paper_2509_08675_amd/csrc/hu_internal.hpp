@@ -26,8 +26,9 @@ struct ColSched {
 };
 
 struct RowsArgs {
-  float2* spec;            // half spectrum, [B][Nh]
+  float2* spec;            // half spectrum, [B][Nh] (Nh: per-field stride, padded layout)
   long long Nh, N, nrows;  // per field
+  int tiled;               // 2D column-group layout (TW = 4) or row-major (3D)
   uint64_t seeds[MAX_CHUNK];
   const void* src;         // real input for the load variants, [B][N]
   const float2* tw;        // exp(-2 pi i t / L), t < L
@@ -50,7 +51,8 @@ struct Axis0Geom {
   int n0;                  // length of axis 0
   int ny;                  // n_y (3D)
   int nx, nxh;
-  int ncol;                // Nh / n0 (columns of the axis-0 passes)
+  int ncol;                // columns of the axis-0 passes (n_x/2+1 in 2D, n_y (n_x/2+1) in 3D)
+  int inner0;              // element stride along axis 0: 4 (2D column groups) or ncol (3D)
   float kap0, kapy, kapx;  // 2 / n_i: wavenumber step in Nyquist units
   long long dfac_0, dfac_y, dfac_x;   // D / n_i, D = lcm of the dims
 };
@@ -104,6 +106,7 @@ struct BinGeomArgs {
 struct RowsZArgs {
   float2* spec;
   long long Nh, N, nrows;
+  int tiled;
   const float2* tw;
   const float2* tw2;
   const double* fstats;

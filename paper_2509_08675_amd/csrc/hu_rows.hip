@@ -6,25 +6,62 @@
 //   rows_c2r   inverse of that for each x row, then the normalisation of Eq. (15) with the
 //              statistics of the filter pass, the FP32 field and the +-1 sign map with counts,
 //              and the real-to-complex transform of the +-1 row written back in place.
+//
+// Half-spectrum layout seen by the row passes: element k of row r sits at
+//   (k / TW) * (nrows * TW) + r * TW + (k % TW),
+// TW = 4 for 2D grids (column groups of four, so that a 4-column tile of the axis-0 pass and a
+// 4-row tile of these passes both move whole 128-byte lines) and TW = n_x/2 + 1 for 3D grids
+// (plain row-major).  Global loads and stores of the half spectrum walk this layout in address
+// order, decoupled from the FFT's thread mapping, through LDS.
 #include "hu_common.hpp"
 
 namespace hu {
 
-// grid (ceil(nrows / C), B), block C * P; thread (c, p) = (tid / P, tid % P) works on row c.
-template <int L, int SRC>
+template <int L, bool TILED>
+struct RowIO {
+  static constexpr int TW = TILED ? 4 : L + 1;
+  static constexpr int NG = (L + 1 + TW - 1) / TW;   // column groups
+};
+
+// R2C split twist of every row of the tile from Z in LDS (padded, natural order) to the half
+// spectrum, in address order:
+//   X[k] = (Z[k] + Z*[L-k])/2 - (i/2) e^{-2 pi i k / 2L} (Z[k] - Z*[L-k]),  X[L] = Re Z[0] - Im Z[0].
+template <int L, int C, int T, bool TILED>
+__device__ __forceinline__ void twist_store_rows(const float2* lds, const float2* __restrict__ tw2, float2* spec_f,
+                                                 long long row0, int rows_here, long long nrows, int tid) {
+  constexpr int TW = RowIO<L, TILED>::TW, NG = RowIO<L, TILED>::NG, RS = Region<L>::value;
+  constexpr int PG = C * TW;
+  for (int u = tid; u < NG * PG; u += T) {
+    const int q = u / PG, w = u - q * PG, cc = w / TW, kk = w - cc * TW;
+    const int k = q * TW + kk;
+    if (k > L || cc >= rows_here) continue;
+    const float2* lz = lds + cc * RS;
+    const float2 zk = lz[lidx(k == L ? 0 : k)];
+    float2 X;
+    if (k == L) {
+      X = make_float2(zk.x - zk.y, 0.0f);
+    } else {
+      const float2 zm = cconj(lz[lidx((L - k) % L)]);
+      const float2 A = cadd(zk, zm), B = csub(zk, zm);
+      X = cscale(cadd(A, mul_mi<false>(cmul(tw2[k], B))), 0.5f);
+    }
+    spec_f[((long long)q * nrows + row0 + cc) * TW + kk] = X;
+  }
+}
+
+// grid (ceil(nrows / C), B), block C * P; thread (c, p) = (tid / P, tid % P) transforms row c.
+template <int L, int SRC, bool TILED>
 __global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L>::C, T = RowTile<L>::T;
+  constexpr int RS = Region<L>::value;
   using Rad = typename Plan<L>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
-  constexpr int RS = Region<L>::value;
   extern __shared__ float2 lds[];
   float* ldsf = reinterpret_cast<float*>(lds);
   const int tid = threadIdx.x;
   const int c = tid / P, p = tid % P;
   const int b = blockIdx.y;
   const long long row0 = (long long)blockIdx.x * C;
-  const long long row = row0 + c;
-  const bool valid = row < a.nrows;
   const long long nx = 2 * L;
 
   if (blockIdx.x == 0) {                        // set up this field's accumulators for later passes
@@ -37,8 +74,8 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
 
   // ---- the C real rows into LDS: sample x of row c goes to float 2 lidx(x / 2) + (x & 1) of region c
   const long long v0 = row0 * nx;
-  const long long rows_here = (a.nrows - row0) < C ? (a.nrows - row0) : C;
-  const int nv = (int)(rows_here * nx);
+  const int rows_here = (int)((a.nrows - row0) < C ? (a.nrows - row0) : C);
+  const int nv = rows_here * 2 * L;
   if constexpr (SRC == SRC_NOISE) {
     // voxel i of the field takes normal i mod 4 of Philox block i / 4
     const uint64_t seed = a.seeds[b];
@@ -78,38 +115,38 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
 #pragma unroll
   for (int s = 0; s < E; ++s) lrow[lidx(slot_index<L, RL, P>(s, p))] = v[s];
   __syncthreads();
-  float2* out = a.spec + (long long)b * a.Nh + row * (L + 1);
-  r2c_twist_store<L, P, E>(lrow, a.tw2, out, p, valid);
+  twist_store_rows<L, C, T, TILED>(lds, a.tw2, a.spec + (long long)b * a.Nh, row0, rows_here, a.nrows, tid);
 }
 
 // C2R along x -> normalise -> field, sign map, counts -> R2C of the +-1 row (THRESH).
-template <int L, bool THRESH>
+template <int L, bool THRESH, bool TILED>
 __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L>::C, T = RowTile<L>::T;
+  constexpr int RS = Region<L>::value;
+  constexpr int TW = RowIO<L, TILED>::TW, NG = RowIO<L, TILED>::NG, PG = C * TW;
   using Rad = typename Plan<L>::fwd;
   using RadF = Reverse<Rad>;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
-  constexpr int LS = L + 1;
-  constexpr int RS = Region<L>::value;
   extern __shared__ float2 lds[];
   __shared__ unsigned red_u[2][T / 64 > 0 ? T / 64 : 1];
   const int tid = threadIdx.x;
   const int c = tid / P, p = tid % P;
   const int b = blockIdx.y;
-  const long long row = (long long)blockIdx.x * C + c;
-  const bool valid = row < a.nrows;
+  const long long row0 = (long long)blockIdx.x * C;
+  const int rows_here = (int)((a.nrows - row0) < C ? (a.nrows - row0) : C);
   float2* lrow = lds + c * RS;
-  float2* srow = a.spec + (long long)b * a.Nh + row * LS;
+  float2* spec_f = a.spec + (long long)b * a.Nh;
 
-  // ---- the half row X[0..L] into LDS; X[0] and X[L] are real after the other axes' inverses
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int k = p + P * i;
-    float2 x = valid ? srow[k] : make_float2(0.f, 0.f);
-    if (k == 0) x.y = 0.0f;
-    lrow[lidx(k)] = x;
+  // ---- the tile's half rows X[0..L] into LDS, in address order; X[0] and X[L] are real after
+  //      the other axes' inverse transforms
+  for (int u = tid; u < NG * PG; u += T) {
+    const int q = u / PG, w = u - q * PG, cc = w / TW, kk = w - cc * TW;
+    const int k = q * TW + kk;
+    if (k > L) continue;
+    float2 x = cc < rows_here ? spec_f[((long long)q * a.nrows + row0 + cc) * TW + kk] : make_float2(0.f, 0.f);
+    if (k == 0 || k == L) x.y = 0.0f;
+    lds[cc * RS + lidx(k)] = x;
   }
-  if (p == 0) lrow[lidx(L)] = valid ? make_float2(srow[L].x, 0.0f) : make_float2(0.f, 0.f);
   __syncthreads();
   // ---- pre-twist: Z[k] = (X[k] + X*[L-k]) + i e^{+2 pi i k / 2L} (X[k] - X*[L-k])
   float2 v[E];
@@ -121,32 +158,48 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
   }
   fft_run<L, P, E, true>(Rad{}, v, lrow, p, a.tw);
 
-  // ---- normalise (Eq. (15)), write the field, threshold
+  // ---- normalise (Eq. (15)); stage the field in LDS (rows contiguous, unpadded)
   const double* fs = a.fstats + (long long)b * 8;
   const float scale = (float)fs[4], offset = (float)fs[5];
-  const float tol = a.near_tol;
-  unsigned npos = 0, nnear = 0;
-  float* frow = a.field ? a.field + (long long)b * a.N + row * (2LL * L) : nullptr;
-  int8_t* trow = a.pm1 ? a.pm1 + (long long)b * a.N + row * (2LL * L) : nullptr;
+  float* stage = reinterpret_cast<float*>(lds);
+  __syncthreads();                               // exchange buffer free
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int n = slot_index<L, RL, P>(s, p);
     const float x0 = fmaf(v[s].x, scale, offset);
     const float x1 = fmaf(v[s].y, scale, offset);
-    if (valid && frow) *reinterpret_cast<float2*>(frow + 2 * n) = make_float2(x0, x1);
+    *reinterpret_cast<float2*>(stage + c * 2 * L + 2 * n) = make_float2(x0, x1);
+    if constexpr (THRESH) v[s] = make_float2(x0 >= 0.0f ? 1.0f : -1.0f, x1 >= 0.0f ? 1.0f : -1.0f);
+  }
+  __syncthreads();
+  // ---- field and sign map out, 4 voxels (16 B of field, 4 B of map) per unit
+  const long long gbase = (long long)b * a.N + row0 * 2 * L;
+  const int nq = rows_here * L / 2;              // units of 4 voxels in the tile
+  unsigned npos = 0, nnear = 0;
+  for (int u = tid; u < nq; u += T) {
+    const float4 f4 = *reinterpret_cast<const float4*>(stage + 4 * u);
+    if (a.field) *reinterpret_cast<float4*>(a.field + gbase + 4 * u) = f4;
     if constexpr (THRESH) {
-      const float t0 = x0 >= 0.0f ? 1.0f : -1.0f, t1 = x1 >= 0.0f ? 1.0f : -1.0f;
-      if (valid) {
-        npos += (x0 >= 0.0f) + (x1 >= 0.0f);
-        nnear += (fabsf(x0) < tol) + (fabsf(x1) < tol);
-        if (trow) {
-          char2 tt;
-          tt.x = (signed char)t0;
-          tt.y = (signed char)t1;
-          *reinterpret_cast<char2*>(trow + 2 * n) = tt;
-        }
+      const float xs[4] = {f4.x, f4.y, f4.z, f4.w};
+      uint32_t packed = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool pos = xs[q] >= 0.0f;
+        npos += pos;
+        nnear += fabsf(xs[q]) < a.near_tol;
+        packed |= (uint32_t)(pos ? 0x01u : 0xFFu) << (8 * q);
       }
-      v[s] = make_float2(t0, t1);
+      if (a.pm1) *reinterpret_cast<uint32_t*>(a.pm1 + gbase + 4 * u) = packed;
+    }
+  }
+  // tail (rows of 6 voxels): the last rows_here * 2L mod 4 samples one by one
+  for (int i = 4 * nq + tid; i < rows_here * 2 * L; i += T) {
+    const float x = stage[i];
+    if (a.field) a.field[gbase + i] = x;
+    if constexpr (THRESH) {
+      npos += x >= 0.0f;
+      nnear += fabsf(x) < a.near_tol;
+      if (a.pm1) a.pm1[gbase + i] = x >= 0.0f ? (int8_t)1 : (int8_t)-1;
     }
   }
   if constexpr (THRESH) {
@@ -160,7 +213,7 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
 #pragma unroll
     for (int s = 0; s < E; ++s) lrow[lidx(slot_index<L, RLF, P>(s, p))] = v[s];
     __syncthreads();
-    r2c_twist_store<L, P, E>(lrow, a.tw2, srow, p, valid);
+    twist_store_rows<L, C, T, TILED>(lds, a.tw2, spec_f, row0, rows_here, a.nrows, tid);
     if (tid == 0 && a.counts) {
       unsigned long long np = 0, nn = 0;
       for (int w = 0; w < (T + 63) / 64; ++w) { np += red_u[0][w]; nn += red_u[1][w]; }
@@ -174,41 +227,51 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
 
 static inline unsigned ceil_div_u(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
-template <int L, int SRC>
+template <int L, int SRC, bool TILED>
 static hipError_t launch_rows_r2c_L(const RowsArgs& a, int batch, hipStream_t st) {
   constexpr int C = RowTile<L>::C, T = RowTile<L>::T;
   dim3 grid(ceil_div_u(a.nrows, C), batch);
-  hipLaunchKernelGGL((k_rows_r2c<L, SRC>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2), st, a);
+  hipLaunchKernelGGL((k_rows_r2c<L, SRC, TILED>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2), st, a);
   return hipGetLastError();
+}
+
+template <int L, int SRC>
+static hipError_t launch_rows_r2c_S(const RowsArgs& a, int batch, hipStream_t st) {
+  return a.tiled ? launch_rows_r2c_L<L, SRC, true>(a, batch, st) : launch_rows_r2c_L<L, SRC, false>(a, batch, st);
 }
 
 hipError_t launch_rows_r2c(int L, int src, const RowsArgs& a, int batch, hipStream_t st) {
   switch (L) {
 #define X(LL)                                                                        \
   case LL:                                                                           \
-    if (src == SRC_NOISE) return launch_rows_r2c_L<LL, SRC_NOISE>(a, batch, st);     \
-    if (src == SRC_F32) return launch_rows_r2c_L<LL, SRC_F32>(a, batch, st);         \
-    return launch_rows_r2c_L<LL, SRC_I8>(a, batch, st);
+    if (src == SRC_NOISE) return launch_rows_r2c_S<LL, SRC_NOISE>(a, batch, st);     \
+    if (src == SRC_F32) return launch_rows_r2c_S<LL, SRC_F32>(a, batch, st);         \
+    return launch_rows_r2c_S<LL, SRC_I8>(a, batch, st);
     HU_ROW_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int L, bool THRESH>
+template <int L, bool THRESH, bool TILED>
 static hipError_t launch_rows_c2r_L(const RowsZArgs& a, int batch, hipStream_t st) {
   constexpr int C = RowTile<L>::C, T = RowTile<L>::T;
   dim3 grid(ceil_div_u(a.nrows, C), batch);
-  hipLaunchKernelGGL((k_rows_c2r<L, THRESH>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2), st, a);
+  hipLaunchKernelGGL((k_rows_c2r<L, THRESH, TILED>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2),
+                     st, a);
   return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_rows_c2r_S(bool thresh, const RowsZArgs& a, int batch, hipStream_t st) {
+  if (a.tiled)
+    return thresh ? launch_rows_c2r_L<L, true, true>(a, batch, st) : launch_rows_c2r_L<L, false, true>(a, batch, st);
+  return thresh ? launch_rows_c2r_L<L, true, false>(a, batch, st) : launch_rows_c2r_L<L, false, false>(a, batch, st);
 }
 
 hipError_t launch_rows_c2r(int L, bool thresh, const RowsZArgs& a, int batch, hipStream_t st) {
   switch (L) {
-#define X(LL)                                                            \
-  case LL:                                                               \
-    return thresh ? launch_rows_c2r_L<LL, true>(a, batch, st)            \
-                  : launch_rows_c2r_L<LL, false>(a, batch, st);
+#define X(LL) case LL: return launch_rows_c2r_S<LL>(thresh, a, batch, st);
     HU_ROW_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;

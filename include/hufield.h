@@ -13,7 +13,8 @@
  * -------------------------------------
  * Grid: hu_dims.n[0] is the slowest axis and n[ndim-1] = n_x the fastest (row-major).  2D is
  *   (n_y, n_x), 3D is (n_z, n_y, n_x).  Each n must be 2^k (4..2048) or 3*2^k (6..768), and n_x/2
- *   must also be one of the supported lengths (so n_x >= 4).
+ *   must also be one of the supported lengths (so n_x >= 4).  A field holds fewer than 2^31
+ *   voxels (in-field offsets are 32-bit), so e.g. 1024^3 is accepted and 2048^3 is not.
  * Wavenumbers: kappa_i = 2 m~_i / n_i in units of the Nyquist wavenumber (m~ the signed index).
  * Noise: voxel i (row-major linear index within a field) takes normal z_{i mod 4} of the
  *   Philox4x32-10 block i // 4 with key (seed lo, seed hi) and counter (block lo, block hi, 0, 0);
@@ -26,20 +27,25 @@
  *   half-spectrum mode counts with multiplicity 2, or 1 where m_x is 0 or n_x/2.
  *
  * Memory: every array argument is DEVICE memory owned by the caller unless marked "host".
- *   The library keeps per-process read-only tables (twiddles, bin edges) that it allocates on
- *   first use of a size; apart from those it never allocates.  Workspace is caller-provided
- *   and its required size comes from hu_workspace_size.
+ *   The library keeps per-process read-only tables (twiddles, bin edges and bin tables) that
+ *   it allocates on first use of a size and keeps until the process ends; hu_pipeline_batch
+ *   also keeps a pinned upload buffer and its cached graphs, and hu_autotune allocates (and
+ *   frees) its own test fields.  Apart from those it never allocates.  Workspace is
+ *   caller-provided and its required size comes from hu_workspace_size(_batch).
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  All work is enqueued
- *   asynchronously; outputs are valid once the stream has been synchronised.  No call
- *   synchronises the stream or reads device memory back to the host.
+ *   asynchronously; outputs are valid once the stream has been synchronised.  The first call
+ *   on a new size waits on the host until its tables are built; hu_pipeline_batch waits for
+ *   its previous upload to have been read.  No call reads device memory back to the host.
  * Errors: every argument is validated on the host before any launch; on error nothing is
  *   enqueued and a negative HU_ERR_* code is returned (hu_strerror names it).  HIP launch
  *   errors are returned as HU_ERR_HIP; errors of earlier asynchronous work surface there too.
  *   A filter with no support on the lattice (max ln chi < -80) cannot be detected on the host
  *   without a pass over the lattice, so it is reported in the stats output (flag = 1) and the
  *   field is then all zeros.
- * Determinism: fields, sign maps and counts are bit-reproducible; FP64 bin sums and the
- *   variance are accumulated with FP64 atomics and may differ in the last bits between runs.
+ * Determinism: fields, sign maps, counts and the statistics (mean and variance come from a
+ *   fixed-order reduction) are bit-reproducible, also across batch sizes and batch layouts;
+ *   the FP64 bin sums are accumulated with FP64 atomics and may differ in the last bits
+ *   between runs.
  */
 #ifndef HUFIELD_H
 #define HUFIELD_H
@@ -134,6 +140,55 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
 int hu_pipeline(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds,
                 hu_bins bins, float near_tol, const hu_outputs* out, void* work, size_t work_bytes,
                 void* stream);
+
+/* One field of a heterogeneous batch: its own grid, filter, seed, bins and outputs (device
+ * pointers, each may be NULL; at least one must be set; bins are used when cont_sum or pm1_sum is
+ * set).  Array sizes as in hu_outputs for a batch of one. */
+typedef struct hu_job {
+  hu_dims dims;
+  hu_filter filt;
+  uint64_t seed;
+  hu_bins bins;
+  float* field;
+  int8_t* pm1;
+  double* stats;
+  uint64_t* counts;
+  double* cont_sum;
+  uint64_t* cont_cnt;
+  double* pm1_sum;
+  uint64_t* pm1_cnt;
+} hu_job;
+
+/* Workspace bytes for hu_pipeline_batch on `jobs` (host array). */
+int hu_workspace_size_batch(const hu_job* jobs, int32_t njobs, size_t* bytes);
+
+/* The whole hot path (as hu_pipeline) for a heterogeneous batch of fields of uneven grids and
+ * parameters, in one submission: the jobs are grouped by grid and bin layout, each group runs
+ * the pass sequence with per-field parameters read from a table in the workspace, and the
+ * groups run side by side from one captured HIP graph that is cached and replayed for later
+ * batches of the same structure on the same workspace.
+ *   jobs, status: host arrays of njobs; status[i] receives job i's validation result (an
+ *   invalid job is skipped, the others run).  Returns HU_OK when the valid jobs were enqueued.
+ * The first call for a structure captures and instantiates the graph (and builds any missing
+ * per-size tables, synchronising the stream); later calls only upload the parameter table
+ * (from a pinned staging buffer) and launch the graph.  Calls sharing one workspace must be
+ * ordered on one stream. */
+int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t* status, void* work,
+                      size_t work_bytes, void* stream);
+
+/* Tile-width autotuner.  Times every kernel family of the pipeline (rows_r2c, cols_y, cols_filter,
+ * rows_c2r, cols_bin) in both variants (default tile width, half width) on a synthetic batch of
+ * `batch` fields of `dims` with `bins`, keeps the faster variant per family for this shape class
+ * (grid, bins, batch size bucket), and, if cache_path is non-NULL, writes all tuned plans as JSON
+ * there (read back at start-up from $HUFIELD_TUNE_CACHE).  ms_out (host, optional) receives the
+ * 2 x 5 mean launch times in ms.  Allocates and frees its own device buffers and synchronises. */
+int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* cache_path, double* ms_out);
+
+/* The tile variants (5 entries, 0 or 1, order as above) that calls on this shape class use. */
+int hu_plan_query(hu_dims dims, int32_t batch, const hu_bins* bins, int32_t* variants);
+
+/* Set the tile variants for a shape class by hand (host array of 5 entries, each 0 or 1). */
+int hu_plan_set(hu_dims dims, int32_t batch, const hu_bins* bins, const int32_t* variants);
 
 const char* hu_strerror(int code);
 

@@ -10,10 +10,10 @@
 
 namespace hu {
 
-template <int L>
-__global__ void __launch_bounds__(ColTile<L>::T) k_cols_bin(BinArgs a) {
-  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L>::C, T = ColTile<L>::T;
-  constexpr int LP = ColTile<L>::LP;
+template <int L, int V>
+__global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
+  constexpr int LP = ColTile<L, V>::LP;
   using Rad = typename Plan<L>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
   extern __shared__ float2 lds[];
@@ -43,20 +43,20 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_bin(BinArgs a) {
   __syncthreads();
   if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, a.bd, a.gm, g, p);
   __syncthreads();
-  hist_flush(hs, a.nb, 1.0 / (double)a.N, a.sum + (long long)b * a.nb, tid, T);
+  double* out = a.io ? a.io[b].pm1_sum : field_ptr(a.sum, a.nb, b);
+  if (out) hist_flush(hs, a.nb, 1.0 / (double)a.N, out, tid, T);
 }
 
-template <int L>
+template <int L, int V>
 static hipError_t launch_cols_bin_L(const BinArgs& a, hipStream_t st) {
-  constexpr int T = ColTile<L>::T;
-  hipLaunchKernelGGL((k_cols_bin<L>), dim3(sched_blocks(a.sc)), dim3(T), col_lds_bytes_t<L>(a.nb), st, a);
+  constexpr int T = ColTile<L, V>::T;
+  hipLaunchKernelGGL((k_cols_bin<L, V>), dim3(sched_blocks(a.sc)), dim3(T), (col_lds_bytes_t<L, V>(a.nb)), st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_cols_bin(int L, const BinArgs& a, int batch, hipStream_t st) {
-  (void)batch;
+hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st) {
   switch (L) {
-#define X(LL) case LL: return launch_cols_bin_L<LL>(a, st);
+#define X(LL) case LL: return variant ? launch_cols_bin_L<LL, 1>(a, st) : launch_cols_bin_L<LL, 0>(a, st);
     HU_COL_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;

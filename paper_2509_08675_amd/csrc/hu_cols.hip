@@ -5,9 +5,9 @@
 
 namespace hu {
 
-template <int L, bool INV>
-__global__ void __launch_bounds__(ColTile<L>::T) k_cols(ColsArgs a) {
-  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L>::C;
+template <int L, bool INV, int V>
+__global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols(ColsArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C;
   using Rad = typename Plan<L>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
   extern __shared__ float2 lds[];
@@ -32,12 +32,11 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols(ColsArgs a) {
   }
 }
 
-template <int L>
+template <int L, int V>
 static ColSched col_sched_L(long long ncol, int batch) {
-  constexpr int C = ColTile<L>::C;
+  constexpr int C = ColTile<L, V>::C;
   ColSched s;
   s.ntiles = (int)((ncol + C - 1) / C);
-  // tiles narrower than a 128-byte line (16 complex) share lines with their neighbours
   // one workgroup per tile (every layout gives each tile whole 128-byte line runs); the
   // same-XCD grouping of neighbouring tiles is kept for G > 1
   s.G = 1;
@@ -46,29 +45,31 @@ static ColSched col_sched_L(long long ncol, int batch) {
   return s;
 }
 
-ColSched col_sched(int L, long long ncol, int batch) {
+ColSched col_sched(int L, int variant, long long ncol, int batch) {
   switch (L) {
-#define X(LL) case LL: return col_sched_L<LL>(ncol, batch);
+#define X(LL) \
+  case LL: return variant ? col_sched_L<LL, 1>(ncol, batch) : col_sched_L<LL, 0>(ncol, batch);
     HU_COL_LENGTHS(X)
 #undef X
     default: return ColSched{0, 0, 1, 0};
   }
 }
 
-int col_tiles(int L, long long ncol) { return col_sched(L, ncol, 1).ntiles; }
+int col_tiles(int L, int variant, long long ncol) { return col_sched(L, variant, ncol, 1).ntiles; }
 
-template <int L, bool INV>
+template <int L, bool INV, int V>
 static hipError_t launch_cols_L(const ColsArgs& a, hipStream_t st) {
-  constexpr int C = ColTile<L>::C, T = ColTile<L>::T;
-  hipLaunchKernelGGL((k_cols<L, INV>), dim3(sched_blocks(a.sc)), dim3(T), col_xchg_bytes<L>(), st, a);
+  constexpr int T = ColTile<L, V>::T;
+  hipLaunchKernelGGL((k_cols<L, INV, V>), dim3(sched_blocks(a.sc)), dim3(T), (col_xchg_bytes<L, V>()), st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_cols(int L, bool inv, const ColsArgs& a, int batch, hipStream_t st) {
-  (void)batch;
+hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st) {
   switch (L) {
-#define X(LL) \
-  case LL: return inv ? launch_cols_L<LL, true>(a, st) : launch_cols_L<LL, false>(a, st);
+#define X(LL)                                                                                    \
+  case LL:                                                                                       \
+    if (variant) return inv ? launch_cols_L<LL, true, 1>(a, st) : launch_cols_L<LL, false, 1>(a, st); \
+    return inv ? launch_cols_L<LL, true, 0>(a, st) : launch_cols_L<LL, false, 0>(a, st);
     HU_COL_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -14,22 +14,31 @@ namespace hu {
 // ---------------------------------------------------------------------------------------------
 // tile widths: transforms per workgroup
 // ---------------------------------------------------------------------------------------------
-template <int L>
+// V = 0: the default width; V = 1: half of it (more, smaller workgroups), for the autotuner.
+template <int L, int V = 0>
 struct RowTile {
   static constexpr int P = Plan<L>::P;
   static constexpr int c0 = 256 / P > 0 ? 256 / P : 1;
   static constexpr int cl = 8192 / Region<L>::value > 0 ? 8192 / Region<L>::value : 1;
-  static constexpr int C = c0 < cl ? c0 : cl;
+  static constexpr int cd0 = c0 < cl ? c0 : cl;
+  static constexpr int m = 64 / (P < 64 ? P : 64);       // C multiple of m: whole waves
+  static constexpr int cd = cd0 / m * m > 0 ? cd0 / m * m : m;
+  static constexpr int C = V == 0 ? cd : (cd / 2 / m * m >= m ? cd / 2 / m * m : cd);
   static constexpr int T = C * P;
+  static_assert(T % 64 == 0, "row tiles are whole waves");
 };
 
-template <int L>
+template <int L, int V = 0>
 struct ColTile {
   static constexpr int P = Plan<L>::P;
   static constexpr int a = 8192 / L < 32 ? 8192 / L : 32;   // 64 KB of exchange buffer (unpadded)
   static constexpr int b = 64 / P > a ? 64 / P : a;
-  static constexpr int C = b * P > 1024 ? 1024 / P : b;
+  static constexpr int cd0 = b * P > 1024 ? 1024 / P : b;
+  static constexpr int m = 64 / (P < 64 ? P : 64);       // C multiple of m: whole waves
+  static constexpr int cd = cd0 / m * m > 0 ? cd0 / m * m : m;
+  static constexpr int C = V == 0 ? cd : (cd / 2 / m * m >= m ? cd / 2 / m * m : cd);
   static constexpr int T = C * P;
+  static_assert(T % 64 == 0, "column tiles are whole waves");
   // padded power-value layout for run-length binning: 4 floats after every 16
   static constexpr int LP = L + (L / 16) * 4 + 4;
 };
@@ -226,17 +235,24 @@ __device__ __forceinline__ void hist_flush(const double* hs, int nb, double scal
   }
 }
 
-template <int L>
+template <int L, int V>
 __host__ __device__ constexpr size_t col_xchg_bytes() {
-  return (size_t)ColTile<L>::C * Region<L>::value * 8;
+  return (size_t)ColTile<L, V>::C * Region<L>::value * 8;
 }
 
-template <int L>
+template <int L, int V>
 __host__ __device__ constexpr size_t col_lds_bytes_t(int nb) {
   // exchange buffer, or the padded power values plus the FP64 histogram
-  return col_xchg_bytes<L>() > (size_t)ColTile<L>::C * ColTile<L>::LP * 4 + (size_t)nb * 8 + 8
-             ? col_xchg_bytes<L>()
-             : (size_t)ColTile<L>::C * ColTile<L>::LP * 4 + (size_t)nb * 8 + 8;
+  return col_xchg_bytes<L, V>() > (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4 + (size_t)nb * 8 + 8
+             ? col_xchg_bytes<L, V>()
+             : (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4 + (size_t)nb * 8 + 8;
+}
+
+// per-field parameter and output accessors: the batch table when present, else the uniform
+// arguments (base pointer + field * stride)
+template <class T>
+__device__ __forceinline__ T* field_ptr(T* base, long long stride, int b) {
+  return base ? base + (long long)b * stride : nullptr;
 }
 
 }  // namespace hu

@@ -8,10 +8,10 @@
 
 namespace hu {
 
-template <int L, int NDIM>
-__global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
-  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L>::C, T = ColTile<L>::T;
-  constexpr int LP = ColTile<L>::LP;
+template <int L, int NDIM, int V>
+__global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
+  constexpr int LP = ColTile<L, V>::LP;
   using Rad = typename Plan<L>::fwd;
   using RadI = Reverse<Rad>;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
@@ -35,7 +35,9 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
   fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
 
   // ---- filter and per-thread statistics
-  const bool do_bins = a.cont_sum != nullptr;
+  double* cont_out = a.io ? a.io[b].cont_sum : field_ptr(a.cont_sum, a.nb, b);
+  const bool do_bins = a.want_bins && cont_out != nullptr;
+  const FiltDev filt = a.io ? a.io[b].filt : a.filt;
   const ColCoord cc = col_coord(a.gm, valid ? g : 0);
   double gsum = 0.0, f0 = 0.0;
   float lmax = -1.0e30f;
@@ -44,7 +46,7 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
   for (int s = 0; s < E; ++s) {
     const int e = slot_index<L, RL, P>(s, p);
     float lnc;
-    const float H = amp_sym<NDIM>(a.filt, a.gm, cc, e, lnc);
+    const float H = amp_sym<NDIM>(filt, a.gm, cc, e, lnc);
     const float2 F = cscale(v[s], H);
     v[s] = F;
     const float m2 = cc.wm * (F.x * F.x + F.y * F.y);
@@ -66,7 +68,7 @@ __global__ void __launch_bounds__(ColTile<L>::T) k_cols_filter(FilterArgs a) {
     __syncthreads();
     if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, a.bd, a.gm, g, p);
     __syncthreads();
-    hist_flush(hs, a.nb, 1.0, a.cont_sum + (long long)b * a.nb, tid, T);
+    hist_flush(hs, a.nb, 1.0, cont_out, tid, T);
   }
   // ---- workgroup statistics -> partials[b][tile] (reduced by k_finalize after this kernel)
   gsum = wave_sum(gsum);
@@ -104,6 +106,9 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
   __shared__ double fac;
   const int b = blockIdx.x, tid = threadIdx.x;
   const double* part = a.partials + (long long)b * a.ntiles * 4;
+  const double sigma_f = a.io ? a.io[b].sigma_f : a.sigma_f;
+  double* stats_out = a.io ? a.io[b].stats : field_ptr(a.stats, 4, b);
+  double* cont_out = a.io ? a.io[b].cont_sum : field_ptr(a.cont_sum, a.nb, b);
   double G = 0.0, F0 = 0.0;
   float lm = -1.0e30f;
   for (int w = tid; w < a.ntiles; w += 256) {
@@ -136,20 +141,18 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
     fs[1] = var;
     fs[2] = lmx;
     fs[3] = degenerate ? 1.0 : 0.0;
-    fs[4] = degenerate ? 0.0 : a.sigma_f / (N * sd);              // scale of the unnormalised inverse
-    fs[5] = degenerate ? 0.0 : -a.sigma_f * mu / sd;               // offset
-    fs[6] = degenerate ? 0.0 : a.sigma_f * a.sigma_f / (N * var);  // continuous-spectrum factor
+    fs[4] = degenerate ? 0.0 : sigma_f / (N * sd);             // scale of the unnormalised inverse
+    fs[5] = degenerate ? 0.0 : -sigma_f * mu / sd;              // offset
+    fs[6] = degenerate ? 0.0 : sigma_f * sigma_f / (N * var);   // continuous-spectrum factor
     fs[7] = Gt;
-    if (a.stats) {
-      double* st = a.stats + (long long)b * 4;
-      st[0] = mu; st[1] = var; st[2] = lmx; st[3] = fs[3];
+    if (stats_out) {
+      stats_out[0] = mu; stats_out[1] = var; stats_out[2] = lmx; stats_out[3] = fs[3];
     }
     fac = fs[6];
   }
   __syncthreads();
-  if (a.cont_sum) {
-    double* cs = a.cont_sum + (long long)b * a.nb;
-    for (int i = tid; i < a.nb; i += 256) cs[i] *= fac;
+  if (cont_out) {
+    for (int i = tid; i < a.nb; i += 256) cont_out[i] *= fac;
   }
 }
 
@@ -158,21 +161,21 @@ hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int L>
+template <int L, int V>
 static hipError_t launch_cols_filter_L(const FilterArgs& a, hipStream_t st) {
-  constexpr int T = ColTile<L>::T;
-  const size_t lds = a.cont_sum ? col_lds_bytes_t<L>(a.nb) : col_xchg_bytes<L>();
+  constexpr int T = ColTile<L, V>::T;
+  const size_t lds = a.want_bins ? col_lds_bytes_t<L, V>(a.nb) : col_xchg_bytes<L, V>();
   if (a.gm.ndim == 2)
-    hipLaunchKernelGGL((k_cols_filter<L, 2>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+    hipLaunchKernelGGL((k_cols_filter<L, 2, V>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
   else
-    hipLaunchKernelGGL((k_cols_filter<L, 3>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+    hipLaunchKernelGGL((k_cols_filter<L, 3, V>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_cols_filter(int L, const FilterArgs& a, int batch, hipStream_t st) {
-  (void)batch;
+hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st) {
   switch (L) {
-#define X(LL) case LL: return launch_cols_filter_L<LL>(a, st);
+#define X(LL) \
+  case LL: return variant ? launch_cols_filter_L<LL, 1>(a, st) : launch_cols_filter_L<LL, 0>(a, st);
     HU_COL_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -1,0 +1,551 @@
+// Host-side implementation shared by the C-ABI entry points (see hu_host.hpp).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <utility>
+
+#include "hu_host.hpp"
+
+namespace hu {
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, float2*> g_tw, g_tw2;
+std::map<std::pair<int, int>, double*> g_edges;
+std::map<std::vector<long long>, BinGeo> g_bingeo;
+
+int current_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+
+// FP64 twiddles rounded once to FP32: tw[t] = exp(-2 pi i t / n) for t < count
+int make_table(int n, int count, float2** out) {
+  std::vector<float2> h(count);
+  for (int t = 0; t < count; ++t) {
+    const double a = 2.0 * M_PI * (double)t / (double)n;
+    h[t] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  float2* d = nullptr;
+  if (hipMalloc(&d, sizeof(float2) * count) != hipSuccess) return HU_ERR_HIP;
+  if (hipMemcpy(d, h.data(), sizeof(float2) * count, hipMemcpyHostToDevice) != hipSuccess) return HU_ERR_HIP;
+  *out = d;
+  return HU_OK;
+}
+
+int get_edges(int na, const double** ex, const double** ey) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int m = na > 1 ? na - 1 : 1;
+  auto key = std::make_pair(current_device(), na);
+  auto it = g_edges.find(key);
+  if (it == g_edges.end()) {
+    // e_j = (cos j pi / A, sin j pi / A), j = 1..A-1; the 45, 90 and 135 degree edges exact
+    std::vector<double> h(2 * m, 0.0);
+    const double c = std::cos(M_PI / 4.0);
+    for (int j = 1; j < na; ++j) {
+      double x, y;
+      if (4 * j == na) { x = c; y = c; }
+      else if (2 * j == na) { x = 0.0; y = 1.0; }
+      else if (4 * j == 3 * na) { x = -c; y = c; }
+      else { x = std::cos(j * M_PI / na); y = std::sin(j * M_PI / na); }
+      h[j - 1] = x;
+      h[m + j - 1] = y;
+    }
+    double* d = nullptr;
+    if (hipMalloc(&d, sizeof(double) * 2 * m) != hipSuccess) return HU_ERR_HIP;
+    if (hipMemcpy(d, h.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice) != hipSuccess) return HU_ERR_HIP;
+    it = g_edges.emplace(key, d).first;
+  }
+  *ex = it->second;
+  *ey = it->second + m;
+  return HU_OK;
+}
+
+bool supported_len(long long n) {
+  if (n < 4 || n > 2048) return false;
+  long long m = n;
+  if (m % 3 == 0) {
+    m /= 3;
+    if (n > 768) return false;
+  }
+  return (m & (m - 1)) == 0;
+}
+
+bool supported_row_len(long long L) {
+  if (L < 2 || L > 1024) return false;
+  long long m = L;
+  if (m % 3 == 0) {
+    m /= 3;
+    if (L > 384) return false;
+  }
+  return (m & (m - 1)) == 0;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+long long lcm_ll(long long a, long long b) { return a / std::gcd(a, b) * b; }
+
+// ---- tuned plans
+std::map<std::string, TunePlan> g_plans;
+bool g_plans_loaded = false;
+
+void load_plans_locked() {
+  if (g_plans_loaded) return;
+  g_plans_loaded = true;
+  const char* path = std::getenv("HUFIELD_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  std::string s;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+  std::fclose(f);
+  // entries look like  "key": [v0, v1, v2, v3, v4]
+  size_t pos = 0;
+  while ((pos = s.find("\": [", pos)) != std::string::npos) {
+    const size_t q = s.rfind('"', pos - 1);
+    if (q == std::string::npos) break;
+    const std::string key = s.substr(q + 1, pos - q - 1);
+    TunePlan p{};
+    const char* c = s.c_str() + pos + 4;
+    if (std::sscanf(c, "%d, %d, %d, %d, %d", &p.v[0], &p.v[1], &p.v[2], &p.v[3], &p.v[4]) == 5) {
+      for (int i = 0; i < NPASS; ++i) p.v[i] = p.v[i] ? 1 : 0;
+      g_plans[key] = p;
+    }
+    pos += 4;
+  }
+}
+
+// ---- profiling
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+size_t g_pool_next = 0;
+
+hipEvent_t pool_event() {
+  if (g_pool_next == g_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_pool.push_back(e);
+  }
+  return g_pool[g_pool_next++];
+}
+
+}  // namespace
+
+bool g_prof = false;
+
+hipError_t timed_impl(const char* name, hipStream_t st, hipError_t (*fn)(void*), void* ctx) {
+  hipEvent_t a = pool_event(), b = pool_event();
+  if (!a || !b) return fn(ctx);
+  (void)hipEventRecord(a, st);
+  hipError_t e = fn(ctx);
+  (void)hipEventRecord(b, st);
+  g_recs.push_back({name, a, b});
+  return e;
+}
+
+int profile_reset(bool on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof = on;
+  g_recs.clear();
+  g_pool_next = 0;
+  while (on && g_pool.size() < 2048) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return HU_ERR_HIP;
+    g_pool.push_back(e);
+  }
+  return HU_OK;
+}
+
+int profile_collect(std::vector<std::string>& names, std::vector<long long>& launches, std::vector<double>& ms) {
+  names.clear();
+  launches.clear();
+  ms.clear();
+  for (const ProfRec& r : g_recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return HU_ERR_HIP;
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return HU_ERR_HIP;
+    size_t i = 0;
+    while (i < names.size() && names[i] != r.name) ++i;
+    if (i == names.size()) {
+      names.push_back(r.name);
+      launches.push_back(0);
+      ms.push_back(0.0);
+    }
+    launches[i] += 1;
+    ms[i] += t;
+  }
+  return HU_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+int get_tw(int L, const float2** tw) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(current_device(), L);
+  auto it = g_tw.find(key);
+  if (it == g_tw.end()) {
+    float2* d;
+    int rc = make_table(L, L, &d);
+    if (rc) return rc;
+    it = g_tw.emplace(key, d).first;
+  }
+  *tw = it->second;
+  return HU_OK;
+}
+
+int get_tw2(int L, const float2** tw2) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(current_device(), L);
+  auto it = g_tw2.find(key);
+  if (it == g_tw2.end()) {
+    float2* d;
+    int rc = make_table(2 * L, L, &d);
+    if (rc) return rc;
+    it = g_tw2.emplace(key, d).first;
+  }
+  *tw2 = it->second;
+  return HU_OK;
+}
+
+int make_geom(const hu_dims& d, Geom* g) {
+  if (d.ndim != 2 && d.ndim != 3) return HU_ERR_ARG;
+  g->nd = d.ndim;
+  g->N = 1;
+  g->D = 1;
+  g->n[2] = 0;
+  for (int i = 0; i < d.ndim; ++i) {
+    if (!supported_len(d.n[i])) return HU_ERR_SIZE;
+    g->n[i] = d.n[i];
+    g->N *= d.n[i];
+    g->D = lcm_ll(g->D, d.n[i]);
+  }
+  g->nx = d.n[d.ndim - 1];
+  if (!supported_row_len(g->nx / 2)) return HU_ERR_SIZE;
+  g->nxh = g->nx / 2 + 1;
+  g->nrows = g->N / g->nx;
+  g->Nh = g->nrows * g->nxh;
+  g->tiled = d.ndim == 2 ? 1 : 0;
+  g->Nhp = g->tiled ? g->nrows * ((g->nxh + 3) / 4 * 4) : g->Nh;
+  if (g->N >= (1LL << 31)) return HU_ERR_SIZE;      // in-field offsets are 32-bit
+  return HU_OK;
+}
+
+int check_filter(const hu_filter* f, int nd) {
+  if (!f) return HU_ERR_ARG;
+  if (!finite_pos(f->p) || !finite_pos(f->semi[0]) || !finite_pos(f->semi[1])) return HU_ERR_ARG;
+  if (nd == 3 && !finite_pos(f->semi[2])) return HU_ERR_ARG;
+  if (!finite_pos(f->alpha) || !finite_pos(f->width) || !finite_pos(f->sigma_f)) return HU_ERR_ARG;
+  if (!std::isfinite(f->rot) || !std::isfinite(f->k0) || f->k0 < 0.0) return HU_ERR_ARG;
+  return HU_OK;
+}
+
+int check_bins(const hu_bins* b, int nd) {
+  if (!b) return HU_ERR_ARG;
+  if (b->n_radial < 1 || b->n_angular < 1) return HU_ERR_ARG;
+  if (b->n_angular > 1 && nd != 2) return HU_ERR_ARG;
+  if ((long long)b->n_radial * b->n_angular + 1 > 8192) return HU_ERR_ARG;
+  return HU_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan) {
+  Layout L{};
+  size_t off = 0;
+  L.spec = off;
+  off += up256((size_t)batch * g.Nhp * sizeof(float2));
+  L.tiles = col_tiles(g.n[0], plan.v[P_FILTER], g.Nh / g.n[0]);
+  if (need_stats) {
+    L.partials = off;
+    off += up256((size_t)batch * L.tiles * 4 * sizeof(double));
+    L.fstats = off;
+    off += up256((size_t)batch * 8 * sizeof(double));
+  }
+  L.total = off;
+  return L;
+}
+
+FiltDev filt_dev(const hu_filter& f) {
+  FiltDev d{};
+  d.cr = (float)std::cos(f.rot);
+  d.sr = (float)std::sin(f.rot);
+  d.ia = (float)(1.0 / f.semi[0]);
+  d.ib = (float)(1.0 / f.semi[1]);
+  d.ic = (float)(1.0 / f.semi[2]);
+  d.p = (float)f.p;
+  d.ip = (float)(1.0 / f.p);
+  d.alpha = (float)f.alpha;
+  d.k0 = (float)f.k0;
+  d.inv2w2 = (float)(1.0 / (2.0 * f.width * f.width));
+  // ln chi at the continuum peak K* = (k0 + sqrt(k0^2 + 4 alpha w^2)) / 2, in FP64
+  const double ks = 0.5 * (f.k0 + std::sqrt(f.k0 * f.k0 + 4.0 * f.alpha * f.width * f.width));
+  const double dd = ks - f.k0;
+  d.lnchimax = (float)(f.alpha * std::log(ks) - dd * dd / (2.0 * f.width * f.width));
+  d.rotated = (f.rot != 0.0) ? 1 : 0;
+  return d;
+}
+
+Axis0Geom axis0(const Geom& g) {
+  Axis0Geom a{};
+  a.ndim = g.nd;
+  a.n0 = g.n[0];
+  a.ny = g.nd == 3 ? g.n[1] : 0;
+  a.nx = g.nx;
+  a.nxh = g.nxh;
+  a.ncol = (int)(g.Nh / g.n[0]);
+  a.inner0 = g.tiled ? 4 : a.ncol;
+  a.kap0 = (float)(2.0 / g.n[0]);
+  a.kapy = g.nd == 3 ? (float)(2.0 / g.n[1]) : 0.0f;
+  a.kapx = (float)(2.0 / g.nx);
+  a.dfac_0 = g.D / g.n[0];
+  a.dfac_y = g.nd == 3 ? g.D / g.n[1] : 0;
+  a.dfac_x = g.D / g.nx;
+  return a;
+}
+
+int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd) {
+  bd->nr = b.n_radial;
+  bd->na = b.n_angular;
+  bd->D2 = g.D * g.D;
+  bd->invD2 = (float)(1.0 / (double)(g.D * g.D));
+  bd->fourR2 = 4LL * b.n_radial * b.n_radial;
+  return get_edges(b.n_angular, &bd->ex, &bd->ey);
+}
+
+int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t st, BinGeo* out) {
+  std::vector<long long> key = {current_device(), g.nd, g.n[0], g.n[1], g.n[2], bins.n_radial, bins.n_angular};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_bingeo.find(key);
+    if (it != g_bingeo.end()) {
+      *out = it->second;
+      return HU_OK;
+    }
+  }
+  const int nb = bins.n_radial * bins.n_angular + 1;
+  BinGeo geo{nullptr, nullptr};
+  HU_HIP(hipMalloc(&geo.counts, sizeof(unsigned long long) * nb));
+  if ((size_t)g.Nh * sizeof(uint16_t) <= ((size_t)64 << 20)) HU_HIP(hipMalloc(&geo.table, sizeof(uint16_t) * g.Nh));
+  HU_HIP(launch_zero_u64(reinterpret_cast<uint64_t*>(geo.counts), nb, st));
+  BinGeomArgs ba{};
+  ba.Nh = g.Nh;
+  ba.gm = axis0(g);
+  ba.bd = bd;
+  ba.nb = nb;
+  ba.table = geo.table;
+  ba.counts = geo.counts;
+  HU_HIP(launch_bin_geom(ba, st));
+  HU_HIP(hipStreamSynchronize(st));          // complete before any stream can use it
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_bingeo.find(key);
+  if (it != g_bingeo.end()) {                // another thread built it meanwhile
+    (void)hipFree(geo.counts);
+    if (geo.table) (void)hipFree(geo.table);
+    *out = it->second;
+    return HU_OK;
+  }
+  g_bingeo.emplace(key, geo);
+  *out = geo;
+  return HU_OK;
+}
+
+// every table a class needs, created before any launch (and before a graph capture)
+int prepare_tables(const Geom& g, const hu_bins* bins, hipStream_t st) {
+  const float2 *a, *b;
+  HU_TRY(get_tw(g.nx / 2, &a));
+  HU_TRY(get_tw2(g.nx / 2, &b));
+  HU_TRY(get_tw(g.n[0], &a));
+  if (g.nd == 3) HU_TRY(get_tw(g.n[1], &a));
+  if (bins) {
+    BinDev bd{};
+    BinGeo geo;
+    HU_TRY(make_bindev(g, *bins, &bd));
+    HU_TRY(get_bingeo(g, *bins, bd, st, &geo));
+  }
+  return HU_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+std::string plan_key(const Geom& g, const hu_bins* bins, int batch) {
+  const int bucket = batch < 2 ? 1 : batch < 8 ? 2 : batch < 32 ? 8 : 32;
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "gfx950|%dx%dx%d|nb%d|b%d", g.n[0], g.n[1], g.nd == 3 ? g.n[2] : 1,
+                bins ? bins->n_radial * bins->n_angular + 1 : 0, bucket);
+  return buf;
+}
+
+TunePlan get_plan(const Geom& g, const hu_bins* bins, int batch) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_plans_locked();
+  auto it = g_plans.find(plan_key(g, bins, batch));
+  if (it != g_plans.end()) return it->second;
+  return TunePlan{{0, 0, 0, 0, 0}};
+}
+
+void set_plan(const std::string& key, const TunePlan& p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  load_plans_locked();
+  g_plans[key] = p;
+}
+
+int save_plans(const char* path) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return HU_ERR_ARG;
+  std::fprintf(f, "{\n  \"format\": \"hufield tile-variant plans: [rows_r2c, cols_y, cols_filter, rows_c2r, cols_bin]\",\n"
+                  "  \"plans\": {\n");
+  size_t i = 0;
+  for (const auto& kv : g_plans) {
+    const TunePlan& p = kv.second;
+    std::fprintf(f, "    \"%s\": [%d, %d, %d, %d, %d]%s\n", kv.first.c_str(), p.v[0], p.v[1], p.v[2], p.v[3], p.v[4],
+                 ++i < g_plans.size() ? "," : "");
+  }
+  std::fprintf(f, "  }\n}\n");
+  std::fclose(f);
+  return HU_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+int enqueue_class(const ClassRun& r, hipStream_t st) {
+  const Geom& g = r.g;
+  const int B = r.B;
+  const bool batch_mode = r.io != nullptr;
+  const hu_outputs& o = r.out;
+  const int Lrow = g.nx / 2;
+  const float2 *tw_row, *tw2_row, *tw_0, *tw_1 = nullptr;
+  HU_TRY(get_tw(Lrow, &tw_row));
+  HU_TRY(get_tw2(Lrow, &tw2_row));
+  HU_TRY(get_tw(g.n[0], &tw_0));
+  if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
+  const int nb = r.bins ? r.bins->n_radial * r.bins->n_angular + 1 : 0;
+  BinDev bd{};
+  BinGeo geo{nullptr, nullptr};
+  if (r.bins) {
+    HU_TRY(make_bindev(g, *r.bins, &bd));
+    HU_TRY(get_bingeo(g, *r.bins, bd, st, &geo));
+  }
+  const bool want_cont = batch_mode ? (r.want_cont && r.bins) : (o.cont_sum != nullptr);
+  const bool want_pm1 = r.thresh && (batch_mode ? (r.want_pm1_spec && r.bins) : (o.pm1_sum != nullptr));
+
+  float2* spec = reinterpret_cast<float2*>(r.work + r.lay.spec);
+  double* partials = reinterpret_cast<double*>(r.work + r.lay.partials);
+  double* fstats = reinterpret_cast<double*>(r.work + r.lay.fstats);
+  const uint32_t* cnt_src = reinterpret_cast<const uint32_t*>(geo.counts);
+
+  // pass A: noise -> R2C rows; block 0 of each field sets up that field's accumulators
+  RowsArgs ra{};
+  ra.spec = spec;
+  ra.Nh = g.Nhp;
+  ra.tiled = g.tiled;
+  ra.N = g.N;
+  ra.nrows = g.nrows;
+  ra.tw = tw_row;
+  ra.tw2 = tw2_row;
+  ra.io = r.io;
+  ra.nb = nb;
+  ra.cnt_src = cnt_src;
+  if (!batch_mode) {
+    for (int i = 0; i < B; ++i) ra.seeds[i] = r.seeds[i];
+    int fs = 0;
+    if (o.cont_sum) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.cont_sum), nullptr, 2 * nb};
+    if (o.cont_cnt) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.cont_cnt), cnt_src, 2 * nb};
+    if (o.pm1_sum) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_sum), nullptr, 2 * nb};
+    if (o.pm1_cnt) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_cnt), cnt_src, 2 * nb};
+    if (o.counts) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.counts), nullptr, 4};
+    ra.fill_spans = fs;
+  }
+  HU_HIP(timed("rows_r2c_noise", st, [&] { return launch_rows_r2c(Lrow, SRC_NOISE, r.plan.v[P_R2C], ra, B, st); }));
+
+  ColsArgs cy{};
+  if (g.nd == 3) {
+    cy.spec = spec;
+    cy.Nh = g.Nhp;
+    cy.ncol = g.n[0] * g.nxh;
+    cy.inner = g.nxh;
+    cy.tw = tw_1;
+    cy.sc = col_sched(g.n[1], r.plan.v[P_COLY], cy.ncol, B);
+    HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st); }));
+  }
+
+  FilterArgs fa{};
+  fa.spec = spec;
+  fa.Nh = g.Nhp;
+  fa.N = g.N;
+  fa.gm = axis0(g);
+  fa.sc = col_sched(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B);
+  if (!batch_mode) fa.filt = filt_dev(r.filt);
+  fa.io = r.io;
+  fa.bd = bd;
+  fa.nb = nb;
+  fa.table = geo.table;
+  fa.tw = tw_0;
+  fa.partials = partials;
+  fa.cont_sum = batch_mode ? nullptr : o.cont_sum;
+  fa.want_bins = want_cont ? 1 : 0;
+  HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], r.plan.v[P_FILTER], fa, st); }));
+  FinalizeArgs fz{};
+  fz.partials = partials;
+  fz.ntiles = fa.sc.ntiles;
+  fz.N = g.N;
+  fz.sigma_f = batch_mode ? 1.0 : r.filt.sigma_f;
+  fz.fstats = fstats;
+  fz.stats = batch_mode ? nullptr : o.stats;
+  fz.cont_sum = batch_mode ? nullptr : o.cont_sum;
+  fz.nb = nb;
+  fz.io = r.io;
+  HU_HIP(timed("finalize", st, [&] { return launch_finalize(fz, B, st); }));
+
+  if (g.nd == 3) HU_HIP(timed("cols_y_inv", st, [&] { return launch_cols(g.n[1], true, r.plan.v[P_COLY], cy, st); }));
+
+  RowsZArgs za{};
+  za.spec = spec;
+  za.Nh = g.Nhp;
+  za.tiled = g.tiled;
+  za.N = g.N;
+  za.nrows = g.nrows;
+  za.tw = tw_row;
+  za.tw2 = tw2_row;
+  za.fstats = fstats;
+  za.io = r.io;
+  if (!batch_mode) {
+    za.field = o.field;
+    za.pm1 = o.pm1;
+    za.counts = o.counts;
+    za.near_tol = r.near_abs;
+  }
+  HU_HIP(timed(r.thresh ? "rows_c2r_thresh" : "rows_c2r", st,
+               [&] { return launch_rows_c2r(Lrow, r.thresh, r.plan.v[P_C2R], za, B, st); }));
+
+  if (want_pm1) {
+    if (g.nd == 3) HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st); }));
+    BinArgs ba{};
+    ba.spec = spec;
+    ba.Nh = g.Nhp;
+    ba.N = g.N;
+    ba.gm = axis0(g);
+    ba.sc = col_sched(g.n[0], r.plan.v[P_BIN], ba.gm.ncol, B);
+    ba.bd = bd;
+    ba.nb = nb;
+    ba.table = geo.table;
+    ba.tw = tw_0;
+    ba.sum = batch_mode ? nullptr : o.pm1_sum;
+    ba.io = r.io;
+    HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], r.plan.v[P_BIN], ba, st); }));
+  }
+  return HU_OK;
+}
+
+}  // namespace hu

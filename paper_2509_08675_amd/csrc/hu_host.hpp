@@ -1,0 +1,108 @@
+// Host-side pieces shared by the C-ABI entry points: geometry and validation, per-size tables,
+// workspace layouts, tuned plans, kernel timing, and the pass sequence of one class of
+// same-shape fields.
+#pragma once
+
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "hufield.h"
+#include "hu_internal.hpp"
+
+#define HU_TRY(expr)                  \
+  do {                                \
+    int _rc = (expr);                 \
+    if (_rc != HU_OK) return _rc;     \
+  } while (0)
+#define HU_HIP(expr)                               \
+  do {                                             \
+    if ((expr) != hipSuccess) return HU_ERR_HIP;   \
+  } while (0)
+
+namespace hu {
+
+struct Geom {
+  int nd;
+  int n[3];
+  int nx, nxh;
+  long long N, Nh, nrows;
+  long long D;      // lcm of the dims
+  int tiled;        // 2D: half spectrum in column groups of 4; 3D: row-major
+  long long Nhp;    // per-field half-spectrum storage (padded to whole column groups in 2D)
+};
+
+// kernel families with tunable tile widths
+enum { P_R2C = 0, P_COLY = 1, P_FILTER = 2, P_C2R = 3, P_BIN = 4, NPASS = 5 };
+struct TunePlan {
+  int v[NPASS];
+};
+
+struct Layout {
+  size_t spec, partials, fstats, total;
+  int tiles;
+};
+
+struct BinGeo {
+  uint16_t* table;               // [ncol][n0] bin of each mode, or null (computed in the kernels)
+  unsigned long long* counts;    // [nb] modes per bin with multiplicity
+};
+
+int make_geom(const hu_dims& d, Geom* g);
+int check_filter(const hu_filter* f, int nd);
+int check_bins(const hu_bins* b, int nd);
+bool aligned(const void* p, size_t a);
+size_t up256(size_t x);
+Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan);
+FiltDev filt_dev(const hu_filter& f);
+Axis0Geom axis0(const Geom& g);
+int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd);
+int get_tw(int L, const float2** tw);
+int get_tw2(int L, const float2** tw2);
+int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t st, BinGeo* out);
+int prepare_tables(const Geom& g, const hu_bins* bins, hipStream_t st);
+
+// tuned plans: in-memory cache, loaded once from $HUFIELD_TUNE_CACHE when set
+std::string plan_key(const Geom& g, const hu_bins* bins, int batch);
+TunePlan get_plan(const Geom& g, const hu_bins* bins, int batch);
+void set_plan(const std::string& key, const TunePlan& p);
+int save_plans(const char* path);
+
+// kernel timing (HIP events around each launch while enabled)
+extern bool g_prof;
+hipError_t timed_impl(const char* name, hipStream_t st, hipError_t (*fn)(void*), void* ctx);
+template <class F>
+hipError_t timed(const char* name, hipStream_t st, F&& f) {
+  using FF = std::remove_reference_t<F>;
+  if (!g_prof) return f();
+  return timed_impl(name, st, [](void* c) { return (*static_cast<FF*>(c))(); }, const_cast<void*>(static_cast<const void*>(&f)));
+}
+int profile_reset(bool on);
+int profile_collect(std::vector<std::string>& names, std::vector<long long>& launches, std::vector<double>& ms);
+
+// One class of B same-shape fields through the whole pass sequence (3D; 2D skips the y passes):
+//   rows_r2c(noise) -> cols(y, fwd) -> cols_filter(z) -> finalize -> cols(y, inv) -> rows_c2r
+//   [-> cols(y, fwd) -> cols_bin(z)]   for the +-1 spectrum
+// Uniform mode: one filter, seeds in `seeds`, outputs at out.* + field * stride (B <= MAX_CHUNK).
+// Batch mode: `io` points at B device FieldIO entries with each field's parameters and outputs.
+struct ClassRun {
+  Geom g;
+  int B;
+  TunePlan plan;
+  const hu_bins* bins;     // null: no spectra
+  bool thresh;             // sign map, counts and the +-1 spectrum
+  // uniform mode
+  hu_filter filt;
+  const uint64_t* seeds;
+  float near_abs;
+  hu_outputs out;
+  // batch mode
+  const FieldIO* io;
+  bool want_cont, want_pm1_spec;
+  // workspace of this class
+  char* work;
+  Layout lay;
+};
+int enqueue_class(const ClassRun& r, hipStream_t st);
+
+}  // namespace hu

@@ -9,7 +9,27 @@
 namespace hu {
 
 enum { SRC_NOISE = 0, SRC_F32 = 1, SRC_I8 = 2 };
-constexpr int MAX_CHUNK = 64;   // fields per launch (seeds travel in the kernel arguments)
+constexpr int MAX_CHUNK = 64;   // fields per launch when seeds travel in the kernel arguments
+constexpr int NVARIANT = 2;     // tile-width variants per kernel: 0 = default, 1 = half width
+
+// Per-field parameters and outputs of a heterogeneous batch, in device memory.  When a kernel's
+// `io` pointer is set, field b takes everything below from io[b] instead of the uniform kernel
+// arguments (base pointer + b * stride).
+struct FieldIO {
+  float* field;            // [N] or null
+  int8_t* pm1;             // [N] or null
+  double* stats;           // [4] or null
+  uint64_t* counts;        // [2] or null
+  double* cont_sum;        // [nb] or null
+  uint64_t* cont_cnt;      // [nb] or null
+  double* pm1_sum;         // [nb] or null
+  uint64_t* pm1_cnt;       // [nb] or null
+  uint64_t seed;
+  double sigma_f;
+  float near_abs;          // absolute near-zero tolerance for the count
+  int pad;
+  FiltDev filt;
+};
 
 // Accumulator set-up done by block 0 of each field in the first pass: dst[b * per_field + i] is
 // set to src[i] (the same per-field block for every field, e.g. precomputed bin counts) or 0.
@@ -30,6 +50,9 @@ struct RowsArgs {
   long long Nh, N, nrows;  // per field
   int tiled;               // 2D column-group layout (TW = 4) or row-major (3D)
   uint64_t seeds[MAX_CHUNK];
+  const FieldIO* io;       // per-field seeds and accumulators (batch path) or null
+  int nb;                  // with io: bins + 1, for clearing the per-field spectra
+  const uint32_t* cnt_src; // with io: precomputed bin counts (nb uint64)
   const void* src;         // real input for the load variants, [B][N]
   const float2* tw;        // exp(-2 pi i t / L), t < L
   const float2* tw2;       // exp(-2 pi i k / 2L), k < L
@@ -63,12 +86,14 @@ struct FilterArgs {
   long long Nh, N;
   Axis0Geom gm;
   FiltDev filt;
+  const FieldIO* io;       // per-field filter and continuous-spectrum output (batch path) or null
   BinDev bd;
   int nb;                  // bins + 1 (corner slot)
   const uint16_t* table;   // bin of each mode, [ncol][n0], or null (computed)
   const float2* tw;
   double* partials;        // [B][tiles][4]: sum w |F|^2, Re F(0), max ln chi
   double* cont_sum;        // [B][nb] raw sums of w |F|^2, or null (counts are filled from the geometry)
+  int want_bins;           // accumulate the continuous spectrum (LDS sized for it)
 };
 
 struct FinalizeArgs {
@@ -80,6 +105,7 @@ struct FinalizeArgs {
   double* stats;           // [B][4] user copy or null
   double* cont_sum;        // [B][nb] rescaled in place, or null
   int nb;
+  const FieldIO* io;
 };
 
 struct BinArgs {
@@ -92,6 +118,7 @@ struct BinArgs {
   const uint16_t* table;
   const float2* tw;
   double* sum;
+  const FieldIO* io;       // per-field +-1 spectrum output (batch path) or null
 };
 
 struct BinGeomArgs {
@@ -114,6 +141,7 @@ struct RowsZArgs {
   int8_t* pm1;
   uint64_t* counts;
   float near_tol;          // absolute
+  const FieldIO* io;       // per-field outputs (batch path) or null
 };
 
 struct ThreshArgs {
@@ -124,18 +152,18 @@ struct ThreshArgs {
   float near_tol;
 };
 
-hipError_t launch_rows_r2c(int L, int src, const RowsArgs& a, int batch, hipStream_t st);
-hipError_t launch_cols(int L, bool inv, const ColsArgs& a, int batch, hipStream_t st);
-hipError_t launch_cols_filter(int L, const FilterArgs& a, int batch, hipStream_t st);
+hipError_t launch_rows_r2c(int L, int src, int variant, const RowsArgs& a, int batch, hipStream_t st);
+hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st);
+hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st);
-hipError_t launch_cols_bin(int L, const BinArgs& a, int batch, hipStream_t st);
-hipError_t launch_rows_c2r(int L, bool thresh, const RowsZArgs& a, int batch, hipStream_t st);
+hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st);
+hipError_t launch_rows_c2r(int L, bool thresh, int variant, const RowsZArgs& a, int batch, hipStream_t st);
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st);
 hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st);
-ColSched col_sched(int L, long long ncol, int batch);
+ColSched col_sched(int L, int variant, long long ncol, int batch);
 hipError_t launch_zero_u64(uint64_t* p, long long n, hipStream_t st);
 hipError_t launch_debug_philox(uint64_t seed, uint64_t first, uint64_t count, uint32_t* words, float* normals,
                                hipStream_t st);
-int col_tiles(int L, long long ncol);
+int col_tiles(int L, int variant, long long ncol);
 
 }  // namespace hu

@@ -50,9 +50,9 @@ __device__ __forceinline__ void twist_store_rows(const float2* lds, const float2
 }
 
 // grid (ceil(nrows / C), B), block C * P; thread (c, p) = (tid / P, tid % P) transforms row c.
-template <int L, int SRC, bool TILED>
-__global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
-  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L>::C, T = RowTile<L>::T;
+template <int L, int SRC, bool TILED, int V>
+__global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L, V>::C, T = RowTile<L, V>::T;
   constexpr int RS = Region<L>::value;
   using Rad = typename Plan<L>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
@@ -65,10 +65,22 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
   const long long nx = 2 * L;
 
   if (blockIdx.x == 0) {                        // set up this field's accumulators for later passes
-    for (int s = 0; s < a.fill_spans; ++s) {
-      uint32_t* dst = a.fill[s].dst + (long long)b * a.fill[s].per_field;
-      const uint32_t* src = a.fill[s].src;
-      for (int i = tid; i < a.fill[s].per_field; i += T) dst[i] = src ? src[i] : 0u;
+    if (a.io) {
+      const FieldIO& io = a.io[b];
+      uint32_t* dst[5] = {reinterpret_cast<uint32_t*>(io.cont_sum), reinterpret_cast<uint32_t*>(io.cont_cnt),
+                          reinterpret_cast<uint32_t*>(io.pm1_sum), reinterpret_cast<uint32_t*>(io.pm1_cnt),
+                          reinterpret_cast<uint32_t*>(io.counts)};
+      const uint32_t* src[5] = {nullptr, a.cnt_src, nullptr, a.cnt_src, nullptr};
+      const int words[5] = {2 * a.nb, 2 * a.nb, 2 * a.nb, 2 * a.nb, 4};
+      for (int s = 0; s < 5; ++s)
+        if (dst[s])
+          for (int i = tid; i < words[s]; i += T) dst[s][i] = src[s] ? src[s][i] : 0u;
+    } else {
+      for (int s = 0; s < a.fill_spans; ++s) {
+        uint32_t* dst = a.fill[s].dst + (long long)b * a.fill[s].per_field;
+        const uint32_t* src = a.fill[s].src;
+        for (int i = tid; i < a.fill[s].per_field; i += T) dst[i] = src ? src[i] : 0u;
+      }
     }
   }
 
@@ -78,7 +90,7 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
   const int nv = rows_here * 2 * L;
   if constexpr (SRC == SRC_NOISE) {
     // voxel i of the field takes normal i mod 4 of Philox block i / 4
-    const uint64_t seed = a.seeds[b];
+    const uint64_t seed = a.io ? a.io[b].seed : a.seeds[b];
     const long long m0 = v0 >> 2, m1 = (v0 + nv + 3) >> 2;
     for (long long m = m0 + tid; m < m1; m += T) {
       float z[4];
@@ -119,9 +131,9 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_r2c(RowsArgs a) {
 }
 
 // C2R along x -> normalise -> field, sign map, counts -> R2C of the +-1 row (THRESH).
-template <int L, bool THRESH, bool TILED>
-__global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
-  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L>::C, T = RowTile<L>::T;
+template <int L, bool THRESH, bool TILED, int V>
+__global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L, V>::C, T = RowTile<L, V>::T;
   constexpr int RS = Region<L>::value;
   constexpr int TW = RowIO<L, TILED>::TW, NG = RowIO<L, TILED>::NG, PG = C * TW;
   using Rad = typename Plan<L>::fwd;
@@ -173,12 +185,16 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
   }
   __syncthreads();
   // ---- field and sign map out, 4 voxels (16 B of field, 4 B of map) per unit
-  const long long gbase = (long long)b * a.N + row0 * 2 * L;
+  float* fout = a.io ? a.io[b].field : field_ptr(a.field, a.N, b);
+  int8_t* tout = a.io ? a.io[b].pm1 : field_ptr(a.pm1, a.N, b);
+  uint64_t* cout = a.io ? a.io[b].counts : field_ptr(a.counts, 2, b);
+  const float near_tol = a.io ? a.io[b].near_abs : a.near_tol;
+  const long long gbase = row0 * 2 * L;
   const int nq = rows_here * L / 2;              // units of 4 voxels in the tile
   unsigned npos = 0, nnear = 0;
   for (int u = tid; u < nq; u += T) {
     const float4 f4 = *reinterpret_cast<const float4*>(stage + 4 * u);
-    if (a.field) *reinterpret_cast<float4*>(a.field + gbase + 4 * u) = f4;
+    if (fout) *reinterpret_cast<float4*>(fout + gbase + 4 * u) = f4;
     if constexpr (THRESH) {
       const float xs[4] = {f4.x, f4.y, f4.z, f4.w};
       uint32_t packed = 0;
@@ -186,20 +202,20 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
       for (int q = 0; q < 4; ++q) {
         const bool pos = xs[q] >= 0.0f;
         npos += pos;
-        nnear += fabsf(xs[q]) < a.near_tol;
+        nnear += fabsf(xs[q]) < near_tol;
         packed |= (uint32_t)(pos ? 0x01u : 0xFFu) << (8 * q);
       }
-      if (a.pm1) *reinterpret_cast<uint32_t*>(a.pm1 + gbase + 4 * u) = packed;
+      if (tout) *reinterpret_cast<uint32_t*>(tout + gbase + 4 * u) = packed;
     }
   }
   // tail (rows of 6 voxels): the last rows_here * 2L mod 4 samples one by one
   for (int i = 4 * nq + tid; i < rows_here * 2 * L; i += T) {
     const float x = stage[i];
-    if (a.field) a.field[gbase + i] = x;
+    if (fout) fout[gbase + i] = x;
     if constexpr (THRESH) {
       npos += x >= 0.0f;
-      nnear += fabsf(x) < a.near_tol;
-      if (a.pm1) a.pm1[gbase + i] = x >= 0.0f ? (int8_t)1 : (int8_t)-1;
+      nnear += fabsf(x) < near_tol;
+      if (tout) tout[gbase + i] = x >= 0.0f ? (int8_t)1 : (int8_t)-1;
     }
   }
   if constexpr (THRESH) {
@@ -214,11 +230,11 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
     for (int s = 0; s < E; ++s) lrow[lidx(slot_index<L, RLF, P>(s, p))] = v[s];
     __syncthreads();
     twist_store_rows<L, C, T, TILED>(lds, a.tw2, spec_f, row0, rows_here, a.nrows, tid);
-    if (tid == 0 && a.counts) {
+    if (tid == 0 && cout) {
       unsigned long long np = 0, nn = 0;
       for (int w = 0; w < (T + 63) / 64; ++w) { np += red_u[0][w]; nn += red_u[1][w]; }
-      atomicAdd((unsigned long long*)(a.counts + 2 * b + 0), np);
-      atomicAdd((unsigned long long*)(a.counts + 2 * b + 1), nn);
+      atomicAdd((unsigned long long*)(cout + 0), np);
+      atomicAdd((unsigned long long*)(cout + 1), nn);
     }
   }
 }
@@ -227,51 +243,55 @@ __global__ void __launch_bounds__(RowTile<L>::T) k_rows_c2r(RowsZArgs a) {
 
 static inline unsigned ceil_div_u(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
-template <int L, int SRC, bool TILED>
+template <int L, int SRC, bool TILED, int V>
 static hipError_t launch_rows_r2c_L(const RowsArgs& a, int batch, hipStream_t st) {
-  constexpr int C = RowTile<L>::C, T = RowTile<L>::T;
+  constexpr int C = RowTile<L, V>::C, T = RowTile<L, V>::T;
   dim3 grid(ceil_div_u(a.nrows, C), batch);
-  hipLaunchKernelGGL((k_rows_r2c<L, SRC, TILED>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2), st, a);
+  hipLaunchKernelGGL((k_rows_r2c<L, SRC, TILED, V>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2), st,
+                     a);
   return hipGetLastError();
 }
 
 template <int L, int SRC>
-static hipError_t launch_rows_r2c_S(const RowsArgs& a, int batch, hipStream_t st) {
-  return a.tiled ? launch_rows_r2c_L<L, SRC, true>(a, batch, st) : launch_rows_r2c_L<L, SRC, false>(a, batch, st);
+static hipError_t launch_rows_r2c_S(int variant, const RowsArgs& a, int batch, hipStream_t st) {
+  if (variant)
+    return a.tiled ? launch_rows_r2c_L<L, SRC, true, 1>(a, batch, st) : launch_rows_r2c_L<L, SRC, false, 1>(a, batch, st);
+  return a.tiled ? launch_rows_r2c_L<L, SRC, true, 0>(a, batch, st) : launch_rows_r2c_L<L, SRC, false, 0>(a, batch, st);
 }
 
-hipError_t launch_rows_r2c(int L, int src, const RowsArgs& a, int batch, hipStream_t st) {
+hipError_t launch_rows_r2c(int L, int src, int variant, const RowsArgs& a, int batch, hipStream_t st) {
   switch (L) {
-#define X(LL)                                                                        \
-  case LL:                                                                           \
-    if (src == SRC_NOISE) return launch_rows_r2c_S<LL, SRC_NOISE>(a, batch, st);     \
-    if (src == SRC_F32) return launch_rows_r2c_S<LL, SRC_F32>(a, batch, st);         \
-    return launch_rows_r2c_S<LL, SRC_I8>(a, batch, st);
+#define X(LL)                                                                                 \
+  case LL:                                                                                    \
+    if (src == SRC_NOISE) return launch_rows_r2c_S<LL, SRC_NOISE>(variant, a, batch, st);     \
+    if (src == SRC_F32) return launch_rows_r2c_S<LL, SRC_F32>(0, a, batch, st);               \
+    return launch_rows_r2c_S<LL, SRC_I8>(0, a, batch, st);
     HU_ROW_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int L, bool THRESH, bool TILED>
+template <int L, bool THRESH, bool TILED, int V>
 static hipError_t launch_rows_c2r_L(const RowsZArgs& a, int batch, hipStream_t st) {
-  constexpr int C = RowTile<L>::C, T = RowTile<L>::T;
+  constexpr int C = RowTile<L, V>::C, T = RowTile<L, V>::T;
   dim3 grid(ceil_div_u(a.nrows, C), batch);
-  hipLaunchKernelGGL((k_rows_c2r<L, THRESH, TILED>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2),
+  hipLaunchKernelGGL((k_rows_c2r<L, THRESH, TILED, V>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2),
                      st, a);
   return hipGetLastError();
 }
 
-template <int L>
-static hipError_t launch_rows_c2r_S(bool thresh, const RowsZArgs& a, int batch, hipStream_t st) {
+template <int L, int V>
+static hipError_t launch_rows_c2r_V(bool thresh, const RowsZArgs& a, int batch, hipStream_t st) {
   if (a.tiled)
-    return thresh ? launch_rows_c2r_L<L, true, true>(a, batch, st) : launch_rows_c2r_L<L, false, true>(a, batch, st);
-  return thresh ? launch_rows_c2r_L<L, true, false>(a, batch, st) : launch_rows_c2r_L<L, false, false>(a, batch, st);
+    return thresh ? launch_rows_c2r_L<L, true, true, V>(a, batch, st) : launch_rows_c2r_L<L, false, true, V>(a, batch, st);
+  return thresh ? launch_rows_c2r_L<L, true, false, V>(a, batch, st) : launch_rows_c2r_L<L, false, false, V>(a, batch, st);
 }
 
-hipError_t launch_rows_c2r(int L, bool thresh, const RowsZArgs& a, int batch, hipStream_t st) {
+hipError_t launch_rows_c2r(int L, bool thresh, int variant, const RowsZArgs& a, int batch, hipStream_t st) {
   switch (L) {
-#define X(LL) case LL: return launch_rows_c2r_S<LL>(thresh, a, batch, st);
+#define X(LL) \
+  case LL: return variant ? launch_rows_c2r_V<LL, 1>(thresh, a, batch, st) : launch_rows_c2r_V<LL, 0>(thresh, a, batch, st);
     HU_ROW_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -44,6 +44,12 @@ class hu_outputs(ctypes.Structure):
                 ("field", "pm1", "stats", "counts", "cont_sum", "cont_cnt", "pm1_sum", "pm1_cnt")]
 
 
+class hu_job(ctypes.Structure):
+    _fields_ = [("dims", hu_dims), ("filt", hu_filter), ("seed", ctypes.c_uint64), ("bins", hu_bins)] + \
+               [(n, ctypes.c_void_p) for n in
+                ("field", "pm1", "stats", "counts", "cont_sum", "cont_cnt", "pm1_sum", "pm1_cnt")]
+
+
 _vp, _sz, _i32, _u64, _f32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_uint64, ctypes.c_float
 _P = ctypes.POINTER
 
@@ -58,8 +64,14 @@ _lib.hu_strerror.restype = ctypes.c_char_p
 _lib.hu_debug_philox.argtypes = [_u64, _u64, _u64, _vp, _vp, _vp]
 _lib.hu_profile_enable.argtypes = [ctypes.c_int]
 _lib.hu_profile_read.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+_lib.hu_workspace_size_batch.argtypes = [_P(hu_job), _i32, _P(_sz)]
+_lib.hu_pipeline_batch.argtypes = [_P(hu_job), _i32, _f32, _P(_i32), _vp, _sz, _vp]
+_lib.hu_autotune.argtypes = [hu_dims, _i32, _P(hu_bins), ctypes.c_char_p, _P(ctypes.c_double)]
+_lib.hu_plan_query.argtypes = [hu_dims, _i32, _P(hu_bins), _P(_i32)]
+_lib.hu_plan_set.argtypes = [hu_dims, _i32, _P(hu_bins), _P(_i32)]
 for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline",
-           "hu_debug_philox", "hu_profile_enable", "hu_profile_read"):
+           "hu_debug_philox", "hu_profile_enable", "hu_profile_read", "hu_workspace_size_batch",
+           "hu_pipeline_batch", "hu_autotune", "hu_plan_query", "hu_plan_set"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -296,3 +308,90 @@ def profile_read(cap=64):
     for i in range(min(n, cap)):
         out[bytes(names[i]).split(b"\0", 1)[0].decode()] = (int(launches[i]), float(ms[i]))
     return out
+
+
+# ---------------------------------------------------------------------------------------------
+# heterogeneous batches and the autotuner
+# ---------------------------------------------------------------------------------------------
+PASS_NAMES = ("rows_r2c", "cols_y", "cols_filter", "rows_c2r", "cols_bin")
+
+
+class BatchBuffers:
+    """Outputs for a heterogeneous batch: job i gets field, pm1, stats, counts and, with bins,
+    the continuous and +-1 spectra, each a device tensor; plus the batch workspace."""
+
+    def __init__(self, jobs, device="cuda", want=("field", "pm1", "stats", "counts", "cont", "pm1_spec")):
+        self.jobs = list(jobs)
+        dev = device
+        self.out = []
+        arr = (hu_job * len(self.jobs))()
+        for i, j in enumerate(self.jobs):
+            dims = tuple(int(n) for n in j["dims"])
+            o = {}
+            if "field" in want:
+                o["field"] = torch.empty(dims, dtype=torch.float32, device=dev)
+            if "pm1" in want:
+                o["pm1"] = torch.empty(dims, dtype=torch.int8, device=dev)
+            if "stats" in want:
+                o["stats"] = torch.empty(4, dtype=torch.float64, device=dev)
+            if "counts" in want:
+                o["counts"] = torch.empty(2, dtype=torch.int64, device=dev)
+            bins = j.get("bins")
+            if bins is not None:
+                nb = _nb(bins)
+                if "cont" in want:
+                    o["cont_sum"] = torch.empty(nb, dtype=torch.float64, device=dev)
+                    o["cont_cnt"] = torch.empty(nb, dtype=torch.int64, device=dev)
+                if "pm1_spec" in want:
+                    o["pm1_sum"] = torch.empty(nb, dtype=torch.float64, device=dev)
+                    o["pm1_cnt"] = torch.empty(nb, dtype=torch.int64, device=dev)
+            self.out.append(o)
+            jb = arr[i]
+            jb.dims = make_dims(dims)
+            jb.filt = make_filter(j["filt"])
+            jb.seed = int(j["seed"]) & 0xFFFFFFFFFFFFFFFF
+            if bins is not None:
+                jb.bins = make_bins(bins)
+            for name in ("field", "pm1", "stats", "counts", "cont_sum", "cont_cnt", "pm1_sum", "pm1_cnt"):
+                setattr(jb, name, o[name].data_ptr() if name in o else None)
+        self._jobs = arr
+        need = _sz()
+        _check(_lib.hu_workspace_size_batch(arr, len(self.jobs), ctypes.byref(need)), "hu_workspace_size_batch")
+        self.work = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=dev)
+        self.status = (_i32 * len(self.jobs))()
+
+    def set_seeds(self, seeds):
+        for i, s in enumerate(seeds):
+            self._jobs[i].seed = int(s) & 0xFFFFFFFFFFFFFFFF
+
+
+def pipeline_batch(bufs, near_tol=1e-5):
+    """The whole hot path for every job of a BatchBuffers in one submission (a replayed HIP graph).
+    Returns the per-job status list (0 = ok)."""
+    dev = bufs.work.device
+    _check(_lib.hu_pipeline_batch(bufs._jobs, len(bufs.jobs), float(near_tol), bufs.status, _ptr(bufs.work),
+                                  bufs.work.numel(), _stream(dev)), "hu_pipeline_batch")
+    return list(bufs.status)
+
+
+def autotune(dims, batch, bins, cache_path=None):
+    """Time both tile variants of every kernel family on this shape and keep the faster; returns
+    ({family: chosen variant}, ms array [2, 5])."""
+    ms = (ctypes.c_double * 10)()
+    b = make_bins(bins)
+    _check(_lib.hu_autotune(make_dims(dims), int(batch), ctypes.byref(b),
+                            cache_path.encode() if cache_path else None, ms), "hu_autotune")
+    return plan_query(dims, batch, bins), np.array(list(ms)).reshape(2, 5)
+
+
+def plan_query(dims, batch, bins):
+    v = (_i32 * 5)()
+    b = make_bins(bins) if bins is not None else None
+    _check(_lib.hu_plan_query(make_dims(dims), int(batch), ctypes.byref(b) if b else None, v), "hu_plan_query")
+    return dict(zip(PASS_NAMES, list(v)))
+
+
+def plan_set(dims, batch, bins, variants):
+    v = (_i32 * 5)(*[int(x) for x in variants])
+    b = make_bins(bins) if bins is not None else None
+    _check(_lib.hu_plan_set(make_dims(dims), int(batch), ctypes.byref(b) if b else None, v), "hu_plan_set")

@@ -49,9 +49,10 @@ def test_strerror(hf):
 
 
 def test_workspace_sizes(hf):
-    # 2D 2048^2 x 16: half spectrum 16 * 2048 * 1025 complex64 plus statistics
+    # 2D 2048^2 x 16: half spectrum 16 * 2048 * 1025 complex64, stored in column groups of four
+    # (1025 -> 1028 columns), plus statistics
     n = hf.workspace_size(hf.HU_OP_PIPELINE, (2048, 2048), 16, (128, 36))
-    spec = 16 * 2048 * 1025 * 8
+    spec = 16 * 2048 * 1028 * 8
     assert spec <= n < spec + (1 << 20)
     m = hf.workspace_size(hf.HU_OP_POWER_SPECTRUM, (256, 256, 256), 4, (128, 1))
     assert m >= 4 * 256 * 256 * 129 * 8

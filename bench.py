@@ -38,8 +38,12 @@ def parse():
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the batched 2D workload (for profiler runs)")
+    ap.add_argument("--workload", default="2d_2048x2048_x16", choices=("2d_2048x2048_x16", "3d_256x256x256_x4"),
+                    help="with --main-only: which workload to time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for scaling PMC byte counters)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="no GPU: turn rocprofv3 output under DIR into the summaries under profiles/")
     return ap.parse_args()
 
 
@@ -66,10 +70,15 @@ def algorithmic_bytes(dims, batch):
     return fam, total
 
 
+# the sources that define the pipeline's kernels and their launch shapes
+PIPELINE_SOURCES = ("hu_device.hpp", "hu_common.hpp", "hu_internal.hpp", "hu_host.hpp", "hu_rows.hip", "hu_cols.hip",
+                    "hu_filter.hip", "hu_bin.hip", "hu_host.hip")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2509_08675_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in PIPELINE_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -158,6 +167,154 @@ def cpu_baseline(cfg, budget_s=12.0):
                 seconds=round(el, 2))
 
 
+# ---------------------------------------------------------------------------------------------
+# rocprofv3 summaries (no GPU): DIR/<workload>/{trace,fetch,write} and DIR/copy_{fetch,write}
+# ---------------------------------------------------------------------------------------------
+PROFILE_COMMANDS = {
+    "trace": "rocprofv3 --kernel-trace --stats -f csv -d DIR/{w}/trace -o trace -- "
+             "python3 REPO/bench.py --main-only --workload {w} --steps 20 --warmup 3",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/{w}/fetch -o fetch -- "
+             "python3 REPO/bench.py --main-only --workload {w} --steps 3 --warmup 1",
+    "write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/{w}/write -o write -- "
+             "python3 REPO/bench.py --main-only --workload {w} --steps 3 --warmup 1",
+    "copy_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/copy_fetch -o copy_fetch -- "
+                  "python3 REPO/bench.py --copy-calibration",
+    "copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/copy_write -o copy_write -- "
+                  "python3 REPO/bench.py --copy-calibration",
+    "sq1": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU "
+           "SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU_TRANS_F32 -f csv -d DIR/sq1 -o sq1 -- "
+           "python3 REPO/bench.py --main-only --steps 2 --warmup 1",
+    "sq2": "rocprofv3 --pmc SQ_WAIT_INST_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_LDS SQ_INSTS_SALU "
+           "SQ_WAIT_INST_ANY SQ_INST_CYCLES_VMEM_RD SQ_INSTS_LDS_ATOMIC -f csv -d DIR/sq2 -o sq2 -- "
+           "python3 REPO/bench.py --main-only --steps 2 --warmup 1",
+}
+
+
+def kernel_family(name):
+    """Pipeline family of a rocprofv3 kernel name (None for other kernels)."""
+    import re
+    m = re.search(r"hu::(k_\w+)<([^>]*)>", name)
+    if not m:
+        return "finalize" if "k_finalize" in name else None
+    k, args = m.group(1), [t.strip() for t in m.group(2).split(",")]
+    if k == "k_rows_r2c":
+        return "rows_r2c_noise" if args[1] == "0" else "rows_r2c"
+    if k == "k_rows_c2r":
+        return "rows_c2r_thresh" if args[1] == "true" else "rows_c2r"
+    if k == "k_cols":
+        return "cols_y_inv" if args[1] == "true" else "cols_y_fwd"
+    return {"k_cols_filter": "cols_filter", "k_cols_bin": "cols_bin"}.get(k)
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit("no *%s under %s" % (suffix, d))
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _per_dispatch(d, counter, family=None, min_value=0.0):
+    """{family: median per-dispatch value of counter}; family=None keeps the largest dispatches
+    of any kernel (the copy run)."""
+    import statistics
+    vals = {}
+    for r in _csv_rows(d, "_counter_collection.csv"):
+        if r["Counter_Name"] != counter:
+            continue
+        f = kernel_family(r["Kernel_Name"]) if family is None else family
+        if f is None:
+            continue
+        vals.setdefault(f, []).append(float(r["Counter_Value"]))
+    if family is not None:
+        v = sorted(vals.get(family, []))
+        top = [x for x in v if x >= 0.5 * v[-1]] if v else []
+        return statistics.median(top) if top else None
+    return {f: statistics.median(v) for f, v in vals.items()}
+
+
+def summarize_profiles(d):
+    from paper_2509_08675_amd.workloads import C2, C3
+    copy_bytes = 4 << 28
+    cf = _per_dispatch(os.path.join(d, "copy_fetch"), "FETCH_SIZE", family="copy")
+    cw = _per_dispatch(os.path.join(d, "copy_write"), "WRITE_SIZE", family="copy")
+    f_fetch, f_write = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    out = dict(source_hash=kernel_source_hash(), copy_factor=dict(fetch=round(f_fetch, 4), write=round(f_write, 4)),
+               workloads={})
+    md = ["# Pipeline kernels: rocprofv3 summaries", "",
+          "Kernel sources hash (bench.py `kernel_source_hash`): `%s`" % out["source_hash"], "",
+          "Commands, each after `cd /tmp && export TMPDIR=/tmp` on one MI355X (`REPO` the repository root, "
+          "`DIR` a scratch output folder, `{w}` each workload below); then "
+          "`python3 REPO/bench.py --summarize-profiles DIR` writes this file and `pmc_traffic.json`:", ""]
+    for k, c in PROFILE_COMMANDS.items():
+        md.append("* %s: `%s`" % (k, c))
+    md += ["", "## Byte-counter calibration (plain 1 GiB device copy)", "",
+           "| counter | KiB per copy dispatch | bytes moved | factor |", "|---|---|---|---|",
+           "| FETCH_SIZE | %.0f | %d | %.4f |" % (cf, copy_bytes, f_fetch),
+           "| WRITE_SIZE | %.0f | %d | %.4f |" % (cw, copy_bytes, f_write), ""]
+    for cfg in (C2, C3):
+        w = cfg["name"]
+        wd = os.path.join(d, w)
+        if not os.path.isdir(wd):
+            continue
+        fam_bytes, total = algorithmic_bytes(cfg["dims"], len(cfg["seeds"]))
+        md += ["## %s" % w, "", "### Kernel trace (`--kernel-trace --stats`)", "",
+               "| kernel | family | calls | mean us | share % |", "|---|---|---|---|---|"]
+        for r in _csv_rows(os.path.join(wd, "trace"), "_kernel_stats.csv"):
+            md.append("| `%s` | %s | %s | %.2f | %s |" % (r["Name"].replace("|", "/")[:90], kernel_family(r["Name"]),
+                                                        r["Calls"], float(r["AverageNs"]) / 1e3, r["Percentage"]))
+        fe = _per_dispatch(os.path.join(wd, "fetch"), "FETCH_SIZE")
+        wr = _per_dispatch(os.path.join(wd, "write"), "WRITE_SIZE")
+        md += ["", "### HBM traffic per launch (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`, calibrated)", "",
+               "| family | FETCH KiB | WRITE KiB | traffic bytes | algorithmic bytes | traffic / algorithmic |",
+               "|---|---|---|---|---|---|"]
+        tr = {}
+        for f in sorted(set(fe) | set(wr)):
+            b = fe.get(f, 0.0) * 1024 * f_fetch + wr.get(f, 0.0) * 1024 * f_write
+            tr[f] = int(round(b))
+            alg = fam_bytes.get(f, 0)
+            md.append("| %s | %.0f | %.0f | %d | %d | %s |" % (f, fe.get(f, 0.0), wr.get(f, 0.0), tr[f], alg,
+                                                               "%.3f" % (b / alg) if alg else "-"))
+        out["workloads"][w] = tr
+        md.append("")
+    sq = {}
+    for g in ("sq1", "sq2"):
+        if os.path.isdir(os.path.join(d, g)):
+            for r in _csv_rows(os.path.join(d, g), "_counter_collection.csv"):
+                f = kernel_family(r["Kernel_Name"])
+                if f:
+                    sq.setdefault(f, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if sq:
+        import statistics
+        fam_ms = {}
+        for r in _csv_rows(os.path.join(d, C2["name"], "trace"), "_kernel_stats.csv"):
+            if kernel_family(r["Name"]):
+                fam_ms[kernel_family(r["Name"])] = float(r["AverageNs"]) * 1e-6
+        modes = len(C2["seeds"]) * C2["dims"][0] * (C2["dims"][1] // 2 + 1)
+        md += ["## Instruction counters, %s (`sq1`, `sq2` passes; whole-chip counts per dispatch)" % C2["name"], "",
+               "VALU lane-instructions per half-spectrum mode = SQ_INSTS_VALU x 64 / modes; VALU issue share = "
+               "SQ_INSTS_VALU / 256 CUs / (mean duration x 2.4 GHz), i.e. the fraction of cycles in which a CU "
+               "issued one wave64 VALU instruction.", "",
+               "| family | VALU lane-instr / mode | VALU issue share | LDS instr / mode | LDS bank-conflict cycles / mode "
+               "| transcendental lane-instr / mode |", "|---|---|---|---|---|---|"]
+        for f in sorted(sq):
+            c = {k: statistics.median(v) for k, v in sq[f].items()}
+            if f not in fam_ms or "SQ_INSTS_VALU" not in c:
+                continue
+            share = c["SQ_INSTS_VALU"] / 256.0 / (fam_ms[f] * 1e-3 * 2.4e9)
+            md.append("| %s | %.1f | %.2f | %.1f | %.1f | %.1f |" % (
+                f, c["SQ_INSTS_VALU"] * 64 / modes, share, c.get("SQ_INSTS_LDS", 0) * 64 / modes,
+                c.get("SQ_LDS_BANK_CONFLICT", 0) * 64 / modes, c.get("SQ_INSTS_VALU_TRANS_F32", 0) * 64 / modes))
+        md.append("")
+    with open(os.path.join(ROOT, "profiles", "pmc_traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    with open(os.path.join(ROOT, "profiles", "pipeline_kernels_2048sq_x16_and_256cube_x4.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def copy_calibration(torch):
     n = 1 << 28     # 1 GiB of float32
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -174,6 +331,9 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     import torch
     if args.copy_calibration:
         copy_calibration(torch)
@@ -181,7 +341,7 @@ def main():
     from paper_2509_08675_amd import hufield as hf
     from paper_2509_08675_amd.workloads import C2, C3
 
-    cfg = C2
+    cfg = C3 if (args.main_only and args.workload == C3["name"]) else C2
     el, prof = time_pipeline(hf, torch, cfg, args.steps, args.warmup)
     ms = el / args.steps * 1e3
     vox = len(cfg["seeds"]) * math.prod(cfg["dims"])

@@ -71,7 +71,7 @@ enum {
 enum { HU_F32 = 0, HU_I8 = 1 };
 
 /* Operations for hu_workspace_size. */
-enum { HU_OP_GEN_FIELD = 0, HU_OP_PIPELINE = 1, HU_OP_POWER_SPECTRUM = 2, HU_OP_LOSS = 3 };
+enum { HU_OP_GEN_FIELD = 0, HU_OP_PIPELINE = 1, HU_OP_POWER_SPECTRUM = 2, HU_OP_LOSS = 3, HU_OP_FILTER_SPECTRUM = 4 };
 
 typedef struct hu_dims {
   int32_t ndim;   /* 2 or 3 */
@@ -140,6 +140,29 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
 int hu_pipeline(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds,
                 hu_bins bins, float near_tol, const hu_outputs* out, void* work, size_t work_bytes,
                 void* stream);
+
+/* Expected binned spectrum of a filter, with no noise: per mode E[P(k)] = sigma_f^2 N H_sym(k)^2 /
+ * sum_k' w_k' H_sym(k')^2 (Eqs. (10)-(11) under the normalisation of Eq. (15)), summed per bin
+ * with the half-spectrum multiplicities w exactly like the continuous spectrum of a field, so
+ * that sum / cnt is the expected bin mean.  The target of a spectrum-matching loss (parameter
+ * optimisation is the extension named in Sec. IV).  sum [R*A+1] FP64 and cnt [R*A+1] (or NULL),
+ * device.  The bin sums use FP64 atomics (last-bit order effects, as the other spectra).
+ * Workspace: hu_workspace_size(HU_OP_FILTER_SPECTRUM, dims, 1, &bins, ...). */
+int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double* sum, uint64_t* cnt,
+                       void* work, size_t work_bytes, void* stream);
+
+/* Adjoint of the binned continuous spectrum with respect to the filter parameters of
+ * Eqs. (12)-(13) (the gradient a parameter-fitting loop of Sec. IV needs).  Inputs are the outputs
+ * of hu_gen_field(dims, 1, filt, &seed, field, stats, &bins, cont_sum, cont_cnt, ...) for one
+ * field, and dL_dP [R*A+1]: the gradient of a loss L with respect to the bin means
+ * P_b = cont_sum_b / cont_cnt_b (the corner slot R*A and empty bins are ignored); all device.
+ * Writes grad [7] = dL/d(a, b, c, p, rot, k0, w) (device FP64; the c entry is 0 in 2D).  The
+ * noise spectrum is regenerated from the seed (nothing of the forward field is read), and the
+ * seven sums are FP64, reduced in a fixed order (bit-reproducible).
+ * Workspace: hu_workspace_size(HU_OP_LOSS, dims, 1, &bins, ...). */
+int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins bins, const double* dL_dP,
+                     const double* cont_sum, const uint64_t* cont_cnt, const double* stats, double* grad,
+                     void* work, size_t work_bytes, void* stream);
 
 /* One field of a heterogeneous batch: its own grid, filter, seed, bins and outputs (device
  * pointers, each may be NULL; at least one must be set; bins are used when cont_sum or pm1_sum is

@@ -27,6 +27,29 @@ hu_outputs offset_outputs(const hu_outputs& o, long long f0, long long N, int nb
 
 TunePlan widest_plan() { return TunePlan{{1, 1, 1, 1, 1}}; }   // most tiles: largest partials
 
+// workspace of hu_spectrum_grad: the noise spectrum, the per-bin weights, the per-tile partials
+struct GradLayout {
+  size_t spec, coef, partials, total;
+  int tiles;
+};
+GradLayout grad_layout(const Geom& g, int nb) {
+  GradLayout L{};
+  L.spec = 0;
+  L.coef = up256((size_t)g.Nhp * 8);
+  L.partials = L.coef + up256((size_t)(nb + 1) * 8);
+  L.tiles = col_tiles(g.n[0], 0, axis0(g).ncol);
+  L.total = L.partials + up256((size_t)L.tiles * 8 * 8);
+  return L;
+}
+
+// workspace of hu_filter_spectrum: the per-block totals
+constexpr int FS_MAX_BLOCKS = 1024;
+int fs_blocks(const Geom& g) {
+  const long long chunk = 256LL * 16;
+  const long long n = (g.Nh + chunk - 1) / chunk;
+  return (int)(n < FS_MAX_BLOCKS ? n : FS_MAX_BLOCKS);
+}
+
 int run_generator(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds, const hu_bins* bins,
                   float near_tol_rel, const hu_outputs& o, bool thresh, void* work, size_t work_bytes, void* stream) {
   Geom g;
@@ -85,6 +108,13 @@ int hu_workspace_size(int op, hu_dims dims, int32_t batch, const hu_bins* bins, 
       return HU_OK;
     case HU_OP_POWER_SPECTRUM:
       *bytes = layout(g, chunk, false, widest_plan()).total;
+      return HU_OK;
+    case HU_OP_LOSS:
+      if (!bins) return HU_ERR_ARG;
+      *bytes = grad_layout(g, bins->n_radial * bins->n_angular + 1).total;
+      return HU_OK;
+    case HU_OP_FILTER_SPECTRUM:
+      *bytes = up256((size_t)FS_MAX_BLOCKS * 8);
       return HU_OK;
     default:
       return HU_ERR_ARG;
@@ -195,6 +225,125 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
     ba.sum = s;
     HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], 0, ba, st); }));
   }
+  return HU_OK;
+}
+
+int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double* sum, uint64_t* cnt, void* work,
+                       size_t work_bytes, void* stream) {
+  Geom g;
+  HU_TRY(make_geom(dims, &g));
+  HU_TRY(check_filter(filt, g.nd));
+  HU_TRY(check_bins(&bins, g.nd));
+  if (!sum) return HU_ERR_ARG;
+  if (!aligned(sum, 16) || (cnt && !aligned(cnt, 16))) return HU_ERR_ALIGN;
+  if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
+  if (work_bytes < up256((size_t)FS_MAX_BLOCKS * 8)) return HU_ERR_WORKSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HU_TRY(prepare_tables(g, &bins, st));
+  const int nb = bins.n_radial * bins.n_angular + 1;
+  BinDev bd{};
+  HU_TRY(make_bindev(g, bins, &bd));
+  BinGeo geo{nullptr, nullptr};
+  HU_TRY(get_bingeo(g, bins, bd, st, &geo));
+  FilterSpecArgs a{};
+  a.gm = axis0(g);
+  a.Nh = (long long)a.gm.ncol * a.gm.n0;
+  a.filt = filt_dev(*filt);
+  a.bd = bd;
+  a.nb = nb;
+  a.table = geo.table;
+  a.sum = sum;
+  a.partials = reinterpret_cast<double*>(work);
+  a.nblocks = fs_blocks(g);
+  a.N = g.N;
+  a.sigma_f = filt->sigma_f;
+  a.counts = geo.counts;
+  a.cnt = cnt;
+  HU_HIP(timed("zero", st, [&] { return launch_zero_u64(reinterpret_cast<uint64_t*>(sum), nb, st); }));
+  HU_HIP(timed("filter_spectrum", st, [&] { return launch_filter_spectrum(a, st); }));
+  return HU_OK;
+}
+
+int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins bins, const double* dL_dP,
+                     const double* cont_sum, const uint64_t* cont_cnt, const double* stats, double* grad, void* work,
+                     size_t work_bytes, void* stream) {
+  Geom g;
+  HU_TRY(make_geom(dims, &g));
+  HU_TRY(check_filter(filt, g.nd));
+  HU_TRY(check_bins(&bins, g.nd));
+  if (!dL_dP || !cont_sum || !cont_cnt || !stats || !grad) return HU_ERR_ARG;
+  const void* ptrs[] = {dL_dP, cont_sum, cont_cnt, stats, grad};
+  for (const void* p : ptrs)
+    if (!aligned(p, 16)) return HU_ERR_ALIGN;
+  if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
+  const int nb = bins.n_radial * bins.n_angular + 1;
+  const GradLayout lay = grad_layout(g, nb);
+  if (work_bytes < lay.total) return HU_ERR_WORKSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HU_TRY(prepare_tables(g, &bins, st));
+  const int Lrow = g.nx / 2;
+  const float2 *tw_row, *tw2_row, *tw_0, *tw_1 = nullptr;
+  HU_TRY(get_tw(Lrow, &tw_row));
+  HU_TRY(get_tw2(Lrow, &tw2_row));
+  HU_TRY(get_tw(g.n[0], &tw_0));
+  if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
+  BinDev bd{};
+  HU_TRY(make_bindev(g, bins, &bd));
+  BinGeo geo{nullptr, nullptr};
+  HU_TRY(get_bingeo(g, bins, bd, st, &geo));
+  char* w = reinterpret_cast<char*>(work);
+  float2* spec = reinterpret_cast<float2*>(w + lay.spec);
+  double* coef = reinterpret_cast<double*>(w + lay.coef);
+  double* partials = reinterpret_cast<double*>(w + lay.partials);
+
+  // the noise spectrum W, transformed along every axis but axis 0 (as in the generator)
+  RowsArgs ra{};
+  ra.spec = spec;
+  ra.Nh = g.Nhp;
+  ra.tiled = g.tiled;
+  ra.N = g.N;
+  ra.nrows = g.nrows;
+  ra.seeds[0] = seed;
+  ra.tw = tw_row;
+  ra.tw2 = tw2_row;
+  ra.fill_spans = 0;
+  HU_HIP(timed("rows_r2c_noise", st, [&] { return launch_rows_r2c(Lrow, SRC_NOISE, 0, ra, 1, st); }));
+  if (g.nd == 3) {
+    ColsArgs cy{};
+    cy.spec = spec;
+    cy.Nh = g.Nhp;
+    cy.ncol = g.n[0] * g.nxh;
+    cy.inner = g.nxh;
+    cy.tw = tw_1;
+    cy.sc = col_sched(g.n[1], 0, cy.ncol, 1);
+    HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, 0, cy, st); }));
+  }
+  GradCoefArgs ga{};
+  ga.dL_dP = dL_dP;
+  ga.cont_sum = cont_sum;
+  ga.cont_cnt = cont_cnt;
+  ga.stats = stats;
+  ga.nb = nb;
+  ga.N = g.N;
+  ga.sigma_f = filt->sigma_f;
+  ga.coef = coef;
+  HU_HIP(timed("grad_coef", st, [&] { return launch_grad_coef(ga, st); }));
+  AdjointArgs aa{};
+  aa.gm = axis0(g);
+  aa.sc = col_sched(g.n[0], 0, aa.gm.ncol, 1);
+  aa.spec = spec;
+  aa.Nh = g.Nhp;
+  aa.filt = filt_dev(*filt);
+  aa.width = (float)filt->width;
+  aa.bd = bd;
+  aa.nb = nb;
+  aa.table = geo.table;
+  aa.tw = tw_0;
+  aa.coef = coef;
+  aa.partials = partials;
+  HU_HIP(timed("cols_adjoint", st, [&] { return launch_cols_adjoint(g.n[0], aa, st); }));
+  GradFinalArgs fa{partials, lay.tiles, grad};
+  HU_HIP(timed("grad_final", st, [&] { return launch_grad_final(fa, st); }));
   return HU_OK;
 }
 

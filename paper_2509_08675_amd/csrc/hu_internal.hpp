@@ -152,6 +152,60 @@ struct ThreshArgs {
   float near_tol;
 };
 
+// Adjoint of the filter with respect to theta = (a, b, c, p, rot, k0, w): the axis-0 pass over the
+// noise spectrum W, with the per-bin loss weights omega(k) = coef[b(k)] - coef[nb].
+struct AdjointArgs {
+  ColSched sc;
+  const float2* spec;      // W transformed along every axis but axis 0, [Nh]
+  long long Nh;
+  Axis0Geom gm;
+  FiltDev filt;
+  float width;             // w (the Gaussian band width)
+  BinDev bd;
+  int nb;
+  const uint16_t* table;   // bin of each mode or null
+  const float2* tw;
+  const double* coef;      // [nb + 1]: beta_b per bin, then gamma
+  double* partials;        // [tiles][8]: the 7 gradient partial sums
+};
+
+struct GradCoefArgs {
+  const double* dL_dP;     // [nb]: d loss / d (bin mean)
+  const double* cont_sum;  // [nb]: forward's normalised continuous-spectrum bin sums
+  const uint64_t* cont_cnt;   // [nb]: mode counts
+  const double* stats;     // [4]: forward's mu, var (raw field)
+  int nb;                  // slots incl. the corner slot (not part of the spectrum)
+  long long N;
+  double sigma_f;
+  double* coef;            // [nb + 1] out
+};
+
+struct GradFinalArgs {
+  const double* partials;  // [ntiles][8]
+  int ntiles;
+  double* grad;            // [7] out
+};
+
+struct FilterSpecArgs {
+  long long Nh;            // modes (ncol * n0)
+  Axis0Geom gm;
+  FiltDev filt;
+  BinDev bd;
+  int nb;
+  const uint16_t* table;
+  double* sum;             // [nb] raw sums of w H^2 (zeroed before the launch)
+  double* partials;        // [gridDim.x]: per-block sum of w H^2
+  int nblocks;
+  long long N;
+  double sigma_f;
+  const unsigned long long* counts;   // [nb] geometry counts, copied to cnt
+  uint64_t* cnt;           // [nb] out or null
+};
+
+hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st);
+hipError_t launch_grad_coef(const GradCoefArgs& a, hipStream_t st);
+hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);
+hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st);
 hipError_t launch_rows_r2c(int L, int src, int variant, const RowsArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st);
 hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st);

@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 HU_OK, HU_ERR_ARG, HU_ERR_SIZE, HU_ERR_ALIGN, HU_ERR_WORKSPACE, HU_ERR_DEGENERATE, HU_ERR_HIP, \
     HU_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 HU_F32, HU_I8 = 0, 1
-HU_OP_GEN_FIELD, HU_OP_PIPELINE, HU_OP_POWER_SPECTRUM, HU_OP_LOSS = 0, 1, 2, 3
+HU_OP_GEN_FIELD, HU_OP_PIPELINE, HU_OP_POWER_SPECTRUM, HU_OP_LOSS, HU_OP_FILTER_SPECTRUM = 0, 1, 2, 3, 4
 
 
 class hu_dims(ctypes.Structure):
@@ -69,9 +69,12 @@ _lib.hu_pipeline_batch.argtypes = [_P(hu_job), _i32, _f32, _P(_i32), _vp, _sz, _
 _lib.hu_autotune.argtypes = [hu_dims, _i32, _P(hu_bins), ctypes.c_char_p, _P(ctypes.c_double)]
 _lib.hu_plan_query.argtypes = [hu_dims, _i32, _P(hu_bins), _P(_i32)]
 _lib.hu_plan_set.argtypes = [hu_dims, _i32, _P(hu_bins), _P(_i32)]
+_lib.hu_filter_spectrum.argtypes = [hu_dims, _P(hu_filter), hu_bins, _vp, _vp, _vp, _sz, _vp]
+_lib.hu_spectrum_grad.argtypes = [hu_dims, _P(hu_filter), _u64, hu_bins, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline",
            "hu_debug_philox", "hu_profile_enable", "hu_profile_read", "hu_workspace_size_batch",
-           "hu_pipeline_batch", "hu_autotune", "hu_plan_query", "hu_plan_set"):
+           "hu_pipeline_batch", "hu_autotune", "hu_plan_query", "hu_plan_set", "hu_filter_spectrum",
+           "hu_spectrum_grad"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -395,3 +398,94 @@ def plan_set(dims, batch, bins, variants):
     v = (_i32 * 5)(*[int(x) for x in variants])
     b = make_bins(bins) if bins is not None else None
     _check(_lib.hu_plan_set(make_dims(dims), int(batch), ctypes.byref(b) if b else None, v), "hu_plan_set")
+
+
+# ---------------------------------------------------------------------------------------------
+# differentiation with respect to the filter parameters
+# ---------------------------------------------------------------------------------------------
+THETA_NAMES = ("a", "b", "c", "p", "rot", "k0", "width")
+
+
+def filter_with_theta(theta, alpha, sigma_f=1.0):
+    """Filter dict from theta = (a, b, c, p, rot, k0, w) and the fixed alpha, sigma_f."""
+    th = [float(x) for x in theta]
+    return dict(semi=tuple(th[0:3]), p=th[3], rot=th[4], k0=th[5], width=th[6], alpha=float(alpha),
+                sigma_f=float(sigma_f))
+
+
+def filter_spectrum(dims, filt, bins, device="cuda", work=None):
+    """Expected binned spectrum of the normalised field of a filter (no noise): sum [nb] FP64 and
+    cnt [nb]; sum / cnt is the expected bin mean of the continuous spectrum."""
+    dims = tuple(int(n) for n in dims)
+    nb = _nb(bins)
+    s = torch.empty(nb, dtype=torch.float64, device=device)
+    c = torch.empty(nb, dtype=torch.int64, device=device)
+    if work is None:
+        work = alloc_workspace(HU_OP_FILTER_SPECTRUM, dims, 1, bins, device)
+    h = make_filter(filt)
+    _check(_lib.hu_filter_spectrum(make_dims(dims), ctypes.byref(h), make_bins(bins), _ptr(s), _ptr(c), _ptr(work),
+                                   work.numel(), _stream(s.device)), "hu_filter_spectrum")
+    return s, c
+
+
+def spectrum_grad(dims, filt, seed, bins, dL_dP, cont_sum, cont_cnt, stats, work=None):
+    """dL/dtheta [7] (device FP64) from dL/d(bin means) [nb] and one field's forward outputs
+    (cont_sum [nb], cont_cnt [nb], stats [4] of gen_field with the same dims, filter, seed, bins)."""
+    dims = tuple(int(n) for n in dims)
+    dev = cont_sum.device
+    grad = torch.empty(7, dtype=torch.float64, device=dev)
+    if work is None:
+        work = alloc_workspace(HU_OP_LOSS, dims, 1, bins, dev)
+    h = make_filter(filt)
+    dL = dL_dP.to(device=dev, dtype=torch.float64).contiguous()
+    _check(_lib.hu_spectrum_grad(make_dims(dims), ctypes.byref(h), int(seed) & 0xFFFFFFFFFFFFFFFF, make_bins(bins),
+                                 _ptr(dL), _ptr(cont_sum), _ptr(cont_cnt), _ptr(stats), _ptr(grad), _ptr(work),
+                                 work.numel(), _stream(dev)), "hu_spectrum_grad")
+    return grad
+
+
+class FilterSpectrum(torch.autograd.Function):
+    """theta [7] = (a, b, c, p, rot, k0, w) -> the binned continuous spectrum P [R*A] (bin means,
+    0 for empty bins) of the field generated on `dims` from `seed` with those filter parameters
+    (alpha and sigma_f fixed).  Forward: hu_gen_field; backward: hu_spectrum_grad (the noise is
+    regenerated from the seed)."""
+
+    @staticmethod
+    def forward(ctx, theta, dims, seed, bins, alpha, sigma_f=1.0):
+        dims = tuple(int(n) for n in dims)
+        filt = filter_with_theta(theta.detach().cpu().tolist(), alpha, sigma_f)
+        dev = theta.device if theta.is_cuda else torch.device("cuda")
+        out = gen_field(dims, filt, [seed], cont_bins=bins, device=dev)
+        check_degenerate(out["stats"])
+        cs, cc, st = out["cont_sum"][0], out["cont_cnt"][0], out["stats"][0]
+        cnt = cc[:-1].to(torch.float64)
+        P = torch.where(cnt > 0, cs[:-1] / cnt.clamp(min=1.0), torch.zeros_like(cnt))
+        ctx.save_for_backward(cs, cc, st)
+        ctx.meta = (dims, int(seed), tuple(bins), filt, theta.device, theta.dtype)
+        return P
+
+    @staticmethod
+    def backward(ctx, gP):
+        cs, cc, st = ctx.saved_tensors
+        dims, seed, bins, filt, tdev, tdt = ctx.meta
+        dL = torch.zeros(cs.shape[0], dtype=torch.float64, device=cs.device)
+        dL[:-1] = gP.to(device=cs.device, dtype=torch.float64)
+        g = spectrum_grad(dims, filt, seed, bins, dL, cs, cc, st)
+        return g.to(device=tdev, dtype=tdt), None, None, None, None, None
+
+
+def spectrum_loss(theta, dims, seed, n_radial, target, alpha, sigma_f=1.0, eps_rel=1e-12):
+    """Spectrum-matching loss L = mean over radial bins 1..R-1 with modes of
+    (ln(P_b + eps) - ln(T_b + eps))^2, eps = eps_rel sigma_f^2, P the field's radial continuous
+    spectrum (FilterSpectrum, differentiable in theta) and T the expected spectrum of the
+    `target` filter; returns a scalar tensor."""
+    bins = (int(n_radial), 1)
+    P = FilterSpectrum.apply(theta, dims, seed, bins, alpha, sigma_f)
+    ts, tc = filter_spectrum(dims, target, bins, device=P.device)
+    cnt = tc[:-1].to(torch.float64)
+    T = torch.where(cnt > 0, ts[:-1] / cnt.clamp(min=1.0), torch.zeros_like(cnt))
+    mask = cnt > 0
+    mask[0] = False
+    eps = eps_rel * float(sigma_f) ** 2
+    d = torch.log(P + eps) - torch.log(T + eps)
+    return (d[mask] ** 2).mean()

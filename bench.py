@@ -11,7 +11,10 @@ Prints ONE JSON line.  Besides the headline value it carries
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample of the same workload;
   pipeline_roofline_frac  compulsory bytes of the whole pipeline / step time / 8 TB/s;
   plain_form    the same work as one call per field, and the batched speedup over it;
-  also          the 3D 256^3 x 4 workload measured the same way.
+  also          the 3D 256^3 x 4 workload measured the same way; the uneven batch of 512 fields
+                (448 2D from 64^2..1024^2, 64 3D from 64^3..128^3) through one replayed graph after
+                autotuning, with its plain form; and the 512^3 forward plus the adjoint of the
+                spectrum-matching loss.
 """
 
 import argparse
@@ -36,6 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the uneven batch and the 512^3 adjoint")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the batched 2D workload (for profiler runs)")
     ap.add_argument("--workload", default="2d_2048x2048_x16", choices=("2d_2048x2048_x16", "3d_256x256x256_x4"),
@@ -73,6 +77,16 @@ def algorithmic_bytes(dims, batch):
 # the sources that define the pipeline's kernels and their launch shapes
 PIPELINE_SOURCES = ("hu_device.hpp", "hu_common.hpp", "hu_internal.hpp", "hu_host.hpp", "hu_rows.hip", "hu_cols.hip",
                     "hu_filter.hip", "hu_bin.hip", "hu_host.hip")
+
+
+def field_bytes_min(dims):
+    """Compulsory HBM bytes of one field's whole pipeline: 2D 6 traversals + 5N, 3D 12 + 5N; a 2D
+    field whose half spectrum fits in 128 KB (one CU's LDS) could stay on chip: 5N."""
+    N = math.prod(dims)
+    Nh = N // dims[-1] * (dims[-1] // 2 + 1)
+    if len(dims) == 2 and 8 * Nh <= 128 * 1024:
+        return 5 * N
+    return (6 if len(dims) == 2 else 12) * 8 * Nh + 5 * N
 
 
 def kernel_source_hash():
@@ -145,6 +159,104 @@ def roofline_obj(cfg, prof, steps, workload):
                 kernels={k: dict(launches=v[0], mean_ms=round(v[1] / v[0], 5),
                                  gbs=round(fam_bytes.get(k, 0) / (v[1] / v[0] * 1e-3) / 1e9, 1))
                          for k, v in prof.items()}), total
+
+
+def time_uneven_batch(hf, torch, steps, warmup):
+    """The uneven batch of 512 fields (448 2D, 64 3D) through hu_pipeline_batch (one replayed
+    graph), after autotuning every shape class; and the plain form, one hu_pipeline call per
+    field with the default tiles."""
+    from paper_2509_08675_amd.workloads import c4_jobs
+    jobs = c4_jobs()
+    classes = {}
+    for j in jobs:
+        key = (tuple(j["dims"]), tuple(j["bins"]))
+        classes[key] = classes.get(key, 0) + 1
+    t0 = time.perf_counter()
+    for (dims, bins), cnt in classes.items():
+        hf.autotune(dims, cnt, bins)
+    tune_s = time.perf_counter() - t0
+    bb = hf.BatchBuffers(jobs)
+    st = hf.pipeline_batch(bb)
+    torch.cuda.synchronize()
+    if any(st):
+        raise RuntimeError("uneven batch: job status %s" % st)
+    for _ in range(warmup):
+        hf.pipeline_batch(bb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hf.pipeline_batch(bb)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    for o in bb.out:
+        hf.check_degenerate(o["stats"].view(1, 4))
+    del bb
+    plain = [hf.PipelineBuffers(j["dims"], 1, j["bins"]) for j in jobs]
+
+    def plain_step():
+        for j, b in zip(jobs, plain):
+            hf.pipeline(b, j["filt"], [j["seed"]])
+    plain_step()
+    torch.cuda.synchronize()
+    psteps = max(steps // 4, 2)
+    t0 = time.perf_counter()
+    for _ in range(psteps):
+        plain_step()
+    torch.cuda.synchronize()
+    pms = (time.perf_counter() - t0) / psteps * 1e3
+    vox = sum(math.prod(j["dims"]) for j in jobs)
+    bmin = sum(field_bytes_min(tuple(j["dims"])) for j in jobs)
+    n2 = sum(1 for j in jobs if len(j["dims"]) == 2)
+    return dict(value=round(vox / (ms * 1e-3), 1), unit="voxels/s", ms_per_step=round(ms, 4),
+                fields=len(jobs), fields_2d=n2, fields_3d=len(jobs) - n2, voxels=vox, shape_classes=len(classes),
+                bytes_min=bmin, pipeline_roofline_frac=round(bmin / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                autotune_s=round(tune_s, 2),
+                plain_form=dict(desc="one hu_pipeline call per field, default tiles", ms_per_step=round(pms, 4),
+                                value=round(vox / (pms * 1e-3), 1), batched_speedup=round(pms / ms, 3)))
+
+
+def time_adjoint(hf, torch, steps):
+    """512^3: forward (field + continuous spectrum) and the adjoint of the spectrum-matching loss."""
+    from paper_2509_08675_amd.workloads import C5
+    dims, seed, bins = tuple(C5["dims"]), C5["seed"], (C5["nr"], 1)
+    filt = C5["filt"]
+    N = math.prod(dims)
+    Nh = N // dims[-1] * (dims[-1] // 2 + 1)
+    field = torch.empty((1,) + dims, dtype=torch.float32, device="cuda")
+    wf = hf.alloc_workspace(hf.HU_OP_GEN_FIELD, dims, 1, bins)
+    wg = hf.alloc_workspace(hf.HU_OP_LOSS, dims, 1, bins)
+    out = hf.gen_field(dims, filt, [seed], cont_bins=bins, work=wf, out=field)
+    ts, tc = hf.filter_spectrum(dims, C5["target"], bins)
+    cs, cc, stt = out["cont_sum"][0], out["cont_cnt"][0], out["stats"][0]
+    cnt = cc[:-1].double()
+    P = torch.where(cnt > 0, cs[:-1] / cnt.clamp(min=1.0), torch.zeros_like(cnt))
+    T = torch.where(cnt > 0, ts[:-1] / cnt.clamp(min=1.0), torch.zeros_like(cnt))
+    mask = cnt > 0
+    mask[0] = False
+    eps = 1e-12
+    d = torch.log(P + eps) - torch.log(T + eps)
+    dL = torch.zeros_like(cs)
+    dL[:-1] = torch.where(mask, 2.0 * d / (P + eps) / mask.sum(), torch.zeros_like(d))
+    loss = float((d[mask] ** 2).mean())
+    torch.cuda.synchronize()
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k * 1e3
+    fwd = timed(lambda: hf.gen_field(dims, filt, [seed], cont_bins=bins, work=wf, out=field), steps)
+    bwd = timed(lambda: hf.spectrum_grad(dims, filt, seed, bins, dL, cs, cc, stt, work=wg), steps)
+    grad = hf.spectrum_grad(dims, filt, seed, bins, dL, cs, cc, stt, work=wg).cpu().tolist()
+    bf, bb = 64 * Nh + 4 * N, 32 * Nh
+    return dict(ms_forward=round(fwd, 4), ms_adjoint=round(bwd, 4), ms_total=round(fwd + bwd, 4),
+                forward_roofline_frac=round(bf / (fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                adjoint_roofline_frac=round(bb / (bwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                bytes_min_forward=bf, bytes_min_adjoint=bb, loss=loss,
+                grad=dict(zip(hf.THETA_NAMES, [float("%.6g" % g) for g in grad])))
 
 
 def cpu_baseline(cfg, budget_s=12.0):
@@ -373,6 +485,10 @@ def main():
                                          ms_per_step=round(ms3, 4),
                                          pipeline_roofline_frac=round(total3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                          roofline=roof3)}
+    if not args.no_extra:
+        line.setdefault("also", {})
+        line["also"]["c4_uneven_512_fields"] = time_uneven_batch(hf, torch, max(args.steps // 5, 5), 2)
+        line["also"]["3d_512cube_forward_and_adjoint"] = time_adjoint(hf, torch, max(args.steps // 5, 5))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

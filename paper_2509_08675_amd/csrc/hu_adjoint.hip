@@ -131,13 +131,9 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
   const int c = tid % C, p = tid / C;
   const int g = (int)tile * C + c;
   const bool valid = g < a.gm.ncol;
-  const int inner = a.gm.inner0;
-  const unsigned go = (unsigned)g / (unsigned)inner;
-  const float2* base = a.spec + (unsigned)(go * (L * inner) + (g - go * inner));
+  const ColIO io = col_io<L>(a.spec, a.Nh, a.gm.inner0, g, p);
   float2 v[E];
-#pragma unroll
-  for (int s = 0; s < E; ++s)
-    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] : make_float2(0.f, 0.f);
+  col_load<L, R1, P, E>(v, io);
   fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
 
   // per-bin weights into LDS (the exchange buffer is free after the transform)

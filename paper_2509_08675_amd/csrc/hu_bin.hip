@@ -24,13 +24,9 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
   const int c = tid % C, p = tid / C;
   const int g = (int)tile * C + c;
   const bool valid = g < a.gm.ncol;
-  const int inner = a.gm.inner0;
-  const unsigned go = (unsigned)g / (unsigned)inner;
-  const float2* base = a.spec + (long long)b * a.Nh + (unsigned)(go * (L * inner) + (g - go * inner));
+  const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, g, p);
   float2 v[E];
-#pragma unroll
-  for (int s = 0; s < E; ++s)
-    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] : make_float2(0.f, 0.f);
+  col_load<L, R1, P, E>(v, io);
   fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
   const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
   float* pw = reinterpret_cast<float*>(lds);

@@ -18,18 +18,11 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols(ColsArgs a) {
   const int c = tid % C, p = tid / C;
   const int g = (int)tile * C + c;
   const bool valid = g < a.ncol;
-  const int inner = a.inner;
-  const unsigned go = (unsigned)g / (unsigned)inner;
-  float2* base = a.spec + (long long)b * a.Nh + (unsigned)(go * (L * inner) + (g - go * inner));
+  const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.inner, g, p);
   float2 v[E];
-#pragma unroll
-  for (int s = 0; s < E; ++s)
-    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] : make_float2(0.f, 0.f);
+  col_load<L, R1, P, E>(v, io);
   fft_run<L, P, E, INV>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
-  if (valid) {
-#pragma unroll
-    for (int s = 0; s < E; ++s) base[(unsigned)(slot_index<L, RL, P>(s, p) * inner)] = v[s];
-  }
+  if (valid) col_store<L, RL, P, E>(v, io);
 }
 
 template <int L, int V>

@@ -248,6 +248,59 @@ __host__ __device__ constexpr size_t col_lds_bytes_t(int nb) {
              : (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4 + (size_t)nb * 8 + 8;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Global I/O through buffer resources: a 128-bit descriptor (base, size in bytes) in scalar
+// registers, a per-thread byte offset in one vector register and a uniform per-slot byte offset
+// in a scalar register, so the slots of a transform cost no vector address arithmetic.  Loads
+// beyond the size return 0 and stores beyond it are dropped.
+// ---------------------------------------------------------------------------------------------
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+using u32x2 = __attribute__((ext_vector_type(2))) unsigned int;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_load2(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store2(rsrc_t r, float2 v, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+// Column g of a column pass over one field's half spectrum: element e sits at
+// (g / inner) L inner + g mod inner + e inner -- in 2D (column groups of four, inner = 4) element
+// (e, g) at ((g >> 2) L + e) 4 + (g & 3), in 3D axis 0 (inner = ncol) at e ncol + g, in the 3D y
+// pass (inner = n_x / 2 + 1, g = z inner + m_x) within its z-plane.  Thread p of the column
+// addresses element p + o at voff + o * step.
+struct ColIO {
+  rsrc_t r;
+  unsigned voff;   // bytes, this thread's first element
+  unsigned step;   // bytes per element along axis 0 (uniform)
+};
+
+template <int L>
+__device__ __forceinline__ ColIO col_io(const float2* field_spec, long long nh, int inner, int g, int p) {
+  ColIO io;
+  io.r = make_rsrc(field_spec, (unsigned)(nh * 8));
+  const unsigned go = (unsigned)g / (unsigned)inner;
+  const unsigned col = go * (unsigned)(L * inner) + ((unsigned)g - go * (unsigned)inner);
+  io.voff = (col + (unsigned)p * (unsigned)inner) * 8u;
+  io.step = (unsigned)inner * 8u;
+  return io;
+}
+
+// the E slots of a transform whose first (load) or last (store) radix is R
+template <int L, int R, int P, int E>
+__device__ __forceinline__ void col_load(float2 (&v)[E], const ColIO& io) {
+#pragma unroll
+  for (int s = 0; s < E; ++s) v[s] = buf_load2(io.r, io.voff, (unsigned)slot_index<L, R, P>(s, 0) * io.step);
+}
+template <int L, int R, int P, int E>
+__device__ __forceinline__ void col_store(const float2 (&v)[E], const ColIO& io) {
+#pragma unroll
+  for (int s = 0; s < E; ++s) buf_store2(io.r, v[s], io.voff, (unsigned)slot_index<L, R, P>(s, 0) * io.step);
+}
+
 // per-field parameter and output accessors: the batch table when present, else the uniform
 // arguments (base pointer + field * stride)
 template <class T>

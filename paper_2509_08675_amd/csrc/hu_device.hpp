@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace hu {
 
 // ---------------------------------------------------------------------------------------------
@@ -208,19 +210,58 @@ struct RadInfo<Radices<Rs...>> {
   static constexpr int last = LastR<Rs...>::value;
 };
 
-// One Stockham stage on the registers of thread p: butterflies j = p + P b, b < E/R.
-template <int L, int R, int NS, int P, int E, bool INV>
+// ---------------------------------------------------------------------------------------------
+// Stage twiddle rows.  Stage i >= 1 of a radix list (R_0, R_1, ...) with NS_i = R_0 ... R_{i-1}
+// multiplies input r of butterfly j by exp(-+ 2 pi i r k / (NS_i R_i)), k = j mod NS_i.  Its rows
+// k = 0 .. NS_i - 1 hold rpad(R_i) consecutive complex entries (r = 0 .. rpad - 1, R rounded up to
+// even so that every row starts on 16 bytes), so one butterfly reads one row with 16-byte loads
+// from a single offset.  The table of a length L holds the rows of the forward radix list, then
+// those of its reverse (the plan of the inverse transforms); the first stage needs none.
+// ---------------------------------------------------------------------------------------------
+__host__ __device__ constexpr int rpad(int R) { return (R + 1) / 2 * 2; }
+
+template <int NS, int... Rs>
+struct TabSize;
+template <int NS>
+struct TabSize<NS> { static constexpr int value = 0; };
+template <int NS, int R, int... Rest>
+struct TabSize<NS, R, Rest...> {
+  static constexpr int value = (NS > 1 ? NS * rpad(R) : 0) + TabSize<NS * R, Rest...>::value;
+};
+template <typename A>
+struct PlanTab;
+template <int... Rs>
+struct PlanTab<Radices<Rs...>> { static constexpr int size = TabSize<1, Rs...>::value; };
+
+// complex entries of the stage table of length L (forward rows, then reversed-plan rows)
+template <int L>
+struct StageTab {
+  using F = typename Plan<L>::fwd;
+  static constexpr int fwd = PlanTab<F>::size;
+  static constexpr int total = fwd + PlanTab<Reverse<F>>::size;
+};
+
+// One Stockham stage on the registers of thread p: butterflies j = p + P b, b < E/R; the stage's
+// twiddle rows start at entry SOFF of the table.
+template <int L, int R, int NS, int P, int E, bool INV, int SOFF>
 __device__ __forceinline__ void stage_compute(float2 (&v)[E], int p, const float2* __restrict__ tw) {
 #pragma unroll
   for (int b = 0; b < E / R; ++b) {
     if constexpr (NS > 1) {
       const int j = p + P * b;
-      const int k = j % NS;
+      const unsigned k = (unsigned)(j % NS);
+      const float4* row = reinterpret_cast<const float4*>(tw) + (unsigned)(SOFF / 2) + k * (unsigned)(rpad(R) / 2);
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * k * (L / (NS * R))];
-        if (INV) w.y = -w.y;
-        v[b * R + r] = cmul(v[b * R + r], w);
+      for (int q = 0; q < rpad(R) / 2; ++q) {
+        const float4 w2 = row[q];
+        if (2 * q >= 1 && 2 * q < R) {
+          const float2 w = make_float2(w2.x, INV ? -w2.y : w2.y);
+          v[b * R + 2 * q] = cmul(v[b * R + 2 * q], w);
+        }
+        if (2 * q + 1 < R) {
+          const float2 w = make_float2(w2.z, INV ? -w2.w : w2.w);
+          v[b * R + 2 * q + 1] = cmul(v[b * R + 2 * q + 1], w);
+        }
       }
     }
     dft<R, INV>(&v[b * R]);
@@ -237,24 +278,89 @@ struct Region {
   static constexpr int value = L + (L >> 4) + 8;
 };
 
+// LDS positions of a stage's reads (element j + r L/R, j = p + P b) and writes (element
+// (j / NS) NS R + j mod NS + r NS).  When the padded position minus that of the thread's first
+// element is the same for every thread p, the stage addresses LDS from one per-thread base with
+// constant offsets (`lin`); this is checked at compile time over every p.
+template <int L, int R, int P, int E>
+struct LoadMap {
+  static constexpr int off(int p, int b, int r) { return lidx(p + P * b + r * (L / R)) - lidx(p); }
+  static constexpr bool check() {
+    for (int p = 0; p < P; ++p)
+      for (int b = 0; b < E / R; ++b)
+        for (int r = 0; r < R; ++r)
+          if (off(p, b, r) != off(0, b, r)) return false;
+    return true;
+  }
+  static constexpr bool lin = check();
+};
+
+template <int R, int NS, int P, int E>
+struct StoreMap {
+  static constexpr int base(int j) { return (j / NS) * NS * R + (j % NS); }
+  static constexpr int off(int p, int b, int r) { return lidx(base(p + P * b) + r * NS) - lidx(base(p)); }
+  static constexpr bool check() {
+    for (int p = 0; p < P; ++p)
+      for (int b = 0; b < E / R; ++b)
+        for (int r = 0; r < R; ++r)
+          if (off(p, b, r) != off(0, b, r)) return false;
+    return true;
+  }
+  static constexpr bool lin = check();
+};
+
 template <int L, int R, int NS, int P, int E>
 __device__ __forceinline__ void stage_store(const float2 (&v)[E], float2* lds, int p) {
+  using M = StoreMap<R, NS, P, E>;
+  if constexpr (M::lin) {
+    float2* sp = lds + lidx(M::base(p));
 #pragma unroll
-  for (int b = 0; b < E / R; ++b) {
-    const int j = p + P * b;
-    const int base = (j / NS) * NS * R + (j % NS);
+    for (int b = 0; b < E / R; ++b)
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[lidx(base + r * NS)] = v[b * R + r];
+      for (int r = 0; r < R; ++r) sp[M::off(0, b, r)] = v[b * R + r];
+  } else {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+      const int base = M::base(p + P * b);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lidx(base + r * NS)] = v[b * R + r];
+    }
+  }
+}
+
+// element j + r L/R of slot b R + r (the read pattern of a stage, and the natural-order pattern a
+// transform starts from or ends in)
+template <int L, int R, int P, int E>
+__device__ __forceinline__ void stage_load(float2 (&v)[E], const float2* lds, int p) {
+  using M = LoadMap<L, R, P, E>;
+  if constexpr (M::lin) {
+    const float2* lp = lds + lidx(p);
+#pragma unroll
+    for (int b = 0; b < E / R; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b * R + r] = lp[M::off(0, b, r)];
+  } else {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b * R + r] = lds[lidx(p + P * b + r * (L / R))];
   }
 }
 
 template <int L, int R, int P, int E>
-__device__ __forceinline__ void stage_load(float2 (&v)[E], const float2* lds, int p) {
+__device__ __forceinline__ void slot_store(const float2 (&v)[E], float2* lds, int p) {
+  using M = LoadMap<L, R, P, E>;
+  if constexpr (M::lin) {
+    float2* lp = lds + lidx(p);
 #pragma unroll
-  for (int b = 0; b < E / R; ++b) {
-    const int j = p + P * b;
+    for (int b = 0; b < E / R; ++b)
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[b * R + r] = lds[lidx(j + r * (L / R))];
+      for (int r = 0; r < R; ++r) lp[M::off(0, b, r)] = v[b * R + r];
+  } else {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lidx(p + P * b + r * (L / R))] = v[b * R + r];
   }
 }
 
@@ -264,23 +370,28 @@ __device__ __forceinline__ int slot_index(int i, int p) {
   return p + P * (i / R) + (i % R) * (L / R);
 }
 
-template <int L, int P, int E, bool INV, int NS, int R, int... Rest>
+template <int L, int P, int E, bool INV, int NS, int SOFF, int R, int... Rest>
 __device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int p, const float2* __restrict__ tw) {
-  stage_compute<L, R, NS, P, E, INV>(v, p, tw);
+  stage_compute<L, R, NS, P, E, INV, SOFF>(v, p, tw);
   if constexpr (sizeof...(Rest) > 0) {
     constexpr int R2 = FirstR<Rest...>::value;
     __syncthreads();
     stage_store<L, R, NS, P, E>(v, lds, p);
     __syncthreads();
     stage_load<L, R2, P, E>(v, lds, p);
-    fft_stages<L, P, E, INV, NS * R, Rest...>(v, lds, p, tw);
+    fft_stages<L, P, E, INV, NS * R, (NS > 1 ? SOFF + NS * rpad(R) : SOFF), Rest...>(v, lds, p, tw);
   }
 }
 
+// The transform with radix list Rs (the forward plan of L or its reverse); tw = the stage table
+// of L.
 template <int L, int P, int E, bool INV, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[E], float2* lds, int p,
                                         const float2* __restrict__ tw) {
-  fft_stages<L, P, E, INV, 1, Rs...>(v, lds, p, tw);
+  using F = typename Plan<L>::fwd;
+  constexpr bool is_fwd = std::is_same<Radices<Rs...>, F>::value;
+  static_assert(is_fwd || std::is_same<Radices<Rs...>, Reverse<F>>::value, "radix list is not a plan of L");
+  fft_stages<L, P, E, INV, 1, (is_fwd ? 0 : StageTab<L>::fwd), Rs...>(v, lds, p, tw);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -25,13 +25,9 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   const int c = tid % C, p = tid / C;
   const int g = (int)tile * C + c;
   const bool valid = g < a.gm.ncol;
-  const int inner = a.gm.inner0;
-  const unsigned go = (unsigned)g / (unsigned)inner;
-  float2* base = a.spec + (long long)b * a.Nh + (unsigned)(go * (L * inner) + (g - go * inner));
+  const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, g, p);
   float2 v[E];
-#pragma unroll
-  for (int s = 0; s < E; ++s)
-    v[s] = valid ? base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] : make_float2(0.f, 0.f);
+  col_load<L, R1, P, E>(v, io);
   fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
 
   // ---- filter and per-thread statistics
@@ -89,10 +85,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
 
   // ---- inverse transform along axis 0 (first radix = last forward radix: no exchange needed)
   fft_run<L, P, E, true>(RadI{}, v, lds + c * Region<L>::value, p, a.tw);
-  if (valid) {
-#pragma unroll
-    for (int s = 0; s < E; ++s) base[(unsigned)(slot_index<L, R1, P>(s, p) * inner)] = v[s];
-  }
+  if (valid) col_store<L, R1, P, E>(v, io);
 }
 
 // ---------------------------------------------------------------------------------------------

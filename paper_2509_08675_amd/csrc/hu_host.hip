@@ -190,13 +190,61 @@ int profile_collect(std::vector<std::string>& names, std::vector<long long>& lau
 }
 
 // ---------------------------------------------------------------------------------------------
+// Stage twiddle table of a length L (layout in hu_device.hpp, StageTab): for the forward radix
+// list and then its reverse, the rows of every stage i >= 1, entry (k, r) = exp(-2 pi i t / L)
+// with t = r k L / (NS_i R_i), FP64 rounded once to FP32.
+template <int... Rs>
+static std::vector<int> radix_vec(Radices<Rs...>) { return {Rs...}; }
+
+static void append_stage_rows(int L, const std::vector<int>& rad, std::vector<float2>& h) {
+  int ns = 1;
+  for (size_t i = 0; i < rad.size(); ++i) {
+    const int R = rad[i];
+    if (ns > 1) {
+      for (int k = 0; k < ns; ++k)
+        for (int r = 0; r < rpad(R); ++r) {
+          const long long t = (long long)r * k * (L / (ns * R));
+          const double a = 2.0 * M_PI * (double)t / (double)L;
+          h.push_back(make_float2((float)std::cos(a), (float)-std::sin(a)));
+        }
+    }
+    ns *= R;
+  }
+}
+
+template <int L>
+static int make_stage_table_L(float2** out) {
+  using F = typename Plan<L>::fwd;
+  std::vector<float2> h;
+  append_stage_rows(L, radix_vec(F{}), h);
+  if ((int)h.size() != StageTab<L>::fwd) return HU_ERR_HIP;
+  append_stage_rows(L, radix_vec(Reverse<F>{}), h);
+  if ((int)h.size() != StageTab<L>::total) return HU_ERR_HIP;
+  h.push_back(make_float2(0.f, 0.f));           // never empty (lengths with one stage)
+  float2* d = nullptr;
+  if (hipMalloc(&d, sizeof(float2) * h.size()) != hipSuccess) return HU_ERR_HIP;
+  if (hipMemcpy(d, h.data(), sizeof(float2) * h.size(), hipMemcpyHostToDevice) != hipSuccess) return HU_ERR_HIP;
+  *out = d;
+  return HU_OK;
+}
+
+static int make_stage_table(int L, float2** out) {
+  switch (L) {
+#define X(LL) case LL: return make_stage_table_L<LL>(out);
+    X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768)
+    X(1024) X(1536) X(2048)
+#undef X
+    default: return HU_ERR_SIZE;
+  }
+}
+
 int get_tw(int L, const float2** tw) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto key = std::make_pair(current_device(), L);
   auto it = g_tw.find(key);
   if (it == g_tw.end()) {
     float2* d;
-    int rc = make_table(L, L, &d);
+    int rc = make_stage_table(L, &d);
     if (rc) return rc;
     it = g_tw.emplace(key, d).first;
   }

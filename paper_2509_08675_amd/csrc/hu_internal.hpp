@@ -54,7 +54,7 @@ struct RowsArgs {
   int nb;                  // with io: bins + 1, for clearing the per-field spectra
   const uint32_t* cnt_src; // with io: precomputed bin counts (nb uint64)
   const void* src;         // real input for the load variants, [B][N]
-  const float2* tw;        // exp(-2 pi i t / L), t < L
+  const float2* tw;        // stage twiddle table of the row length (StageTab layout)
   const float2* tw2;       // exp(-2 pi i k / 2L), k < L
   FillSpan fill[6];
   int fill_spans;
@@ -66,7 +66,7 @@ struct ColsArgs {
   long long Nh;
   int ncol;                // transforms per field
   int inner;               // element stride (complex) along the axis
-  const float2* tw;
+  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
 };
 
 struct Axis0Geom {
@@ -90,7 +90,7 @@ struct FilterArgs {
   BinDev bd;
   int nb;                  // bins + 1 (corner slot)
   const uint16_t* table;   // bin of each mode, [ncol][n0], or null (computed)
-  const float2* tw;
+  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
   double* partials;        // [B][tiles][4]: sum w |F|^2, Re F(0), max ln chi
   double* cont_sum;        // [B][nb] raw sums of w |F|^2, or null (counts are filled from the geometry)
   int want_bins;           // accumulate the continuous spectrum (LDS sized for it)
@@ -116,7 +116,7 @@ struct BinArgs {
   BinDev bd;
   int nb;
   const uint16_t* table;
-  const float2* tw;
+  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
   double* sum;
   const FieldIO* io;       // per-field +-1 spectrum output (batch path) or null
 };
@@ -134,7 +134,7 @@ struct RowsZArgs {
   float2* spec;
   long long Nh, N, nrows;
   int tiled;
-  const float2* tw;
+  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
   const float2* tw2;
   const double* fstats;
   float* field;
@@ -164,7 +164,7 @@ struct AdjointArgs {
   BinDev bd;
   int nb;
   const uint16_t* table;   // bin of each mode or null
-  const float2* tw;
+  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
   const double* coef;      // [nb + 1]: beta_b per bin, then gamma
   double* partials;        // [tiles][8]: the 7 gradient partial sums
 };

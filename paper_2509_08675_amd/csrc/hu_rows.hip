@@ -120,12 +120,10 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
 
   float2 v[E];
   float2* lrow = lds + c * RS;
-#pragma unroll
-  for (int s = 0; s < E; ++s) v[s] = lrow[lidx(slot_index<L, R1, P>(s, p))];
+  stage_load<L, R1, P, E>(v, lrow, p);
   fft_run<L, P, E, false>(Rad{}, v, lrow, p, a.tw);
   __syncthreads();
-#pragma unroll
-  for (int s = 0; s < E; ++s) lrow[lidx(slot_index<L, RL, P>(s, p))] = v[s];
+  slot_store<L, RL, P, E>(v, lrow, p);
   __syncthreads();
   twist_store_rows<L, C, T, TILED>(lds, a.tw2, a.spec + (long long)b * a.Nh, row0, rows_here, a.nrows, tid);
 }
@@ -226,8 +224,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
     fft_run<L, P, E, false>(RadF{}, v, lrow, p, a.tw);
     __syncthreads();
     constexpr int RLF = RadInfo<RadF>::last;
-#pragma unroll
-    for (int s = 0; s < E; ++s) lrow[lidx(slot_index<L, RLF, P>(s, p))] = v[s];
+    slot_store<L, RLF, P, E>(v, lrow, p);
     __syncthreads();
     twist_store_rows<L, C, T, TILED>(lds, a.tw2, spec_f, row0, rows_here, a.nrows, tid);
     if (tid == 0 && cout) {

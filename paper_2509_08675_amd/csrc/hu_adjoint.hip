@@ -151,7 +151,7 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
       const int e = slot_index<L, RL, P>(s, p);
       float dH[7];
       const float Hs = hsym_partials<NDIM>(f, a.width, a.gm, cc, e, dH);
-      const int bin = a.table ? (int)a.table[(unsigned)(g * L + e)] : mode_bin(a.bd, a.gm, cc, e);
+      const int bin = (int)a.table[(unsigned)(g * L + e)];
       const float omega = (float)(cf[bin] - gamma);
       const float W2 = v[s].x * v[s].x + v[s].y * v[s].y;
       const float cfac = cc.wm * omega * 2.0f * Hs * W2;
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(FS_THREADS) k_filter_spectrum(FilterSpecArgs a
       float lnc;
       const float H = amp_sym<NDIM>(a.filt, a.gm, cc, e, lnc);
       const double val = (double)(cc.wm * H * H);
-      const int bin = a.table ? (int)a.table[i] : mode_bin(a.bd, a.gm, cc, e);
+      const int bin = (int)a.table[i];
       tot += val;
       if (bin != cur) {
         if (cur >= 0) atomicAdd(hs + cur, run);

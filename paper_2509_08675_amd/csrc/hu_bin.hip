@@ -37,7 +37,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
     pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = wm * (v[s].x * v[s].x + v[s].y * v[s].y);
   for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
   __syncthreads();
-  if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, a.bd, a.gm, g, p);
+  if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, g, p);
   __syncthreads();
   double* out = a.io ? a.io[b].pm1_sum : field_ptr(a.sum, a.nb, b);
   if (out) hist_flush(hs, a.nb, 1.0 / (double)a.N, out, tid, T);

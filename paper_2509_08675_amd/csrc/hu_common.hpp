@@ -183,47 +183,35 @@ __device__ __forceinline__ int mode_bin(const BinDev& bd, const Axis0Geom& gm, c
 // ---------------------------------------------------------------------------------------------
 // Run-length binning.  The per-mode power values w |X|^2 of the C columns sit in LDS (padded
 // layout pw_index).  Thread (c, p) walks the E consecutive modes e = p E .. p E + E - 1 of its
-// column, reads their bins (precomputed table, column-major [g][L], or computed), sums in FP64
+// column, reads their bins from the per-geometry table (column-major [g][L], u16), sums in FP64
 // while the bin stays the same and adds each run to the LDS histogram with one atomic.
 // ---------------------------------------------------------------------------------------------
 template <int L, int E>
-__device__ __forceinline__ void bin_runs(const float* pw, double* hs, const uint16_t* __restrict__ table,
-                                         const BinDev& bd, const Axis0Geom& gm, int g, int p) {
+__device__ __forceinline__ void bin_runs(const float* pw, double* hs, const uint16_t* __restrict__ table, int g, int p) {
   const int e0 = p * E;
-  int bins[E];
-  if (table) {
-    const uint16_t* t = table + (unsigned)(g * L + e0);
-    if constexpr ((L % 8) == 0 && (E % 8) == 0) {
-#pragma unroll
-      for (int q = 0; q < E / 8; ++q) {
-        const uint4 w = *reinterpret_cast<const uint4*>(t + 8 * q);
-        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          bins[8 * q + 2 * h] = (int)(ws[h] & 0xFFFFu);
-          bins[8 * q + 2 * h + 1] = (int)(ws[h] >> 16);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < E; ++i) bins[i] = t[i];
-    }
-  } else {
-    const ColCoord cc = col_coord(gm, g);
-#pragma unroll
-    for (int i = 0; i < E; ++i) bins[i] = mode_bin(bd, gm, cc, e0 + i);
-  }
-  int cur = bins[0];
+  const uint16_t* t = table + (unsigned)(g * L + e0);
+  int cur = -1;
   double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const double v = (double)pw[pw_index(e0 + i)];
-    if (bins[i] != cur) {
-      atomicAdd(hs + cur, acc);
-      cur = bins[i];
+  auto step = [&](int bin, int e) {
+    const double v = (double)pw[pw_index(e)];
+    if (bin != cur) {
+      if (cur >= 0) atomicAdd(hs + cur, acc);
+      cur = bin;
       acc = 0.0;
     }
     acc += v;
+  };
+  if constexpr ((L % 8) == 0 && (E % 8) == 0) {
+#pragma unroll
+    for (int q = 0; q < E / 8; ++q) {
+      const uint4 w = *reinterpret_cast<const uint4*>(t + 8 * q);
+      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int h = 0; h < 8; ++h) step((int)((ws[h >> 1] >> (16 * (h & 1))) & 0xFFFFu), e0 + 8 * q + h);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < E; ++i) step((int)t[i], e0 + i);
   }
   atomicAdd(hs + cur, acc);
 }

@@ -37,7 +37,14 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   const ColCoord cc = col_coord(a.gm, valid ? g : 0);
   double gsum = 0.0, f0 = 0.0;
   float lmax = -1.0e30f;
-  float pwv[E];
+  // the exchange buffer is free once every thread has its transform in registers: the power
+  // values of the continuous spectrum go to LDS as they are computed
+  float* pw = reinterpret_cast<float*>(lds);
+  double* hs = reinterpret_cast<double*>(pw + ((C * LP + 1) & ~1));
+  if (do_bins) {
+    __syncthreads();
+    for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
+  }
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const int e = slot_index<L, RL, P>(s, p);
@@ -46,32 +53,25 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
     const float2 F = cscale(v[s], H);
     v[s] = F;
     const float m2 = cc.wm * (F.x * F.x + F.y * F.y);
-    pwv[s] = valid ? m2 : 0.0f;
+    if (do_bins) pw[c * LP + pw_index(e)] = valid ? m2 : 0.0f;
     if (valid) {
       gsum += (double)m2;
       lmax = fmaxf(lmax, lnc);
       if (g == 0 && e == 0) f0 = (double)F.x;
     }
   }
-  // ---- continuous-spectrum histogram (run-length over contiguous modes of each column)
-  if (do_bins) {
-    float* pw = reinterpret_cast<float*>(lds);
-    double* hs = reinterpret_cast<double*>(pw + ((C * LP + 1) & ~1));
-    __syncthreads();                              // the exchange buffer is free from here
-#pragma unroll
-    for (int s = 0; s < E; ++s) pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = pwv[s];
-    for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
-    __syncthreads();
-    if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, a.bd, a.gm, g, p);
-    __syncthreads();
-    hist_flush(hs, a.nb, 1.0, cont_out, tid, T);
-  }
   // ---- workgroup statistics -> partials[b][tile] (reduced by k_finalize after this kernel)
   gsum = wave_sum(gsum);
   lmax = wave_max(lmax);
   f0 = wave_sum(f0);
   if ((tid & 63) == 0) { red_d[tid >> 6] = gsum; red_f[tid >> 6] = lmax; red_d0[tid >> 6] = f0; }
+  // ---- continuous-spectrum histogram (run-length over contiguous modes of each column)
   __syncthreads();
+  if (do_bins) {
+    if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, g, p);
+    __syncthreads();
+    hist_flush(hs, a.nb, 1.0, cont_out, tid, T);
+  }
   if (tid == 0) {
     double gs = 0.0, fz = 0.0;
     float lm = -1.0e30f;

@@ -386,7 +386,7 @@ int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t
   const int nb = bins.n_radial * bins.n_angular + 1;
   BinGeo geo{nullptr, nullptr};
   HU_HIP(hipMalloc(&geo.counts, sizeof(unsigned long long) * nb));
-  if ((size_t)g.Nh * sizeof(uint16_t) <= ((size_t)64 << 20)) HU_HIP(hipMalloc(&geo.table, sizeof(uint16_t) * g.Nh));
+  HU_HIP(hipMalloc(&geo.table, sizeof(uint16_t) * g.Nh));
   HU_HIP(launch_zero_u64(reinterpret_cast<uint64_t*>(geo.counts), nb, st));
   BinGeomArgs ba{};
   ba.Nh = g.Nh;

@@ -44,7 +44,7 @@ struct Layout {
 };
 
 struct BinGeo {
-  uint16_t* table;               // [ncol][n0] bin of each mode, or null (computed in the kernels)
+  uint16_t* table;               // [ncol][n0] bin of each mode
   unsigned long long* counts;    // [nb] modes per bin with multiplicity
 };
 

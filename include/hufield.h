@@ -14,7 +14,8 @@
  * Grid: hu_dims.n[0] is the slowest axis and n[ndim-1] = n_x the fastest (row-major).  2D is
  *   (n_y, n_x), 3D is (n_z, n_y, n_x).  Each n must be 2^k (4..2048) or 3*2^k (6..768), and n_x/2
  *   must also be one of the supported lengths (so n_x >= 4).  A field holds fewer than 2^31
- *   voxels (in-field offsets are 32-bit), so e.g. 1024^3 is accepted and 2048^3 is not.
+ *   voxels and its FP32 half spectrum (8 N/n_x (n_x/2+1) bytes) is smaller than 4 GiB (in-field
+ *   offsets are 32-bit), so e.g. 1024^2 x 768 is accepted and 1024^3 is not.
  * Wavenumbers: kappa_i = 2 m~_i / n_i in units of the Nyquist wavenumber (m~ the signed index).
  * Noise: voxel i (row-major linear index within a field) takes normal z_{i mod 4} of the
  *   Philox4x32-10 block i // 4 with key (seed lo, seed hi) and counter (block lo, block hi, 0, 0);

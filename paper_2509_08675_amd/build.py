@@ -20,6 +20,9 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions stay off: the compiler must not form v_pk_* FP32 ops
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # no automatic multiply-add contraction: a formula rounds the same way in every
+         # instantiation (tile widths, batch layouts); the kernels write their fmaf explicitly
+         "-ffp-contract=off",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

@@ -351,7 +351,7 @@ const char* hu_strerror(int code) {
   switch (code) {
     case HU_OK: return "ok";
     case HU_ERR_ARG: return "invalid argument";
-    case HU_ERR_SIZE: return "grid size outside the supported set (2^k in 4..2048, 3*2^k in 6..768 per axis, N < 2^31)";
+    case HU_ERR_SIZE: return "grid size outside the supported set (2^k in 4..2048, 3*2^k in 6..768 per axis, N < 2^31, half spectrum < 4 GiB)";
     case HU_ERR_ALIGN: return "misaligned pointer (arrays need 16 bytes, workspace 256 bytes)";
     case HU_ERR_WORKSPACE: return "workspace smaller than hu_workspace_size";
     case HU_ERR_DEGENERATE: return "filter has no support on the lattice (max ln chi < -80)";

@@ -244,6 +244,7 @@ __host__ __device__ constexpr size_t col_lds_bytes_t(int nb) {
 // ---------------------------------------------------------------------------------------------
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 using u32x2 = __attribute__((ext_vector_type(2))) unsigned int;
+using u32x4 = __attribute__((ext_vector_type(4))) unsigned int;
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);

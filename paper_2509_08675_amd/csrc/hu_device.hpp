@@ -22,8 +22,10 @@ namespace hu {
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// The library is built without automatic multiply-add contraction, so that every instantiation
+// of a formula rounds the same way; the fused forms used are written out.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
@@ -57,7 +59,7 @@ __device__ __forceinline__ float2 mul_w16(float2 a) {
   (void)PI;
   // forward: exp(-i t) = (c, -s); inverse: (c, +s), with (c, s) = (cos t, sin t)
   const float sy = INV ? s : -s;
-  return make_float2(a.x * c - a.y * sy, a.x * sy + a.y * c);
+  return make_float2(fmaf(a.x, c, -(a.y * sy)), fmaf(a.x, sy, a.y * c));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -84,7 +86,7 @@ template <bool INV>
 __device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
   const float h = 0.86602540378443864676f;  // sqrt(3)/2
   float2 t = cadd(a1, a2), u = csub(a1, a2);
-  float2 m = make_float2(a0.x - 0.5f * t.x, a0.y - 0.5f * t.y);
+  float2 m = make_float2(fmaf(-0.5f, t.x, a0.x), fmaf(-0.5f, t.y, a0.y));
   float2 v = cscale(mul_mi<INV>(u), h);
   a0 = cadd(a0, t);
   a1 = cadd(m, v);
@@ -463,8 +465,8 @@ __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2
 // The largest ratio is 1, so only the other one (2D) or two (3D) need a power.
 template <int NDIM>
 __device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, float kz) {
-  const float kxr = f.cr * kx + f.sr * ky;
-  const float kyr = -f.sr * kx + f.cr * ky;
+  const float kxr = fmaf(f.cr, kx, f.sr * ky);
+  const float kyr = fmaf(-f.sr, kx, f.cr * ky);
   const float ux = fabsf(kxr) * f.ia, uy = fabsf(kyr) * f.ib;
   float um, S;
   if constexpr (NDIM == 2) {
@@ -483,10 +485,10 @@ __device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, fl
     const float r1 = mid * inv, r2 = lo * inv;
     S = 1.0f + (r1 > 0.0f ? hw_exp2(f.p * hw_log2(r1)) : 0.0f) + (r2 > 0.0f ? hw_exp2(f.p * hw_log2(r2)) : 0.0f);
   }
-  const float log2K = hw_log2(um) + hw_log2(S) * f.ip;
+  const float log2K = fmaf(hw_log2(S), f.ip, hw_log2(um));
   const float K = hw_exp2(log2K);
   const float d = K - f.k0;
-  return f.alpha * (log2K * 0.69314718055994531f) - d * d * f.inv2w2 - f.lnchimax;
+  return fmaf(f.alpha, log2K * 0.69314718055994531f, -fmaf(d * d, f.inv2w2, f.lnchimax));
 }
 
 // exp(x / 2) for ln chi -> amplitude

@@ -286,6 +286,7 @@ int make_geom(const hu_dims& d, Geom* g) {
   g->tiled = d.ndim == 2 ? 1 : 0;
   g->Nhp = g->tiled ? g->nrows * ((g->nxh + 3) / 4 * 4) : g->Nh;
   if (g->N >= (1LL << 31)) return HU_ERR_SIZE;      // in-field offsets are 32-bit
+  if (g->Nhp * 8 >= (1LL << 32)) return HU_ERR_SIZE; // byte offsets within one field's half spectrum
   return HU_OK;
 }
 

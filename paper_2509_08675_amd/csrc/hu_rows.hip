@@ -8,45 +8,155 @@
 //              and the real-to-complex transform of the +-1 row written back in place.
 //
 // Half-spectrum layout seen by the row passes: element k of row r sits at
-//   (k / TW) * (nrows * TW) + r * TW + (k % TW),
-// TW = 4 for 2D grids (column groups of four, so that a 4-column tile of the axis-0 pass and a
-// 4-row tile of these passes both move whole 128-byte lines) and TW = n_x/2 + 1 for 3D grids
-// (plain row-major).  Global loads and stores of the half spectrum walk this layout in address
-// order, decoupled from the FFT's thread mapping, through LDS.
+//   2D (column groups of four): (k >> 2) (nrows 4) + 4 r + (k & 3);
+//   3D (row-major):             r (L + 1) + k.
+// The C rows of a tile therefore occupy, in 2D, one contiguous run of 4C elements per group of
+// four k (so a 4-row tile and a 4-column tile of the axis-0 pass both move whole 128-byte
+// lines), and in 3D one contiguous run of C (L + 1) elements.  Global loads and stores walk these
+// runs in address order through buffer descriptors, decoupled from the FFT's thread mapping by
+// LDS; the walk advances by constant steps, so no per-element division or 64-bit address is
+// formed.
 #include "hu_common.hpp"
 
 namespace hu {
 
-template <int L, bool TILED>
-struct RowIO {
-  static constexpr int TW = TILED ? 4 : L + 1;
-  static constexpr int NG = (L + 1 + TW - 1) / TW;   // column groups
+// Address-order walk over the half rows X[0..L] of a tile.  Unit u of the tile covers element k
+// of tile row cc at element offset goff from the tile's first element (2D: the first run of the
+// tile; 3D: the tile's first row).  Each thread visits ITERS units with compile-time strides, so
+// the walk unrolls and every global load of a thread is in flight at once.
+template <int L, int C, int T, bool TILED>
+struct RowWalk {
+  static constexpr int GS = TILED ? 4 * C : L + 1;   // elements per run
+  static constexpr int NG = TILED ? L / 4 + 1 : C;   // runs per tile
+  static constexpr int NU = NG * GS;
+  static constexpr int PR = T / C;                   // threads per row
+  // 2D steady: each thread keeps one position w in the 4C-element run and steps over runs;
+  // 3D: the threads of row cc walk its L + 1 contiguous elements
+  static constexpr bool STEADY = TILED && (T % GS) == 0;
+  static constexpr int QS = STEADY ? T / GS : 1;     // runs per sweep
+  static constexpr int ITERS = STEADY ? (NG + QS - 1) / QS : (!TILED ? (L + 1 + PR - 1) / PR : (NU + T - 1) / T);
+
+  // unit `it` of thread tid: tile row, element k, element offset; false when outside the tile
+  __device__ __forceinline__ static bool unit(int tid, int it, unsigned run_stride, int rows_here, int& cc, int& k,
+                                              unsigned& goff) {
+    if constexpr (STEADY) {
+      const int w = tid % GS;
+      const int q = tid / GS + it * QS;
+      cc = w >> 2;
+      k = 4 * q + (w & 3);
+      goff = (unsigned)q * run_stride + (unsigned)w;
+      return q < NG && k <= L && cc < rows_here;
+    } else if constexpr (!TILED) {
+      cc = tid / PR;
+      k = tid % PR + it * PR;
+      goff = (unsigned)(cc * (L + 1) + k);
+      return k <= L && cc < rows_here;
+    } else {
+      const int u = tid + it * T;
+      const int q = u / GS, w = u - q * GS;
+      cc = w >> 2;
+      k = 4 * q + (w & 3);
+      goff = (unsigned)q * run_stride + (unsigned)w;
+      return u < NU && k <= L && cc < rows_here;
+    }
+  }
 };
 
 // R2C split twist of every row of the tile from Z in LDS (padded, natural order) to the half
 // spectrum, in address order:
 //   X[k] = (Z[k] + Z*[L-k])/2 - (i/2) e^{-2 pi i k / 2L} (Z[k] - Z*[L-k]),  X[L] = Re Z[0] - Im Z[0].
 template <int L, int C, int T, bool TILED>
-__device__ __forceinline__ void twist_store_rows(const float2* lds, const float2* __restrict__ tw2, float2* spec_f,
-                                                 long long row0, int rows_here, long long nrows, int tid) {
-  constexpr int TW = RowIO<L, TILED>::TW, NG = RowIO<L, TILED>::NG, RS = Region<L>::value;
-  constexpr int PG = C * TW;
-  for (int u = tid; u < NG * PG; u += T) {
-    const int q = u / PG, w = u - q * PG, cc = w / TW, kk = w - cc * TW;
-    const int k = q * TW + kk;
-    if (k > L || cc >= rows_here) continue;
+__device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, rsrc_t spec, unsigned tile_off,
+                                                 unsigned run_stride, int rows_here, int tid) {
+  using W = RowWalk<L, C, T, TILED>;
+  constexpr int RS = Region<L>::value;
+  float2 w[W::ITERS];
+#pragma unroll
+  for (int it = 0; it < W::ITERS; ++it) {          // the twiddles first: all loads in flight together
+    int cc, k;
+    unsigned goff;
+    const bool in = W::unit(tid, it, run_stride, rows_here, cc, k, goff);
+    w[it] = buf_load2(tw2, (unsigned)(in && k < L ? k : 0) * 8u, 0);
+  }
+#pragma unroll
+  for (int it = 0; it < W::ITERS; ++it) {
+    int cc, k;
+    unsigned goff;
+    if (!W::unit(tid, it, run_stride, rows_here, cc, k, goff)) continue;
     const float2* lz = lds + cc * RS;
-    const float2 zk = lz[lidx(k == L ? 0 : k)];
     float2 X;
     if (k == L) {
-      X = make_float2(zk.x - zk.y, 0.0f);
+      const float2 z0 = lz[0];
+      X = make_float2(z0.x - z0.y, 0.0f);
     } else {
-      const float2 zm = cconj(lz[lidx((L - k) % L)]);
+      const float2 zk = lz[lidx(k)];
+      const float2 zm = cconj(lz[lidx(k == 0 ? 0 : L - k)]);
       const float2 A = cadd(zk, zm), B = csub(zk, zm);
-      X = cscale(cadd(A, mul_mi<false>(cmul(tw2[k], B))), 0.5f);
+      X = cscale(cadd(A, mul_mi<false>(cmul(w[it], B))), 0.5f);
     }
-    spec_f[((long long)q * nrows + row0 + cc) * TW + kk] = X;
+    buf_store2(spec, X, (tile_off + goff) * 8u, 0);
   }
+}
+
+// The tile's half rows X[0..L] from the half spectrum into LDS (padded, natural order), in
+// address order; X[0] and X[L] are made real (the other axes' inverse transforms leave them so up
+// to rounding).
+template <int L, int C, int T, bool TILED>
+__device__ __forceinline__ void load_rows(float2* lds, rsrc_t spec, unsigned tile_off, unsigned run_stride,
+                                          int rows_here, int tid) {
+  using W = RowWalk<L, C, T, TILED>;
+  constexpr int RS = Region<L>::value;
+  float2 x[W::ITERS];
+#pragma unroll
+  for (int it = 0; it < W::ITERS; ++it) {
+    int cc, k;
+    unsigned goff;
+    const bool in = W::unit(tid, it, run_stride, rows_here, cc, k, goff);
+    x[it] = buf_load2(spec, in ? (tile_off + goff) * 8u : 0xFFFFFFF0u, 0);   // outside: past the end, reads 0
+  }
+#pragma unroll
+  for (int it = 0; it < W::ITERS; ++it) {
+    int cc, k;
+    unsigned goff;
+    if (!W::unit(tid, it, run_stride, rows_here, cc, k, goff)) continue;
+    float2 v = x[it];
+    if (k == 0 || k == L) v.y = 0.0f;
+    lds[cc * RS + lidx(k)] = v;
+  }
+}
+
+// LDS positions of element L - (p + P b + r L/R): the mirrored read of the C2R pre-twist, from one
+// per-thread base when the offsets are thread-independent (checked at compile time).
+template <int L, int R, int P, int E>
+struct MirrorMap {
+  static constexpr int off(int p, int b, int r) { return lidx(L - (p + P * b + r * (L / R))) - lidx(L - p); }
+  static constexpr bool check() {
+    for (int p = 0; p < P; ++p)
+      for (int b = 0; b < E / R; ++b)
+        for (int r = 0; r < R; ++r)
+          if (off(p, b, r) != off(0, b, r)) return false;
+    return true;
+  }
+  static constexpr bool lin = check();
+};
+
+// Tile geometry of the half spectrum: the element offset of the tile's first element and the
+// element stride between consecutive runs.
+template <bool TILED, int L>
+__device__ __forceinline__ void tile_geom(long long row0, long long nrows, unsigned& tile_off, unsigned& run_stride) {
+  if constexpr (TILED) {
+    tile_off = (unsigned)(row0 * 4);
+    run_stride = (unsigned)(nrows * 4);
+  } else {
+    tile_off = (unsigned)(row0 * (L + 1));
+    run_stride = 0u;
+  }
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // grid (ceil(nrows / C), B), block C * P; thread (c, p) = (tid / P, tid % P) transforms row c.
@@ -90,17 +200,36 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
   const int nv = rows_here * 2 * L;
   if constexpr (SRC == SRC_NOISE) {
     // voxel i of the field takes normal i mod 4 of Philox block i / 4
-    const uint64_t seed = a.io ? a.io[b].seed : a.seeds[b];
-    const long long m0 = v0 >> 2, m1 = (v0 + nv + 3) >> 2;
-    for (long long m = m0 + tid; m < m1; m += T) {
-      float z[4];
-      noise4((uint64_t)m, seed, z);
+    uint64_t seed;
+    if (a.io) seed = a.io[b].seed;
+    else seed = a.seeds[b];
+    seed = uniform_u64(seed);
+    if constexpr ((L % 2) == 0) {
+      // rows of 2L voxels, a multiple of 4: each block lies in one row and fills complex
+      // elements 2j, 2j + 1 of it, which are adjacent in LDS (2j + 1 never starts a padded group)
+      constexpr int BPR = L / 2;                    // blocks per row
+      const uint64_t m0 = (uint64_t)(v0 >> 2);
+      const int nblk = rows_here * BPR;
+      for (int i = tid; i < nblk; i += T) {
+        float z[4];
+        noise4(m0 + (uint64_t)i, seed, z);
+        const int rc = i / BPR, j = i - rc * BPR;
+        float2* d = lds + rc * RS + lidx(2 * j);
+        d[0] = make_float2(z[0], z[1]);
+        d[1] = make_float2(z[2], z[3]);
+      }
+    } else {
+      const long long m0 = v0 >> 2, m1 = (v0 + nv + 3) >> 2;
+      for (long long m = m0 + tid; m < m1; m += T) {
+        float z[4];
+        noise4((uint64_t)m, seed, z);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int v = (int)(4 * m + q - v0);
-        if (v >= 0 && v < nv) {
-          const int rc = v / (2 * L), x = v - rc * (2 * L);
-          ldsf[2 * (rc * RS + lidx(x >> 1)) + (x & 1)] = z[q];
+        for (int q = 0; q < 4; ++q) {
+          const int v = (int)(4 * m + q - v0);
+          if (v >= 0 && v < nv) {
+            const int rc = v / (2 * L), x = v - rc * (2 * L);
+            ldsf[2 * (rc * RS + lidx(x >> 1)) + (x & 1)] = z[q];
+          }
         }
       }
     }
@@ -125,7 +254,11 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
   __syncthreads();
   slot_store<L, RL, P, E>(v, lrow, p);
   __syncthreads();
-  twist_store_rows<L, C, T, TILED>(lds, a.tw2, a.spec + (long long)b * a.Nh, row0, rows_here, a.nrows, tid);
+  unsigned tile_off, run_stride;
+  tile_geom<TILED, L>(row0, a.nrows, tile_off, run_stride);
+  const rsrc_t spec = make_rsrc(a.spec + (long long)b * a.Nh, (unsigned)(a.Nh * 8));
+  const rsrc_t tw2 = make_rsrc(a.tw2, (unsigned)(L * 8));
+  twist_store_rows<L, C, T, TILED>(lds, tw2, spec, tile_off, run_stride, rows_here, tid);
 }
 
 // C2R along x -> normalise -> field, sign map, counts -> R2C of the +-1 row (THRESH).
@@ -133,7 +266,6 @@ template <int L, bool THRESH, bool TILED, int V>
 __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L, V>::C, T = RowTile<L, V>::T;
   constexpr int RS = Region<L>::value;
-  constexpr int TW = RowIO<L, TILED>::TW, NG = RowIO<L, TILED>::NG, PG = C * TW;
   using Rad = typename Plan<L>::fwd;
   using RadF = Reverse<Rad>;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
@@ -145,26 +277,28 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   const long long row0 = (long long)blockIdx.x * C;
   const int rows_here = (int)((a.nrows - row0) < C ? (a.nrows - row0) : C);
   float2* lrow = lds + c * RS;
-  float2* spec_f = a.spec + (long long)b * a.Nh;
+  unsigned tile_off, run_stride;
+  tile_geom<TILED, L>(row0, a.nrows, tile_off, run_stride);
+  const rsrc_t spec = make_rsrc(a.spec + (long long)b * a.Nh, (unsigned)(a.Nh * 8));
+  const rsrc_t tw2 = make_rsrc(a.tw2, (unsigned)(L * 8));
 
-  // ---- the tile's half rows X[0..L] into LDS, in address order; X[0] and X[L] are real after
-  //      the other axes' inverse transforms
-  for (int u = tid; u < NG * PG; u += T) {
-    const int q = u / PG, w = u - q * PG, cc = w / TW, kk = w - cc * TW;
-    const int k = q * TW + kk;
-    if (k > L) continue;
-    float2 x = cc < rows_here ? spec_f[((long long)q * a.nrows + row0 + cc) * TW + kk] : make_float2(0.f, 0.f);
-    if (k == 0 || k == L) x.y = 0.0f;
-    lds[cc * RS + lidx(k)] = x;
-  }
+  // ---- the tile's half rows X[0..L] into LDS, in address order
+  load_rows<L, C, T, TILED>(lds, spec, tile_off, run_stride, rows_here, tid);
   __syncthreads();
   // ---- pre-twist: Z[k] = (X[k] + X*[L-k]) + i e^{+2 pi i k / 2L} (X[k] - X*[L-k])
   float2 v[E];
+  {
+    using M = LoadMap<L, R1, P, E>;
+    using MM = MirrorMap<L, R1, P, E>;
 #pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int k = slot_index<L, R1, P>(s, p);
-    const float2 xk = lrow[lidx(k)], xc = cconj(lrow[lidx(L - k)]);
-    v[s] = cadd(cadd(xk, xc), mul_mi<true>(cmul(cconj(a.tw2[k]), csub(xk, xc))));
+    for (int s = 0; s < E; ++s) {
+      const int bb = s / R1, r = s % R1;
+      const int k = slot_index<L, R1, P>(s, p);
+      const float2 xk = M::lin ? lrow[lidx(p) + M::off(0, bb, r)] : lrow[lidx(k)];
+      const float2 xc = cconj(MM::lin ? lrow[lidx(L - p) + MM::off(0, bb, r)] : lrow[lidx(L - k)]);
+      const float2 w = cconj(buf_load2(tw2, (unsigned)p * 8u, (unsigned)slot_index<L, R1, P>(s, 0) * 8u));
+      v[s] = cadd(cadd(xk, xc), mul_mi<true>(cmul(w, csub(xk, xc))));
+    }
   }
   fft_run<L, P, E, true>(Rad{}, v, lrow, p, a.tw);
 
@@ -183,16 +317,31 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   }
   __syncthreads();
   // ---- field and sign map out, 4 voxels (16 B of field, 4 B of map) per unit
-  float* fout = a.io ? a.io[b].field : field_ptr(a.field, a.N, b);
-  int8_t* tout = a.io ? a.io[b].pm1 : field_ptr(a.pm1, a.N, b);
-  uint64_t* cout = a.io ? a.io[b].counts : field_ptr(a.counts, 2, b);
-  const float near_tol = a.io ? a.io[b].near_abs : a.near_tol;
+  float* fout;
+  int8_t* tout;
+  uint64_t* cout;
+  float near_tol;
+  if (a.io) {
+    const FieldIO& io = a.io[b];
+    fout = io.field;
+    tout = io.pm1;
+    cout = io.counts;
+    near_tol = io.near_abs;
+  } else {
+    fout = field_ptr(a.field, a.N, b);
+    tout = field_ptr(a.pm1, a.N, b);
+    cout = field_ptr(a.counts, 2, b);
+    near_tol = a.near_tol;
+  }
   const long long gbase = row0 * 2 * L;
+  const unsigned tile_vox = (unsigned)rows_here * 2u * L;
+  const rsrc_t fo = make_rsrc(fout ? fout + gbase : nullptr, fout ? tile_vox * 4u : 0u);
+  const rsrc_t to = make_rsrc(tout ? tout + gbase : nullptr, tout ? tile_vox : 0u);
   const int nq = rows_here * L / 2;              // units of 4 voxels in the tile
   unsigned npos = 0, nnear = 0;
   for (int u = tid; u < nq; u += T) {
     const float4 f4 = *reinterpret_cast<const float4*>(stage + 4 * u);
-    if (fout) *reinterpret_cast<float4*>(fout + gbase + 4 * u) = f4;
+    if (fout) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, f4), fo, (unsigned)u * 16u, 0, 0);
     if constexpr (THRESH) {
       const float xs[4] = {f4.x, f4.y, f4.z, f4.w};
       uint32_t packed = 0;
@@ -203,7 +352,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
         nnear += fabsf(xs[q]) < near_tol;
         packed |= (uint32_t)(pos ? 0x01u : 0xFFu) << (8 * q);
       }
-      if (tout) *reinterpret_cast<uint32_t*>(tout + gbase + 4 * u) = packed;
+      if (tout) __builtin_amdgcn_raw_buffer_store_b32(packed, to, (unsigned)u * 4u, 0, 0);
     }
   }
   // tail (rows of 6 voxels): the last rows_here * 2L mod 4 samples one by one
@@ -226,7 +375,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
     constexpr int RLF = RadInfo<RadF>::last;
     slot_store<L, RLF, P, E>(v, lrow, p);
     __syncthreads();
-    twist_store_rows<L, C, T, TILED>(lds, a.tw2, spec_f, row0, rows_here, a.nrows, tid);
+    twist_store_rows<L, C, T, TILED>(lds, tw2, spec, tile_off, run_stride, rows_here, tid);
     if (tid == 0 && cout) {
       unsigned long long np = 0, nn = 0;
       for (int w = 0; w < (T + 63) / 64; ++w) { np += red_u[0][w]; nn += red_u[1][w]; }

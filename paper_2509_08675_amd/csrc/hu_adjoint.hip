@@ -134,7 +134,7 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
   const ColIO io = col_io<L>(a.spec, a.Nh, a.gm.inner0, g, p);
   float2 v[E];
   col_load<L, R1, P, E>(v, io);
-  fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
+  fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, 0>::RS, p, a.tw);
 
   // per-bin weights into LDS (the exchange buffer is free after the transform)
   double* cf = reinterpret_cast<double*>(lds);

@@ -27,7 +27,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
   const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, g, p);
   float2 v[E];
   col_load<L, R1, P, E>(v, io);
-  fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
+  fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
   const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
   float* pw = reinterpret_cast<float*>(lds);
   double* hs = reinterpret_cast<double*>(pw + ((C * LP + 1) & ~1));

@@ -21,7 +21,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols(ColsArgs a) {
   const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.inner, g, p);
   float2 v[E];
   col_load<L, R1, P, E>(v, io);
-  fft_run<L, P, E, INV>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
+  fft_run<L, P, E, INV>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
   if (valid) col_store<L, RL, P, E>(v, io);
 }
 

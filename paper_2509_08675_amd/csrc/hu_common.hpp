@@ -39,8 +39,14 @@ struct ColTile {
   static constexpr int C = V == 0 ? cd : (cd / 2 / m * m >= m ? cd / 2 / m * m : cd);
   static constexpr int T = C * P;
   static_assert(T % 64 == 0, "column tiles are whole waves");
-  // padded power-value layout for run-length binning: 4 floats after every 16
-  static constexpr int LP = L + (L / 16) * 4 + 4;
+  static constexpr int LPAD = C >= 16 ? 1 : 4;
+  // exchange region per column: wide tiles (a wave spans many columns) use the bank-staggered
+  // stride
+  static constexpr int RS = C >= 16 ? RegionWide<L>::value : Region<L>::value;
+  // padded power-value layout for run-length binning: 4 floats after every 16; the words per
+  // column are chosen so that the columns a wave addresses at once fall on different banks
+  static constexpr int LPB = (L + (L / 16) * 4 + 31) / 32 * 32;
+  static constexpr int LP = LPB + LPAD;
 };
 
 __host__ __device__ constexpr int pw_index(int e) { return e + (e >> 4) * 4; }
@@ -225,7 +231,7 @@ __device__ __forceinline__ void hist_flush(const double* hs, int nb, double scal
 
 template <int L, int V>
 __host__ __device__ constexpr size_t col_xchg_bytes() {
-  return (size_t)ColTile<L, V>::C * Region<L>::value * 8;
+  return (size_t)ColTile<L, V>::C * ColTile<L, V>::RS * 8;
 }
 
 template <int L, int V>

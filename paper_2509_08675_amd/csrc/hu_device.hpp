@@ -279,6 +279,12 @@ template <int L>
 struct Region {
   static constexpr int value = L + (L >> 4) + 8;
 };
+// the same rounded up to a multiple of 16 plus 1: for tiles of many transforms whose lanes in a
+// wave belong to different transforms, consecutive regions then start on different banks
+template <int L>
+struct RegionWide {
+  static constexpr int value = (L + (L >> 4) + 15) / 16 * 16 + 1;
+};
 
 // LDS positions of a stage's reads (element j + r L/R, j = p + P b) and writes (element
 // (j / NS) NS R + j mod NS + r NS).  When the padded position minus that of the thread's first

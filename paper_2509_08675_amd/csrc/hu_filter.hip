@@ -28,7 +28,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, g, p);
   float2 v[E];
   col_load<L, R1, P, E>(v, io);
-  fft_run<L, P, E, false>(Rad{}, v, lds + c * Region<L>::value, p, a.tw);
+  fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
 
   // ---- filter and per-thread statistics
   double* cont_out = a.io ? a.io[b].cont_sum : field_ptr(a.cont_sum, a.nb, b);
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   }
 
   // ---- inverse transform along axis 0 (first radix = last forward radix: no exchange needed)
-  fft_run<L, P, E, true>(RadI{}, v, lds + c * Region<L>::value, p, a.tw);
+  fft_run<L, P, E, true>(RadI{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
   if (valid) col_store<L, R1, P, E>(v, io);
 }
 

@@ -378,28 +378,44 @@ __device__ __forceinline__ int slot_index(int i, int p) {
   return p + P * (i / R) + (i % R) * (L / R);
 }
 
-template <int L, int P, int E, bool INV, int NS, int SOFF, int R, int... Rest>
+// Exchange synchronisation.  A transform whose P threads all sit in one wave and own its LDS
+// region needs no workgroup barrier: the LDS operations of a wave complete in issue order, so a
+// wave-scope fence (which also keeps the compiler from moving LDS accesses across it) suffices.
+template <bool WAVE>
+__device__ __forceinline__ void xchg_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int L, int P, int E, bool INV, bool WAVE, int NS, int SOFF, int R, int... Rest>
 __device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int p, const float2* __restrict__ tw) {
   stage_compute<L, R, NS, P, E, INV, SOFF>(v, p, tw);
   if constexpr (sizeof...(Rest) > 0) {
     constexpr int R2 = FirstR<Rest...>::value;
-    __syncthreads();
+    xchg_sync<WAVE>();
     stage_store<L, R, NS, P, E>(v, lds, p);
-    __syncthreads();
+    xchg_sync<WAVE>();
     stage_load<L, R2, P, E>(v, lds, p);
-    fft_stages<L, P, E, INV, NS * R, (NS > 1 ? SOFF + NS * rpad(R) : SOFF), Rest...>(v, lds, p, tw);
+    fft_stages<L, P, E, INV, WAVE, NS * R, (NS > 1 ? SOFF + NS * rpad(R) : SOFF), Rest...>(v, lds, p, tw);
   }
 }
 
 // The transform with radix list Rs (the forward plan of L or its reverse); tw = the stage table
-// of L.
-template <int L, int P, int E, bool INV, int... Rs>
+// of L.  WAVE: the P threads of each transform lie in one wave and the region `lds` is theirs
+// alone (row passes with P dividing 64), so the exchanges synchronise the wave only.
+template <int L, int P, int E, bool INV, bool WAVE = false, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[E], float2* lds, int p,
                                         const float2* __restrict__ tw) {
   using F = typename Plan<L>::fwd;
   constexpr bool is_fwd = std::is_same<Radices<Rs...>, F>::value;
   static_assert(is_fwd || std::is_same<Radices<Rs...>, Reverse<F>>::value, "radix list is not a plan of L");
-  fft_stages<L, P, E, INV, 1, (is_fwd ? 0 : StageTab<L>::fwd), Rs...>(v, lds, p, tw);
+  static_assert(!WAVE || (64 % P) == 0, "wave-local exchange needs each transform inside one wave");
+  fft_stages<L, P, E, INV, WAVE, 1, (is_fwd ? 0 : StageTab<L>::fwd), Rs...>(v, lds, p, tw);
 }
 
 // ---------------------------------------------------------------------------------------------

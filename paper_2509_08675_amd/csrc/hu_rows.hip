@@ -247,11 +247,12 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
   }
   __syncthreads();
 
+  constexpr bool WV = (64 % P) == 0;             // each row inside one wave
   float2 v[E];
   float2* lrow = lds + c * RS;
   stage_load<L, R1, P, E>(v, lrow, p);
-  fft_run<L, P, E, false>(Rad{}, v, lrow, p, a.tw);
-  __syncthreads();
+  fft_run<L, P, E, false, WV>(Rad{}, v, lrow, p, a.tw);
+  xchg_sync<WV>();
   slot_store<L, RL, P, E>(v, lrow, p);
   __syncthreads();
   unsigned tile_off, run_stride;
@@ -300,7 +301,8 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
       v[s] = cadd(cadd(xk, xc), mul_mi<true>(cmul(w, csub(xk, xc))));
     }
   }
-  fft_run<L, P, E, true>(Rad{}, v, lrow, p, a.tw);
+  constexpr bool WV = (64 % P) == 0;             // each row inside one wave
+  fft_run<L, P, E, true, WV>(Rad{}, v, lrow, p, a.tw);
 
   // ---- normalise (Eq. (15)); stage the field in LDS (rows contiguous, unpadded)
   const double* fs = a.fstats + (long long)b * 8;
@@ -369,9 +371,11 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
     npos = wave_usum(npos);
     nnear = wave_usum(nnear);
     if ((tid & 63) == 0) { red_u[0][tid >> 6] = npos; red_u[1][tid >> 6] = nnear; }
-    // forward transform of the packed +-1 row (its first radix is the inverse's last)
-    fft_run<L, P, E, false>(RadF{}, v, lrow, p, a.tw);
+    // forward transform of the packed +-1 row (its first radix is the inverse's last); the
+    // staging buffer read above overlaps other rows' exchange regions
     __syncthreads();
+    fft_run<L, P, E, false, WV>(RadF{}, v, lrow, p, a.tw);
+    xchg_sync<WV>();
     constexpr int RLF = RadInfo<RadF>::last;
     slot_store<L, RLF, P, E>(v, lrow, p);
     __syncthreads();

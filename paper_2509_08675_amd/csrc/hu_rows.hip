@@ -4,8 +4,9 @@
 //              transform of each x row: an n_x/2-point complex FFT of the packed samples
 //              x[2n] + i x[2n+1] followed by the split twist;
 //   rows_c2r   inverse of that for each x row, then the normalisation of Eq. (15) with the
-//              statistics of the filter pass, the FP32 field and the +-1 sign map with counts,
-//              and the real-to-complex transform of the +-1 row written back in place.
+//              statistics of the filter pass, the FP32 field and the +-1 sign map with counts
+//              (stored straight from the transform's registers), and the real-to-complex
+//              transform of the +-1 row written back in place.
 //
 // Half-spectrum layout seen by the row passes: element k of row r sits at
 //   2D (column groups of four): (k >> 2) (nrows 4) + 4 r + (k & 3);
@@ -304,21 +305,11 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   constexpr bool WV = (64 % P) == 0;             // each row inside one wave
   fft_run<L, P, E, true, WV>(Rad{}, v, lrow, p, a.tw);
 
-  // ---- normalise (Eq. (15)); stage the field in LDS (rows contiguous, unpadded)
+  // ---- normalise (Eq. (15)) in registers.  The field and the sign map go out straight from the
+  //      slots: in slot s the P threads of a row hold P consecutive complex elements, i.e. 2P
+  //      consecutive voxels, so each store instruction writes contiguous memory.
   const double* fs = a.fstats + (long long)b * 8;
   const float scale = (float)fs[4], offset = (float)fs[5];
-  float* stage = reinterpret_cast<float*>(lds);
-  __syncthreads();                               // exchange buffer free
-#pragma unroll
-  for (int s = 0; s < E; ++s) {
-    const int n = slot_index<L, RL, P>(s, p);
-    const float x0 = fmaf(v[s].x, scale, offset);
-    const float x1 = fmaf(v[s].y, scale, offset);
-    *reinterpret_cast<float2*>(stage + c * 2 * L + 2 * n) = make_float2(x0, x1);
-    if constexpr (THRESH) v[s] = make_float2(x0 >= 0.0f ? 1.0f : -1.0f, x1 >= 0.0f ? 1.0f : -1.0f);
-  }
-  __syncthreads();
-  // ---- field and sign map out, 4 voxels (16 B of field, 4 B of map) per unit
   float* fout;
   int8_t* tout;
   uint64_t* cout;
@@ -336,44 +327,34 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
     near_tol = a.near_tol;
   }
   const long long gbase = row0 * 2 * L;
+  // stores past the tile's rows, and all stores of an absent output (size 0), are dropped
   const unsigned tile_vox = (unsigned)rows_here * 2u * L;
   const rsrc_t fo = make_rsrc(fout ? fout + gbase : nullptr, fout ? tile_vox * 4u : 0u);
   const rsrc_t to = make_rsrc(tout ? tout + gbase : nullptr, tout ? tile_vox : 0u);
-  const int nq = rows_here * L / 2;              // units of 4 voxels in the tile
+  const bool row_ok = c < rows_here;
+  const unsigned vox0 = (unsigned)(c * 2 * L + 2 * p);      // voxel of this thread's slot-0 element
   unsigned npos = 0, nnear = 0;
-  for (int u = tid; u < nq; u += T) {
-    const float4 f4 = *reinterpret_cast<const float4*>(stage + 4 * u);
-    if (fout) __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, f4), fo, (unsigned)u * 16u, 0, 0);
-    if constexpr (THRESH) {
-      const float xs[4] = {f4.x, f4.y, f4.z, f4.w};
-      uint32_t packed = 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool pos = xs[q] >= 0.0f;
-        npos += pos;
-        nnear += fabsf(xs[q]) < near_tol;
-        packed |= (uint32_t)(pos ? 0x01u : 0xFFu) << (8 * q);
-      }
-      if (tout) __builtin_amdgcn_raw_buffer_store_b32(packed, to, (unsigned)u * 4u, 0, 0);
-    }
-  }
-  // tail (rows of 6 voxels): the last rows_here * 2L mod 4 samples one by one
-  for (int i = 4 * nq + tid; i < rows_here * 2 * L; i += T) {
-    const float x = stage[i];
-    if (fout) fout[gbase + i] = x;
+  for (int s = 0; s < E; ++s) {
+    const unsigned so = 2u * (unsigned)slot_index<L, RL, P>(s, 0);
+    const float x0 = fmaf(v[s].x, scale, offset);
+    const float x1 = fmaf(v[s].y, scale, offset);
+    buf_store2(fo, make_float2(x0, x1), vox0 * 4u, so * 4u);
     if constexpr (THRESH) {
-      npos += x >= 0.0f;
-      nnear += fabsf(x) < near_tol;
-      if (tout) tout[gbase + i] = x >= 0.0f ? (int8_t)1 : (int8_t)-1;
+      const bool p0 = x0 >= 0.0f, p1 = x1 >= 0.0f;
+      npos += (unsigned)p0 + (unsigned)p1;
+      nnear += (unsigned)(fabsf(x0) < near_tol) + (unsigned)(fabsf(x1) < near_tol);
+      const unsigned b0 = p0 ? 0x01u : 0xFFu, b1 = p1 ? 0x0100u : 0xFF00u;
+      __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(b0 | b1), to, vox0, so, 0);
+      v[s] = make_float2(p0 ? 1.0f : -1.0f, p1 ? 1.0f : -1.0f);
     }
   }
   if constexpr (THRESH) {
+    if (!row_ok) npos = nnear = 0;
     npos = wave_usum(npos);
     nnear = wave_usum(nnear);
     if ((tid & 63) == 0) { red_u[0][tid >> 6] = npos; red_u[1][tid >> 6] = nnear; }
-    // forward transform of the packed +-1 row (its first radix is the inverse's last); the
-    // staging buffer read above overlaps other rows' exchange regions
-    __syncthreads();
+    // forward transform of the packed +-1 row (its first radix is the inverse's last)
     fft_run<L, P, E, false, WV>(RadF{}, v, lrow, p, a.tw);
     xchg_sync<WV>();
     constexpr int RLF = RadInfo<RadF>::last;

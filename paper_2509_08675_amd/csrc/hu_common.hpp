@@ -39,14 +39,13 @@ struct ColTile {
   static constexpr int C = V == 0 ? cd : (cd / 2 / m * m >= m ? cd / 2 / m * m : cd);
   static constexpr int T = C * P;
   static_assert(T % 64 == 0, "column tiles are whole waves");
-  static constexpr int LPAD = C >= 16 ? 1 : 4;
-  // exchange region per column: wide tiles (a wave spans many columns) use the bank-staggered
-  // stride
-  static constexpr int RS = C >= 16 ? RegionWide<L>::value : Region<L>::value;
-  // padded power-value layout for run-length binning: 4 floats after every 16; the words per
-  // column are chosen so that the columns a wave addresses at once fall on different banks
-  static constexpr int LPB = (L + (L / 16) * 4 + 31) / 32 * 32;
-  static constexpr int LP = LPB + LPAD;
+  // exchange region per column.  Wide tiles (a wave spans many columns): the bank-staggered
+  // stride.  Narrow tiles (a 16-lane phase spans 4 columns x 4 threads): L + L/16 + 4 complex,
+  // i.e. 8 mod 32 words, so the four columns of a phase use disjoint banks.
+  static constexpr int RS = C >= 16 ? RegionWide<L>::value : L + (L >> 4) + 4;
+  // padded power-value layout for run-length binning: 4 floats after every 16, and an odd
+  // number of words per column
+  static constexpr int LP = (L + (L / 16) * 4 + 31) / 32 * 32 + 1;
 };
 
 __host__ __device__ constexpr int pw_index(int e) { return e + (e >> 4) * 4; }

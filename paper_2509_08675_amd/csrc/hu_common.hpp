@@ -26,6 +26,7 @@ struct RowTile {
   static constexpr int C = V == 0 ? cd : (cd / 2 / m * m >= m ? cd / 2 / m * m : cd);
   static constexpr int T = C * P;
   static_assert(T % 64 == 0, "row tiles are whole waves");
+  static constexpr int RS = Region<L>::value;          // exchange region per row
 };
 
 template <int L, int V = 0>

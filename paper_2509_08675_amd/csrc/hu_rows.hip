@@ -66,11 +66,10 @@ struct RowWalk {
 // R2C split twist of every row of the tile from Z in LDS (padded, natural order) to the half
 // spectrum, in address order:
 //   X[k] = (Z[k] + Z*[L-k])/2 - (i/2) e^{-2 pi i k / 2L} (Z[k] - Z*[L-k]),  X[L] = Re Z[0] - Im Z[0].
-template <int L, int C, int T, bool TILED>
+template <int L, int C, int T, bool TILED, int RS>
 __device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, rsrc_t spec, unsigned tile_off,
                                                  unsigned run_stride, int rows_here, int tid) {
   using W = RowWalk<L, C, T, TILED>;
-  constexpr int RS = Region<L>::value;
   float2 w[W::ITERS];
 #pragma unroll
   for (int it = 0; it < W::ITERS; ++it) {          // the twiddles first: all loads in flight together
@@ -102,11 +101,10 @@ __device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, 
 // The tile's half rows X[0..L] from the half spectrum into LDS (padded, natural order), in
 // address order; X[0] and X[L] are made real (the other axes' inverse transforms leave them so up
 // to rounding).
-template <int L, int C, int T, bool TILED>
+template <int L, int C, int T, bool TILED, int RS>
 __device__ __forceinline__ void load_rows(float2* lds, rsrc_t spec, unsigned tile_off, unsigned run_stride,
                                           int rows_here, int tid) {
   using W = RowWalk<L, C, T, TILED>;
-  constexpr int RS = Region<L>::value;
   float2 x[W::ITERS];
 #pragma unroll
   for (int it = 0; it < W::ITERS; ++it) {
@@ -164,7 +162,7 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
 template <int L, int SRC, bool TILED, int V>
 __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L, V>::C, T = RowTile<L, V>::T;
-  constexpr int RS = Region<L>::value;
+  constexpr int RS = RowTile<L, V>::RS;
   using Rad = typename Plan<L>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
   extern __shared__ float2 lds[];
@@ -260,14 +258,14 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
   tile_geom<TILED, L>(row0, a.nrows, tile_off, run_stride);
   const rsrc_t spec = make_rsrc(a.spec + (long long)b * a.Nh, (unsigned)(a.Nh * 8));
   const rsrc_t tw2 = make_rsrc(a.tw2, (unsigned)(L * 8));
-  twist_store_rows<L, C, T, TILED>(lds, tw2, spec, tile_off, run_stride, rows_here, tid);
+  twist_store_rows<L, C, T, TILED, RS>(lds, tw2, spec, tile_off, run_stride, rows_here, tid);
 }
 
 // C2R along x -> normalise -> field, sign map, counts -> R2C of the +-1 row (THRESH).
 template <int L, bool THRESH, bool TILED, int V>
 __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = RowTile<L, V>::C, T = RowTile<L, V>::T;
-  constexpr int RS = Region<L>::value;
+  constexpr int RS = RowTile<L, V>::RS;
   using Rad = typename Plan<L>::fwd;
   using RadF = Reverse<Rad>;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
@@ -285,7 +283,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   const rsrc_t tw2 = make_rsrc(a.tw2, (unsigned)(L * 8));
 
   // ---- the tile's half rows X[0..L] into LDS, in address order
-  load_rows<L, C, T, TILED>(lds, spec, tile_off, run_stride, rows_here, tid);
+  load_rows<L, C, T, TILED, RS>(lds, spec, tile_off, run_stride, rows_here, tid);
   __syncthreads();
   // ---- pre-twist: Z[k] = (X[k] + X*[L-k]) + i e^{+2 pi i k / 2L} (X[k] - X*[L-k])
   float2 v[E];
@@ -360,7 +358,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
     constexpr int RLF = RadInfo<RadF>::last;
     slot_store<L, RLF, P, E>(v, lrow, p);
     __syncthreads();
-    twist_store_rows<L, C, T, TILED>(lds, tw2, spec, tile_off, run_stride, rows_here, tid);
+    twist_store_rows<L, C, T, TILED, RS>(lds, tw2, spec, tile_off, run_stride, rows_here, tid);
     if (tid == 0 && cout) {
       unsigned long long np = 0, nn = 0;
       for (int w = 0; w < (T + 63) / 64; ++w) { np += red_u[0][w]; nn += red_u[1][w]; }
@@ -378,8 +376,8 @@ template <int L, int SRC, bool TILED, int V>
 static hipError_t launch_rows_r2c_L(const RowsArgs& a, int batch, hipStream_t st) {
   constexpr int C = RowTile<L, V>::C, T = RowTile<L, V>::T;
   dim3 grid(ceil_div_u(a.nrows, C), batch);
-  hipLaunchKernelGGL((k_rows_r2c<L, SRC, TILED, V>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2), st,
-                     a);
+  constexpr size_t lds = (size_t)C * RowTile<L, V>::RS * sizeof(float2);
+  hipLaunchKernelGGL((k_rows_r2c<L, SRC, TILED, V>), grid, dim3(T), lds, st, a);
   return hipGetLastError();
 }
 
@@ -407,8 +405,8 @@ template <int L, bool THRESH, bool TILED, int V>
 static hipError_t launch_rows_c2r_L(const RowsZArgs& a, int batch, hipStream_t st) {
   constexpr int C = RowTile<L, V>::C, T = RowTile<L, V>::T;
   dim3 grid(ceil_div_u(a.nrows, C), batch);
-  hipLaunchKernelGGL((k_rows_c2r<L, THRESH, TILED, V>), grid, dim3(T), (size_t)C * Region<L>::value * sizeof(float2),
-                     st, a);
+  constexpr size_t lds = (size_t)C * RowTile<L, V>::RS * sizeof(float2);
+  hipLaunchKernelGGL((k_rows_c2r<L, THRESH, TILED, V>), grid, dim3(T), lds, st, a);
   return hipGetLastError();
 }
 

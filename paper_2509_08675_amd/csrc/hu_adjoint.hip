@@ -16,178 +16,330 @@
 //
 // The expected spectrum of a filter: E[P] per mode is sigma_f^2 N H^2 / sum_k w_k H^2 (Eqs. (10)-(11)
 // with the normalisation of Eq. (15)), binned like the field's spectrum.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "hu_common.hpp"
 
 namespace hu {
 
-// ln H (relative) and d lnH/dtheta at one canonical wavenumber; returns H.  With
-// u_i = |kappa'_i| / a_i, K = (sum_i u_i^p)^(1/p), r_i = u_i / K:
-//   d lnH/dK  = (alpha / K - (K - k0) / w^2) / 2
-//   dK/da_i   = -K r_i^p / a_i
-//   dK/dp     = (K / p) sum_i r_i^p ln r_i
-//   dK/drot   = r_x^(p-1) sgn(kappa'_x) kappa'_y / a - r_y^(p-1) sgn(kappa'_y) kappa'_x / b
-//               (d kappa'_x / drot = kappa'_y, d kappa'_y / drot = -kappa'_x)
-//   d lnH/dk0 = (K - k0) / (2 w^2),   d lnH/dw = (K - k0)^2 / (2 w^3)
-// Terms with u_i = 0 contribute nothing.  The ratios t_i = (u_i / u_max)^p keep every power in
-// range: r_i^p = t_i / S with S = sum_i t_i.
-template <int NDIM>
-__device__ __forceinline__ float lnh_partials(const FiltDev& f, float w, float kx, float ky, float kz, float (&d)[7]) {
+// ln H (relative) and its derivatives.  With u_i = |kappa'_i| / a_i, K = (sum_i u_i^p)^(1/p),
+// r_i = u_i / K and D = d lnH/dK = (alpha / K - (K - k0) / w^2) / 2:
+//   d lnH/da_i = -D K r_i^p / a_i
+//   d lnH/dp   = D (K / p) sum_i r_i^p ln r_i
+//   d lnH/drot = D K (r_x^p kappa'_y / kappa'_x - r_y^p kappa'_x / kappa'_y)
+//                (d kappa'_x / drot = kappa'_y, d kappa'_y / drot = -kappa'_x, r^(p-1) = r^p K / u)
+//   d lnH/dk0  = (K - k0) / (2 w^2),   d lnH/dw = (K - k0)^2 / (2 w^3)
+// Every K term carries the factor D K = alpha / 2 - K (K - k0) / (2 w^2), so 1/K is never formed.  Powers are taken relative to the largest u_i in the log2 domain: t_i = 2^(p (l_i - l_m)),
+// l_i = log2 u_i, so r_i^p = t_i / S with S = sum_i t_i in [1, 3], and K = 2^(l_m + log2(S) / p).
+// Axes with u_i = 0 contribute nothing (t_i = 0, their l_i is a finite sentinel).
+constexpr float LOG_OFF = -1.0e4f;
+
+// H and the seven derivatives of ln H without their per-filter constant factors:
+//   d lnH/dtheta_j = kf_j r_j,  r = (DK t_x, DK t_y, DK t_z, DK sum_i t_i (l_i - log2 K), DK (t_x A - t_y B),
+//                                    K - k0, (K - k0)^2),
+//   kf = (-1/a, -1/b, -1/c, ln2 / p, 1, 1/(2 w^2), 1/(2 w^3)),  t_i = r_i^p,  DK = D K
+// (A, B as in dK/drot above); the factors are applied once per thread after the sums.
+struct LnhOut {
+  float H;
+  float r[7];
+};
+
+__device__ __forceinline__ void lnh_tail(const FiltDev& f, float lm, float S, const float (&rp)[3], const float (&l)[3],
+                                         float A, float B, LnhOut& o) {
   constexpr float LN2 = 0.69314718055994531f;
-  const float kxr = f.cr * kx + f.sr * ky;
-  const float kyr = -f.sr * kx + f.cr * ky;
-  float u[3];
-  u[0] = fabsf(kxr) * f.ia;
-  u[1] = fabsf(kyr) * f.ib;
-  u[2] = NDIM == 3 ? fabsf(kz) * f.ic : 0.0f;
-  float um = fmaxf(u[0], u[1]);
-  if constexpr (NDIM == 3) um = fmaxf(um, u[2]);
-  if (!(um > 0.0f)) {
-#pragma unroll
-    for (int j = 0; j < 7; ++j) d[j] = 0.0f;
-    return 0.0f;
-  }
-  const float inv = __builtin_amdgcn_rcpf(um);
-  float l2r[3], t[3];
-  float S = 0.0f;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const bool on = (i < NDIM) && u[i] > 0.0f;
-    l2r[i] = on ? hw_log2(u[i] * inv) : 0.0f;
-    t[i] = on ? hw_exp2(f.p * l2r[i]) : 0.0f;
-    S += t[i];
-  }
-  const float log2S = hw_log2(S);
-  const float log2K = hw_log2(um) + log2S * f.ip;
+  const float log2K = fmaf(hw_log2(S), f.ip, lm);
   const float K = hw_exp2(log2K);
   const float dd = K - f.k0;
-  const float lnc = f.alpha * (log2K * LN2) - dd * dd * f.inv2w2 - f.lnchimax;
-  const float H = amp_from_lnchi(lnc);
-  const float dK = 0.5f * (f.alpha * __builtin_amdgcn_rcpf(K) - 2.0f * dd * f.inv2w2);
-  const float invS = __builtin_amdgcn_rcpf(S);
-  float rp[3], accp = 0.0f;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    rp[i] = t[i] * invS;
-    accp += rp[i] > 0.0f ? rp[i] * (LN2 * (l2r[i] - log2S * f.ip)) : 0.0f;
-  }
-  d[0] = dK * (-K * rp[0] * f.ia);
-  d[1] = dK * (-K * rp[1] * f.ib);
-  d[2] = NDIM == 3 ? dK * (-K * rp[2] * f.ic) : 0.0f;
-  d[3] = dK * K * f.ip * accp;
-  // r_i^(p-1) = r_i^p K / u_i
-  const float rx = u[0] > 0.0f ? rp[0] * K * __builtin_amdgcn_rcpf(u[0]) : 0.0f;
-  const float ry = u[1] > 0.0f ? rp[1] * K * __builtin_amdgcn_rcpf(u[1]) : 0.0f;
-  const float sx = kxr > 0.0f ? 1.0f : (kxr < 0.0f ? -1.0f : 0.0f);
-  const float sy = kyr > 0.0f ? 1.0f : (kyr < 0.0f ? -1.0f : 0.0f);
-  d[4] = dK * (rx * sx * kyr * f.ia - ry * sy * kxr * f.ib);
-  d[5] = dd * f.inv2w2;
-  d[6] = dd * dd * f.inv2w2 * __builtin_amdgcn_rcpf(w);
-  return H;
+  const float d5 = dd * f.inv2w2;
+  o.H = amp_from_lnchi(fmaf(f.alpha, log2K * LN2, -fmaf(dd, d5, f.lnchimax)));
+  const float KD = fmaf(-2.0f * K, d5, f.alpha) * 0.5f;
+  const float accp = fmaf(rp[0], l[0] - log2K, fmaf(rp[1], l[1] - log2K, rp[2] * (l[2] - log2K)));
+  o.r[0] = KD * rp[0];
+  o.r[1] = KD * rp[1];
+  o.r[2] = KD * rp[2];
+  o.r[3] = KD * accp;
+  o.r[4] = KD * fmaf(rp[0], A, -rp[1] * B);
+  o.r[5] = dd;
+  o.r[6] = dd * dd;
 }
 
-// H_sym and dH_sym/dtheta at axis-0 index e of column cc: on the Nyquist planes of a rotated
-// filter H_sym averages H at kappa and at kappa with its Nyquist components negated, and is
-// differentiated term by term.
-template <int NDIM>
-__device__ __forceinline__ float hsym_partials(const FiltDev& f, float w, const Axis0Geom& gm, const ColCoord& cc,
-                                               int e, float (&dH)[7]) {
-  const int mt = e < gm.n0 / 2 ? e : e - gm.n0;
-  const float k0c = (float)mt * gm.kap0;
-  const bool nyq0 = (2 * e == gm.n0);
-  const float kx = cc.kx_c;
-  float ky, kz;
-  bool ny_y;
-  if constexpr (NDIM == 2) { ky = k0c; kz = 0.0f; ny_y = nyq0; }
-  else { ky = cc.ky; kz = k0c; ny_y = cc.nyq_y; }
-  float d1[7];
-  const float H1 = lnh_partials<NDIM>(f, w, kx, ky, kz, d1);
-  if (f.rotated && (cc.nyq_x || ny_y)) {
-    float d2[7];
-    const float H2 = lnh_partials<NDIM>(f, w, cc.nyq_x ? -kx : kx, ny_y ? -ky : ky, kz, d2);
+__device__ __forceinline__ void lnh_zero(LnhOut& o) {
+  o.H = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 7; ++j) dH[j] = 0.5f * (H1 * d1[j] + H2 * d2[j]);
-    return 0.5f * (H1 + H2);
+  for (int j = 0; j < 7; ++j) o.r[j] = 0.0f;
+}
+
+// 2D: both in-plane components vary along an axis-0 column
+__device__ __forceinline__ void lnh2(const FiltDev& f, float kx, float ky, LnhOut& o) {
+  const float kxr = fmaf(f.cr, kx, f.sr * ky);
+  const float kyr = fmaf(-f.sr, kx, f.cr * ky);
+  const float u0 = fabsf(kxr) * f.ia, u1 = fabsf(kyr) * f.ib;
+  const bool on0 = u0 > 0.0f, on1 = u1 > 0.0f;
+  if (!(on0 || on1)) {
+    lnh_zero(o);
+    return;
   }
-#pragma unroll
-  for (int j = 0; j < 7; ++j) dH[j] = H1 * d1[j];
-  return H1;
+  float l[3];
+  l[0] = on0 ? hw_log2(u0) : LOG_OFF;
+  l[1] = on1 ? hw_log2(u1) : LOG_OFF;
+  l[2] = LOG_OFF;
+  const bool big0 = l[0] >= l[1];
+  const float lm = big0 ? l[0] : l[1];
+  const float lo = big0 ? l[1] : l[0];
+  const float t = (on0 && on1) ? hw_exp2(f.p * (lo - lm)) : 0.0f;
+  const float S = 1.0f + t;
+  const float iS = __builtin_amdgcn_rcpf(S);
+  const float rp[3] = {big0 ? iS : t * iS, big0 ? t * iS : iS, 0.0f};
+  const float r = (on0 && on1) ? __builtin_amdgcn_rcpf(kxr * kyr) : 0.0f;
+  lnh_tail(f, lm, S, rp, l, kyr * kyr * r, kxr * kxr * r, o);
+}
+
+// 3D: kappa_x and kappa_y are fixed along an axis-0 column, so their logs and relative powers
+// are computed once per column
+struct Lnh3Col {
+  float l0, l1, lxy;   // log2 u_x, log2 u_y (or the sentinel), their maximum
+  float c0, c1, c01;   // 2^(p (l_i - lxy)), their sum (0 when both are off)
+  float A, B;          // kappa'_y / kappa'_x and kappa'_x / kappa'_y (0 for an axis that is off)
+  bool on;             // u_x > 0 or u_y > 0
+};
+
+__device__ __forceinline__ Lnh3Col lnh3_col(const FiltDev& f, float kx, float ky) {
+  Lnh3Col c;
+  const float kxr = fmaf(f.cr, kx, f.sr * ky);
+  const float kyr = fmaf(-f.sr, kx, f.cr * ky);
+  const float u0 = fabsf(kxr) * f.ia, u1 = fabsf(kyr) * f.ib;
+  const bool on0 = u0 > 0.0f, on1 = u1 > 0.0f;
+  c.on = on0 || on1;
+  c.l0 = on0 ? hw_log2(u0) : LOG_OFF;
+  c.l1 = on1 ? hw_log2(u1) : LOG_OFF;
+  c.lxy = fmaxf(c.l0, c.l1);
+  c.c0 = on0 ? hw_exp2(f.p * (c.l0 - c.lxy)) : 0.0f;
+  c.c1 = on1 ? hw_exp2(f.p * (c.l1 - c.lxy)) : 0.0f;
+  c.c01 = c.c0 + c.c1;
+  c.A = on0 ? kyr / kxr : 0.0f;
+  c.B = on1 ? kxr / kyr : 0.0f;
+  return c;
+}
+
+__device__ __forceinline__ void lnh3(const FiltDev& f, const Lnh3Col& c, float kz, LnhOut& o) {
+  const float u2 = fabsf(kz) * f.ic;
+  const bool on2 = u2 > 0.0f;
+  if (!(on2 || c.on)) {
+    lnh_zero(o);
+    return;
+  }
+  float l[3] = {c.l0, c.l1, on2 ? hw_log2(u2) : LOG_OFF};
+  // z the largest: t_z = 1 and the in-plane powers scale by 2^(p (l_xy - l_z)); else t_z = 2^(p (l_z - l_xy))
+  const bool zbig = !c.on || (on2 && l[2] > c.lxy);
+  const float e = hw_exp2(-f.p * fabsf(l[2] - c.lxy));
+  const float g = zbig ? e : 1.0f;
+  const float t2 = zbig ? 1.0f : (on2 ? e : 0.0f);
+  const float lm = zbig ? l[2] : c.lxy;
+  const float S = fmaf(g, c.c01, t2);
+  const float iS = __builtin_amdgcn_rcpf(S);
+  const float gi = g * iS;
+  const float rp[3] = {c.c0 * gi, c.c1 * gi, t2 * iS};
+  lnh_tail(f, lm, S, rp, l, c.A, c.B, o);
 }
 
 // ---------------------------------------------------------------------------------------------
 // axis-0 adjoint pass: forward FFT of each column of W, then the seven FP64 sums; per-tile
 // partials, reduced in a fixed order by k_grad_final
 // ---------------------------------------------------------------------------------------------
+// LDS layout of the per-mode phase: |W|^2 as [C][PS] floats, the tile's bin-table slice as [C][TS]
+// entries, then the per-bin weights.  A half wave covers 16 columns x 2 threads of a column, and
+// the threads of a column read neighbouring modes; a column stride of 2 mod 32 words puts the 32
+// reads of a half wave into distinct banks (the table's two threads share a word).
+template <int L>
+struct AdjLds {
+  static constexpr int C = ColTile<L, 0>::C;
+  static constexpr int PS = (L + 31) / 32 * 32 + 2;
+  static constexpr int TS = (L + 63) / 64 * 64 + 4;
+  static constexpr size_t fixed = (size_t)C * PS * 4 + (size_t)C * TS * 2;
+};
+
+// per-mode accumulation: one evaluation of H, or the mean of two on a Nyquist plane of a rotated
+// filter (H_sym, differentiated term by term); cb = w_m omega 2 |W|^2
+__device__ __forceinline__ void adj_acc(double (&acc)[7], float cb, const LnhOut& o) {
+  const float wt = cb * o.H * o.H;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) acc[j] += (double)(wt * o.r[j]);
+}
+__device__ __forceinline__ void adj_acc2(double (&acc)[7], float cb, const LnhOut& o1, const LnhOut& o2) {
+  const float hs = 0.5f * (o1.H + o2.H);
+  const float w1 = 0.5f * cb * hs * o1.H, w2 = 0.5f * cb * hs * o2.H;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) acc[j] += (double)fmaf(w1, o1.r[j], w2 * o2.r[j]);
+}
+
+// Persistent over tiles (tile = blockIdx.x + k gridDim.x, a fixed assignment, so the sums are
+// reproducible): each tile's columns are transformed, |W|^2 and the tile's bin-table slice go to
+// LDS, the next tile's columns are requested into the transform's registers, and the per-mode sums
+// run while they arrive.  One row of partials per workgroup.
 template <int L, int NDIM>
 __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, 0>::C, T = ColTile<L, 0>::T;
+  constexpr int PS = AdjLds<L>::PS, TS = AdjLds<L>::TS;
   using Rad = typename Plan<L>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
+  constexpr float LN2 = 0.69314718055994531f;
   extern __shared__ float2 lds[];
   __shared__ double red[7][T / 64];
-  int b;
-  long long tile;
-  if (!map_tile(a.sc, b, tile)) return;
   const int tid = threadIdx.x;
   const int c = tid % C, p = tid / C;
-  const int g = (int)tile * C + c;
-  const bool valid = g < a.gm.ncol;
-  const ColIO io = col_io<L>(a.spec, a.Nh, a.gm.inner0, g, p);
-  float2 v[E];
-  col_load<L, R1, P, E>(v, io);
-  fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, 0>::RS, p, a.tw);
-
-  // per-bin weights into LDS (the exchange buffer is free after the transform)
-  double* cf = reinterpret_cast<double*>(lds);
-  __syncthreads();
+  const int n0 = a.gm.n0;
+  float* pw = reinterpret_cast<float*>(lds);
+  uint16_t* tb = reinterpret_cast<uint16_t*>(pw + C * PS);
+  double* cf = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + a.cf_off);
   for (int i = tid; i <= a.nb; i += T) cf[i] = a.coef[i];
-  __syncthreads();
-  const double gamma = cf[a.nb];
+  const FiltDev f = a.filt;
   double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (valid) {
-    const ColCoord cc = col_coord(a.gm, g);
-    const FiltDev f = a.filt;
-#pragma unroll 4
-    for (int s = 0; s < E; ++s) {
-      const int e = slot_index<L, RL, P>(s, p);
-      float dH[7];
-      const float Hs = hsym_partials<NDIM>(f, a.width, a.gm, cc, e, dH);
-      const int bin = (int)a.table[(unsigned)(g * L + e)];
-      const float omega = (float)(cf[bin] - gamma);
-      const float W2 = v[s].x * v[s].x + v[s].y * v[s].y;
-      const float cfac = cc.wm * omega * 2.0f * Hs * W2;
+  int tile = blockIdx.x;
+  float2 v[E];
+  col_load<L, R1, P, E>(v, col_io<L>(a.spec, a.Nh, a.gm.inner0, tile * C + c, p));
+  for (; tile < a.ntiles; tile += gridDim.x) {
+    const int g = tile * C + c;
+    fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, 0>::RS, p, a.tw);
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < 7; ++j) acc[j] += (double)(cfac * dH[j]);
+    for (int s = 0; s < E; ++s) pw[c * PS + slot_index<L, RL, P>(s, p)] = v[s].x * v[s].x + v[s].y * v[s].y;
+    {
+      const int g0 = tile * C;
+      const int ncv = a.gm.ncol - g0 < C ? a.gm.ncol - g0 : C;
+      const uint16_t* src = a.table + (size_t)g0 * L;
+      if constexpr (L % 8 == 0) {
+        for (int i = tid; i < ncv * (L / 8); i += T) {
+          const uint4 w = reinterpret_cast<const uint4*>(src)[i];
+          uint32_t* d = reinterpret_cast<uint32_t*>(tb + ((8 * i) / L) * TS + (8 * i) % L);
+          d[0] = w.x;
+          d[1] = w.y;
+          d[2] = w.z;
+          d[3] = w.w;
+        }
+      } else {
+        for (int i = tid; i < ncv * L; i += T) tb[(i / L) * TS + i % L] = src[i];
+      }
     }
+    __syncthreads();
+    if (tile + (int)gridDim.x < a.ntiles)
+      col_load<L, R1, P, E>(v, col_io<L>(a.spec, a.Nh, a.gm.inner0, (tile + (int)gridDim.x) * C + c, p));
+    if (g < a.gm.ncol) {
+      const ColCoord cc = col_coord(a.gm, g);
+      const double gamma = cf[a.nb];
+      const float* pc = pw + c * PS;
+      const uint16_t* tc = tb + c * TS;
+      const float kx = cc.kx_c;
+      const float wm2 = 2.0f * cc.wm;
+      if constexpr (NDIM == 3) {
+        const bool partner = f.rotated && (cc.nyq_x || cc.nyq_y);
+        const Lnh3Col c1 = lnh3_col(f, kx, cc.ky);
+        const Lnh3Col c2 = partner ? lnh3_col(f, cc.nyq_x ? -kx : kx, cc.nyq_y ? -cc.ky : cc.ky) : c1;
+#pragma unroll 2
+        for (int k = 0; k < E; ++k) {
+          const int e = p + P * k;
+          const float kz = (float)(e < n0 / 2 ? e : e - n0) * a.gm.kap0;
+          const float cb = wm2 * (float)(cf[tc[e]] - gamma) * pc[e];
+          LnhOut o1;
+          lnh3(f, c1, kz, o1);
+          if (partner) {
+            LnhOut o2;
+            lnh3(f, c2, kz, o2);
+            adj_acc2(acc, cb, o1, o2);
+          } else {
+            adj_acc(acc, cb, o1);
+          }
+        }
+      } else {
+#pragma unroll 2
+        for (int k = 0; k < E; ++k) {
+          const int e = p + P * k;
+          const float ky = (float)(e < n0 / 2 ? e : e - n0) * a.gm.kap0;
+          const float cb = wm2 * (float)(cf[tc[e]] - gamma) * pc[e];
+          LnhOut o1;
+          lnh2(f, kx, ky, o1);
+          if (f.rotated && (cc.nyq_x || 2 * e == n0)) {
+            LnhOut o2;
+            lnh2(f, cc.nyq_x ? -kx : kx, 2 * e == n0 ? -ky : ky, o2);
+            adj_acc2(acc, cb, o1, o2);
+          } else {
+            adj_acc(acc, cb, o1);
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
+  // the per-filter factors of the seven terms
+  const double kf[7] = {-(double)f.ia, -(double)f.ib, -(double)f.ic, (double)(LN2 * f.ip), 1.0, (double)f.inv2w2,
+                        (double)f.inv2w2 / (double)a.width};
 #pragma unroll
   for (int j = 0; j < 7; ++j) {
-    const double sj = wave_sum(acc[j]);
+    const double sj = wave_sum(acc[j] * kf[j]);
     if ((tid & 63) == 0) red[j][tid >> 6] = sj;
   }
   __syncthreads();
   if (tid < 7) {
     double s = 0.0;
     for (int w = 0; w < T / 64; ++w) s += red[tid][w];
-    a.partials[tile * 8 + tid] = s;
+    a.partials[(long long)blockIdx.x * 8 + tid] = s;
   }
 }
 
+// workgroups of a kernel that fit on the device at once (cached per device, kernel and LDS size)
+static hipError_t resident_blocks(const void* kern, int threads, size_t lds, int* slots) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, size_t>, int> cache;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const auto key = std::make_tuple(dev, kern, lds);
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) {
+    *slots = it->second;
+    return hipSuccess;
+  }
+  int ncu = 0, per_cu = 0;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1 || ncu < 1) return hipErrorInvalidConfiguration;
+  cache[key] = *slots = per_cu * ncu;
+  return hipSuccess;
+}
+
 template <int L>
-static hipError_t launch_cols_adjoint_L(const AdjointArgs& a, hipStream_t st) {
-  constexpr int T = ColTile<L, 0>::T;
+static size_t adjoint_cf_off() {
   const size_t x = col_xchg_bytes<L, 0>();
-  const size_t c = (size_t)(a.nb + 1) * 8;
-  const size_t lds = x > c ? x : c;
+  const size_t f = AdjLds<L>::fixed;
+  return ((x > f ? x : f) + 15) / 16 * 16;
+}
+
+template <int L>
+static hipError_t launch_cols_adjoint_L(AdjointArgs a, hipStream_t st, int* grid_out) {
+  constexpr int T = ColTile<L, 0>::T;
+  a.cf_off = (int)adjoint_cf_off<L>();
+  const size_t lds = (size_t)a.cf_off + (size_t)(a.nb + 1) * 8;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const void* kern = a.gm.ndim == 2 ? reinterpret_cast<const void*>(&k_cols_adjoint<L, 2>)
+                                    : reinterpret_cast<const void*>(&k_cols_adjoint<L, 3>);
+  int slots = 0;
+  const hipError_t e = resident_blocks(kern, T, lds, &slots);
+  if (e != hipSuccess) return e;
+  const int grid = a.ntiles < slots ? a.ntiles : slots;
+  *grid_out = grid;
   if (a.gm.ndim == 2)
-    hipLaunchKernelGGL((k_cols_adjoint<L, 2>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+    hipLaunchKernelGGL((k_cols_adjoint<L, 2>), dim3(grid), dim3(T), lds, st, a);
   else
-    hipLaunchKernelGGL((k_cols_adjoint<L, 3>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+    hipLaunchKernelGGL((k_cols_adjoint<L, 3>), dim3(grid), dim3(T), lds, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st) {
+hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st, int* grid) {
   switch (L) {
-#define X(LL) case LL: return launch_cols_adjoint_L<LL>(a, st);
+#define X(LL) case LL: return launch_cols_adjoint_L<LL>(a, st, grid);
     HU_COL_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -230,26 +382,42 @@ hipError_t launch_grad_coef(const GradCoefArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// fixed-order sum of the per-tile partials into the seven gradient components
-__global__ void __launch_bounds__(256) k_grad_final(GradFinalArgs a) {
-  __shared__ double red[256];
+// fixed-order sum of the per-tile partials into the seven gradient components: each thread sums
+// whole partial rows (tiles tid, tid + 1024, ...), then waves and the workgroup reduce in a fixed
+// order
+constexpr int GF_THREADS = 1024;
+
+__global__ void __launch_bounds__(GF_THREADS) k_grad_final(GradFinalArgs a) {
+  __shared__ double red[7][GF_THREADS / 64];
   const int tid = threadIdx.x;
+  double s[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int t = tid; t < a.ntiles; t += GF_THREADS) {
+    const double2* row = reinterpret_cast<const double2*>(a.partials + (long long)t * 8);
+    const double2 q0 = row[0], q1 = row[1], q2 = row[2], q3 = row[3];
+    s[0] += q0.x;
+    s[1] += q0.y;
+    s[2] += q1.x;
+    s[3] += q1.y;
+    s[4] += q2.x;
+    s[5] += q2.y;
+    s[6] += q3.x;
+  }
+#pragma unroll
   for (int j = 0; j < 7; ++j) {
-    double s = 0.0;
-    for (int t = tid; t < a.ntiles; t += 256) s += a.partials[(long long)t * 8 + j];
-    red[tid] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
-    if (tid == 0) a.grad[j] = red[0];
-    __syncthreads();
+    const double w = wave_sum(s[j]);
+    if ((tid & 63) == 0) red[j][tid >> 6] = w;
+  }
+  __syncthreads();
+  if (tid < 7) {
+    double r = 0.0;
+    for (int w = 0; w < GF_THREADS / 64; ++w) r += red[tid][w];
+    a.grad[tid] = r;
   }
 }
 
 hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(GF_THREADS), 0, st, a);
   return hipGetLastError();
 }
 

@@ -330,7 +330,7 @@ int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins
   HU_HIP(timed("grad_coef", st, [&] { return launch_grad_coef(ga, st); }));
   AdjointArgs aa{};
   aa.gm = axis0(g);
-  aa.sc = col_sched(g.n[0], 0, aa.gm.ncol, 1);
+  aa.ntiles = lay.tiles;
   aa.spec = spec;
   aa.Nh = g.Nhp;
   aa.filt = filt_dev(*filt);
@@ -341,8 +341,9 @@ int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins
   aa.tw = tw_0;
   aa.coef = coef;
   aa.partials = partials;
-  HU_HIP(timed("cols_adjoint", st, [&] { return launch_cols_adjoint(g.n[0], aa, st); }));
-  GradFinalArgs fa{partials, lay.tiles, grad};
+  int rows = 0;
+  HU_HIP(timed("cols_adjoint", st, [&] { return launch_cols_adjoint(g.n[0], aa, st, &rows); }));
+  GradFinalArgs fa{partials, rows, grad};
   HU_HIP(timed("grad_final", st, [&] { return launch_grad_final(fa, st); }));
   return HU_OK;
 }

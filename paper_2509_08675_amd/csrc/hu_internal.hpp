@@ -155,7 +155,7 @@ struct ThreshArgs {
 // Adjoint of the filter with respect to theta = (a, b, c, p, rot, k0, w): the axis-0 pass over the
 // noise spectrum W, with the per-bin loss weights omega(k) = coef[b(k)] - coef[nb].
 struct AdjointArgs {
-  ColSched sc;
+  int ntiles;              // column tiles of the axis-0 pass
   const float2* spec;      // W transformed along every axis but axis 0, [Nh]
   long long Nh;
   Axis0Geom gm;
@@ -166,7 +166,8 @@ struct AdjointArgs {
   const uint16_t* table;   // bin of each mode or null
   const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
   const double* coef;      // [nb + 1]: beta_b per bin, then gamma
-  double* partials;        // [tiles][8]: the 7 gradient partial sums
+  double* partials;        // [workgroups][8]: the 7 gradient partial sums
+  int cf_off;              // LDS byte offset of the per-bin weights (set by the launcher)
 };
 
 struct GradCoefArgs {
@@ -181,8 +182,8 @@ struct GradCoefArgs {
 };
 
 struct GradFinalArgs {
-  const double* partials;  // [ntiles][8]
-  int ntiles;
+  const double* partials;  // [rows][8]
+  int ntiles;              // rows
   double* grad;            // [7] out
 };
 
@@ -202,7 +203,7 @@ struct FilterSpecArgs {
   uint64_t* cnt;           // [nb] out or null
 };
 
-hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st);
+hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st, int* grid);
 hipError_t launch_grad_coef(const GradCoefArgs& a, hipStream_t st);
 hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);
 hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st);

@@ -16,10 +16,6 @@
 //
 // The expected spectrum of a filter: E[P] per mode is sigma_f^2 N H^2 / sum_k w_k H^2 (Eqs. (10)-(11)
 // with the normalisation of Eq. (15)), binned like the field's spectrum.
-#include <map>
-#include <mutex>
-#include <tuple>
-
 #include "hu_common.hpp"
 
 namespace hu {
@@ -285,29 +281,6 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
     for (int w = 0; w < T / 64; ++w) s += red[tid][w];
     a.partials[(long long)blockIdx.x * 8 + tid] = s;
   }
-}
-
-// workgroups of a kernel that fit on the device at once (cached per device, kernel and LDS size)
-static hipError_t resident_blocks(const void* kern, int threads, size_t lds, int* slots) {
-  static std::mutex mu;
-  static std::map<std::tuple<int, const void*, size_t>, int> cache;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  const auto key = std::make_tuple(dev, kern, lds);
-  std::lock_guard<std::mutex> lock(mu);
-  const auto it = cache.find(key);
-  if (it != cache.end()) {
-    *slots = it->second;
-    return hipSuccess;
-  }
-  int ncu = 0, per_cu = 0;
-  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
-  if (e != hipSuccess) return e;
-  if (per_cu < 1 || ncu < 1) return hipErrorInvalidConfiguration;
-  cache[key] = *slots = per_cu * ncu;
-  return hipSuccess;
 }
 
 template <int L>

@@ -209,7 +209,7 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
       cy.ncol = g.n[0] * g.nxh;
       cy.inner = g.nxh;
       cy.tw = tw_1;
-      cy.sc = col_sched(g.n[1], 0, cy.ncol, B);
+      cy.sc = col_sched(g.n[1], 0, cy.ncol, B, Y_PASS_GROUP);
       HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, 0, cy, st); }));
     }
     BinArgs ba{};
@@ -315,7 +315,7 @@ int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins
     cy.ncol = g.n[0] * g.nxh;
     cy.inner = g.nxh;
     cy.tw = tw_1;
-    cy.sc = col_sched(g.n[1], 0, cy.ncol, 1);
+    cy.sc = col_sched(g.n[1], 0, cy.ncol, 1, Y_PASS_GROUP);
     HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, 0, cy, st); }));
   }
   GradCoefArgs ga{};

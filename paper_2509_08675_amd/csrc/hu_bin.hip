@@ -10,6 +10,7 @@
 
 namespace hu {
 
+// One tile per workgroup; the FP64 histogram shares the exchange buffer and is flushed per tile.
 template <int L, int V>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
@@ -43,9 +44,78 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
   if (out) hist_flush(hs, a.nb, 1.0 / (double)a.N, out, tid, T);
 }
 
+// Persistent, when the FP64 histogram fits beyond the exchange buffer with two workgroups per CU:
+// each workgroup takes a contiguous chunk of (field, tile) pairs, keeps one histogram per field
+// (flushed when the field changes) and requests the next tile's columns into the transform's
+// registers once the current power values are in LDS, so their loads overlap the binning.
 template <int L, int V>
-static hipError_t launch_cols_bin_L(const BinArgs& a, hipStream_t st) {
+__global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin_keep(BinArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
+  constexpr int LP = ColTile<L, V>::LP;
+  using Rad = typename Plan<L>::fwd;
+  constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
+  extern __shared__ float2 lds[];
+  const int total = a.sc.batch * a.sc.ntiles;
+  const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
+  int lin = (int)blockIdx.x * per;
+  const int end = lin + per < total ? lin + per : total;
+  if (lin >= end) return;
+  const int tid = threadIdx.x;
+  const int c = tid % C, p = tid / C;
+  float* pw = reinterpret_cast<float*>(lds);
+  double* hs = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + a.hs_off);
+  const double scale = 1.0 / (double)a.N;
+  int b = lin / a.sc.ntiles;
+  int tile = lin - b * a.sc.ntiles;
+  for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
+  float2 v[E];
+  col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, tile * C + c, p));
+  for (;;) {
+    const int g = tile * C + c;
+    const bool valid = g < a.gm.ncol;
+    fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
+    const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
+    __syncthreads();                                // the exchange buffer is free from here
+#pragma unroll
+    for (int s = 0; s < E; ++s)
+      pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = wm * (v[s].x * v[s].x + v[s].y * v[s].y);
+    __syncthreads();
+    ++lin;
+    const int bn = lin / a.sc.ntiles, tn = lin - bn * a.sc.ntiles;
+    if (lin < end) col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)bn * a.Nh, a.Nh, a.gm.inner0, tn * C + c, p));
+    if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, g, p);
+    __syncthreads();
+    if (lin == end || bn != b) {
+      double* out = a.io ? a.io[b].pm1_sum : field_ptr(a.sum, a.nb, b);
+      if (out) hist_flush(hs, a.nb, scale, out, tid, T);
+      if (lin == end) break;
+      __syncthreads();                              // the flush has read hs
+      for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
+    }
+    b = bn;
+    tile = tn;
+  }
+}
+
+template <int L, int V>
+static hipError_t launch_cols_bin_L(BinArgs a, hipStream_t st) {
   constexpr int T = ColTile<L, V>::T;
+  const long long total = (long long)a.sc.batch * a.sc.ntiles;
+  if (total == 0) return hipSuccess;
+  const size_t x = col_xchg_bytes<L, V>();
+  const size_t pwb = (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4;
+  const size_t base = ((x > pwb ? x : pwb) + 15) / 16 * 16;
+  const size_t keep = base + (size_t)a.nb * 8;
+  if (keep <= LDS_PER_CU / 2) {
+    a.hs_off = (int)base;
+    int slots = 0;
+    const hipError_t e = resident_blocks(reinterpret_cast<const void*>(&k_cols_bin_keep<L, V>), T, keep, &slots);
+    if (e != hipSuccess) return e;
+    const long long per = (total + slots - 1) / slots;
+    const unsigned grid = (unsigned)((total + per - 1) / per);
+    hipLaunchKernelGGL((k_cols_bin_keep<L, V>), dim3(grid), dim3(T), keep, st, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_cols_bin<L, V>), dim3(sched_blocks(a.sc)), dim3(T), (col_lds_bytes_t<L, V>(a.nb)), st, a);
   return hipGetLastError();
 }

@@ -26,22 +26,22 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols(ColsArgs a) {
 }
 
 template <int L, int V>
-static ColSched col_sched_L(long long ncol, int batch) {
+static ColSched col_sched_L(long long ncol, int batch, int group) {
   constexpr int C = ColTile<L, V>::C;
   ColSched s;
   s.ntiles = (int)((ncol + C - 1) / C);
-  // one workgroup per tile (every layout gives each tile whole 128-byte line runs); the
-  // same-XCD grouping of neighbouring tiles is kept for G > 1
-  s.G = 1;
+  // one workgroup per tile; `group` consecutive tiles go to the same XCD (they share the 128-byte
+  // lines at their boundaries when the column index runs over rows that are not line-aligned)
+  s.G = group > 0 ? group : 1;
   s.ntiles_pad = (s.ntiles + s.G - 1) / s.G * s.G;
   s.batch = batch;
   return s;
 }
 
-ColSched col_sched(int L, int variant, long long ncol, int batch) {
+ColSched col_sched(int L, int variant, long long ncol, int batch, int group) {
   switch (L) {
 #define X(LL) \
-  case LL: return variant ? col_sched_L<LL, 1>(ncol, batch) : col_sched_L<LL, 0>(ncol, batch);
+  case LL: return variant ? col_sched_L<LL, 1>(ncol, batch, group) : col_sched_L<LL, 0>(ncol, batch, group);
     HU_COL_LENGTHS(X)
 #undef X
     default: return ColSched{0, 0, 1, 0};

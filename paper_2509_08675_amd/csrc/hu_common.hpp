@@ -11,6 +11,8 @@
 
 namespace hu {
 
+constexpr size_t LDS_PER_CU = 160 * 1024;   // gfx950
+
 // ---------------------------------------------------------------------------------------------
 // tile widths: transforms per workgroup
 // ---------------------------------------------------------------------------------------------

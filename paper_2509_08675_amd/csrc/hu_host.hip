@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <tuple>
 #include <utility>
 
 #include "hu_host.hpp"
@@ -327,6 +328,29 @@ Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan) {
   return L;
 }
 
+// workgroups of a kernel that fit on the device at once (cached per device, kernel and LDS size)
+hipError_t resident_blocks(const void* kern, int threads, size_t lds, int* slots) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, size_t>, int> cache;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const auto key = std::make_tuple(dev, kern, lds);
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) {
+    *slots = it->second;
+    return hipSuccess;
+  }
+  int ncu = 0, per_cu = 0;
+  e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1 || ncu < 1) return hipErrorInvalidConfiguration;
+  cache[key] = *slots = per_cu * ncu;
+  return hipSuccess;
+}
+
 FiltDev filt_dev(const hu_filter& f) {
   FiltDev d{};
   d.cr = (float)std::cos(f.rot);
@@ -525,7 +549,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     cy.ncol = g.n[0] * g.nxh;
     cy.inner = g.nxh;
     cy.tw = tw_1;
-    cy.sc = col_sched(g.n[1], r.plan.v[P_COLY], cy.ncol, B);
+    cy.sc = col_sched(g.n[1], r.plan.v[P_COLY], cy.ncol, B, Y_PASS_GROUP);
     HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st); }));
   }
 

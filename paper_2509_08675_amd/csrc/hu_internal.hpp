@@ -109,7 +109,7 @@ struct FinalizeArgs {
 };
 
 struct BinArgs {
-  ColSched sc;
+  ColSched sc;             // tiles per field and fields (the launch is persistent over them)
   const float2* spec;
   long long Nh, N;
   Axis0Geom gm;
@@ -119,6 +119,7 @@ struct BinArgs {
   const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
   double* sum;
   const FieldIO* io;       // per-field +-1 spectrum output (batch path) or null
+  int hs_off;              // LDS byte offset of the histogram (set by the launcher)
 };
 
 struct BinGeomArgs {
@@ -204,6 +205,9 @@ struct FilterSpecArgs {
 };
 
 hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st, int* grid);
+// workgroups of a kernel with this block size and LDS that are resident on the current device at
+// once (cached per device, kernel and LDS size)
+hipError_t resident_blocks(const void* kern, int threads, size_t lds, int* slots);
 hipError_t launch_grad_coef(const GradCoefArgs& a, hipStream_t st);
 hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);
 hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st);
@@ -215,7 +219,11 @@ hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st)
 hipError_t launch_rows_c2r(int L, bool thresh, int variant, const RowsZArgs& a, int batch, hipStream_t st);
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st);
 hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st);
-ColSched col_sched(int L, int variant, long long ncol, int batch);
+// `group` tiles in a row per XCD (see ColSched)
+ColSched col_sched(int L, int variant, long long ncol, int batch, int group = 1);
+// tile group of the 3D y passes: their columns run over x rows of n_x / 2 + 1 complex values,
+// which do not start on 128-byte lines, so neighbouring tiles share lines
+constexpr int Y_PASS_GROUP = 8;
 hipError_t launch_zero_u64(uint64_t* p, long long n, hipStream_t st);
 hipError_t launch_debug_philox(uint64_t seed, uint64_t first, uint64_t count, uint32_t* words, float* normals,
                                hipStream_t st);

@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the uneven batch and the 512^3 adjoint")
     ap.add_argument("--main-only", action="store_true",
                     help="time only the batched 2D workload (for profiler runs)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the 512^3 forward + adjoint (for profiler runs)")
     ap.add_argument("--workload", default="2d_2048x2048_x16", choices=("2d_2048x2048_x16", "3d_256x256x256_x4"),
                     help="with --main-only: which workload to time")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -74,9 +76,20 @@ def algorithmic_bytes(dims, batch):
     return fam, total
 
 
+def adjoint_bytes(dims):
+    """Compulsory HBM bytes per launch at one field of the forward (field and continuous spectrum, no
+    threshold) and of the adjoint: the gradient pass regenerates the noise spectrum (write), runs the
+    y pass (read + write) and reads it once in the axis-0 pass."""
+    N = math.prod(dims)
+    Nh = N // dims[-1] * (dims[-1] // 2 + 1)
+    t = 8 * Nh
+    return {"rows_r2c_noise": t, "cols_y_fwd": 2 * t, "cols_filter": 2 * t, "cols_y_inv": 2 * t,
+            "rows_c2r": t + 4 * N, "cols_adjoint": t}
+
+
 # the sources that define the pipeline's kernels and their launch shapes
 PIPELINE_SOURCES = ("hu_device.hpp", "hu_common.hpp", "hu_internal.hpp", "hu_host.hpp", "hu_rows.hip", "hu_cols.hip",
-                    "hu_filter.hip", "hu_bin.hip", "hu_host.hip")
+                    "hu_filter.hip", "hu_bin.hip", "hu_host.hip", "hu_adjoint.hip", "hu_api.hip")
 
 
 def field_bytes_min(dims):
@@ -215,7 +228,7 @@ def time_uneven_batch(hf, torch, steps, warmup):
                                 value=round(vox / (pms * 1e-3), 1), batched_speedup=round(pms / ms, 3)))
 
 
-def time_adjoint(hf, torch, steps):
+def time_adjoint(hf, torch, steps, warmup=1):
     """512^3: forward (field + continuous spectrum) and the adjoint of the spectrum-matching loss."""
     from paper_2509_08675_amd.workloads import C5
     dims, seed, bins = tuple(C5["dims"]), C5["seed"], (C5["nr"], 1)
@@ -241,7 +254,8 @@ def time_adjoint(hf, torch, steps):
     torch.cuda.synchronize()
 
     def timed(fn, k):
-        fn()
+        for _ in range(max(warmup, 1)):
+            fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(k):
@@ -293,6 +307,12 @@ PROFILE_COMMANDS = {
                   "python3 REPO/bench.py --copy-calibration",
     "copy_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/copy_write -o copy_write -- "
                   "python3 REPO/bench.py --copy-calibration",
+    "adj_trace": "rocprofv3 --kernel-trace --stats -f csv -d DIR/3d_512x512x512_adjoint/trace -o trace -- "
+                 "python3 REPO/bench.py --adjoint-only --steps 10 --warmup 2",
+    "adj_fetch": "rocprofv3 --pmc FETCH_SIZE -f csv -d DIR/3d_512x512x512_adjoint/fetch -o fetch -- "
+                 "python3 REPO/bench.py --adjoint-only --steps 2 --warmup 1",
+    "adj_write": "rocprofv3 --pmc WRITE_SIZE -f csv -d DIR/3d_512x512x512_adjoint/write -o write -- "
+                 "python3 REPO/bench.py --adjoint-only --steps 2 --warmup 1",
     "sq1": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU "
            "SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU_TRANS_F32 -f csv -d DIR/sq1 -o sq1 -- "
            "python3 REPO/bench.py --main-only --steps 2 --warmup 1",
@@ -305,17 +325,19 @@ PROFILE_COMMANDS = {
 def kernel_family(name):
     """Pipeline family of a rocprofv3 kernel name (None for other kernels)."""
     import re
-    m = re.search(r"hu::(k_\w+)<([^>]*)>", name)
+    m = re.search(r"hu::(k_\w+)(?:<([^>]*)>)?", name)
     if not m:
-        return "finalize" if "k_finalize" in name else None
-    k, args = m.group(1), [t.strip() for t in m.group(2).split(",")]
+        return None
+    k, args = m.group(1), [t.strip() for t in (m.group(2) or "").split(",")]
+    if k in ("k_finalize", "k_grad_coef", "k_grad_final", "k_cols_adjoint"):
+        return k[2:]
     if k == "k_rows_r2c":
         return "rows_r2c_noise" if args[1] == "0" else "rows_r2c"
     if k == "k_rows_c2r":
         return "rows_c2r_thresh" if args[1] == "true" else "rows_c2r"
     if k == "k_cols":
         return "cols_y_inv" if args[1] == "true" else "cols_y_fwd"
-    return {"k_cols_filter": "cols_filter", "k_cols_bin": "cols_bin"}.get(k)
+    return {"k_cols_filter": "cols_filter", "k_cols_bin": "cols_bin", "k_cols_bin_keep": "cols_bin"}.get(k)
 
 
 def _csv_rows(d, suffix):
@@ -366,15 +388,21 @@ def summarize_profiles(d):
            "| counter | KiB per copy dispatch | bytes moved | factor |", "|---|---|---|---|",
            "| FETCH_SIZE | %.0f | %d | %.4f |" % (cf, copy_bytes, f_fetch),
            "| WRITE_SIZE | %.0f | %d | %.4f |" % (cw, copy_bytes, f_write), ""]
-    for cfg in (C2, C3):
+    from paper_2509_08675_amd.workloads import C5
+    for cfg in (C2, C3, C5):
         w = cfg["name"]
         wd = os.path.join(d, w)
         if not os.path.isdir(wd):
             continue
-        fam_bytes, total = algorithmic_bytes(cfg["dims"], len(cfg["seeds"]))
+        if cfg is C5:
+            fam_bytes = adjoint_bytes(cfg["dims"])
+        else:
+            fam_bytes, total = algorithmic_bytes(cfg["dims"], len(cfg["seeds"]))
         md += ["## %s" % w, "", "### Kernel trace (`--kernel-trace --stats`)", "",
                "| kernel | family | calls | mean us | share % |", "|---|---|---|---|---|"]
         for r in _csv_rows(os.path.join(wd, "trace"), "_kernel_stats.csv"):
+            if "hu::" not in r["Name"]:
+                continue                # the harness's own small torch kernels
             md.append("| `%s` | %s | %s | %.2f | %s |" % (r["Name"].replace("|", "/")[:90], kernel_family(r["Name"]),
                                                         r["Calls"], float(r["AverageNs"]) / 1e3, r["Percentage"]))
         fe = _per_dispatch(os.path.join(wd, "fetch"), "FETCH_SIZE")
@@ -452,6 +480,9 @@ def main():
         return
     from paper_2509_08675_amd import hufield as hf
     from paper_2509_08675_amd.workloads import C2, C3
+    if args.adjoint_only:
+        print(json.dumps(time_adjoint(hf, torch, args.steps, args.warmup)), flush=True)
+        return
 
     cfg = C3 if (args.main_only and args.workload == C3["name"]) else C2
     el, prof = time_pipeline(hf, torch, cfg, args.steps, args.warmup)

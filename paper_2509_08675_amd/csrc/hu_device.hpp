@@ -477,6 +477,16 @@ struct FiltDev {
   int rotated;           // rot != 0 (H_sym differs from H on x / y Nyquist planes)
 };
 
+// Load of a read-only table entry at a wave-uniform index through the constant address space, so
+// the compiler issues a scalar load (the host pass never runs device code and reads normally).
+__device__ __forceinline__ float2 uniform_load2(const float2* p, int i) {
+#if __HIP_DEVICE_COMPILE__
+  return ((const __attribute__((address_space(4))) float2*)p)[i];
+#else
+  return p[i];
+#endif
+}
+
 // raw hardware log2 / exp2 (v_log_f32, v_exp_f32)
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }

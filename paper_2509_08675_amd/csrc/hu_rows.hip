@@ -66,17 +66,40 @@ struct RowWalk {
 // R2C split twist of every row of the tile from Z in LDS (padded, natural order) to the half
 // spectrum, in address order:
 //   X[k] = (Z[k] + Z*[L-k])/2 - (i/2) e^{-2 pi i k / 2L} (Z[k] - Z*[L-k]),  X[L] = Re Z[0] - Im Z[0].
-template <int L, int C, int T, bool TILED, int RS>
-__device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, rsrc_t spec, unsigned tile_off,
-                                                 unsigned run_stride, int rows_here, int tid) {
+// The twist factor of element k, e^{-i pi k / L} (the table tw2), for the units of the row walk.
+// Where k splits into a per-thread part and a per-iteration part (k = kt + 4 QS it in the steady
+// 2D walk, k = kt + PR it in the 3D walk), FACT forms it as tw2[kt] tw2[ki]: one vector load per
+// thread and a uniform (scalar) load per iteration instead of a vector load per unit.
+template <int L, int C, int T, bool TILED>
+struct TwistSplit {
   using W = RowWalk<L, C, T, TILED>;
-  float2 w[W::ITERS];
+  static constexpr bool ok = W::STEADY || !TILED;
+  static constexpr int KI = W::STEADY ? 4 * W::QS : W::PR;   // k step per iteration
+  __device__ __forceinline__ static int kt(int tid) {
+    if constexpr (W::STEADY) return 4 * (tid / W::GS) + ((tid % W::GS) & 3);
+    else return tid % W::PR;
+  }
+};
+
+template <int L, int C, int T, bool TILED, int RS, bool FACT>
+__device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, const float2* tw2p, rsrc_t spec,
+                                                 unsigned tile_off, unsigned run_stride, int rows_here, int tid) {
+  using W = RowWalk<L, C, T, TILED>;
+  using TS = TwistSplit<L, C, T, TILED>;
+  constexpr bool SPLIT = FACT && TS::ok;
+  constexpr int NW = SPLIT ? 1 : W::ITERS;
+  float2 w[NW];
+  if constexpr (SPLIT) {
+    const int kt = TS::kt(tid);
+    w[0] = buf_load2(tw2, (unsigned)(kt < L ? kt : 0) * 8u, 0);
+  } else {
 #pragma unroll
-  for (int it = 0; it < W::ITERS; ++it) {          // the twiddles first: all loads in flight together
-    int cc, k;
-    unsigned goff;
-    const bool in = W::unit(tid, it, run_stride, rows_here, cc, k, goff);
-    w[it] = buf_load2(tw2, (unsigned)(in && k < L ? k : 0) * 8u, 0);
+    for (int it = 0; it < W::ITERS; ++it) {        // the twiddles first: all loads in flight together
+      int cc, k;
+      unsigned goff;
+      const bool in = W::unit(tid, it, run_stride, rows_here, cc, k, goff);
+      w[it] = buf_load2(tw2, (unsigned)(in && k < L ? k : 0) * 8u, 0);
+    }
   }
 #pragma unroll
   for (int it = 0; it < W::ITERS; ++it) {
@@ -92,7 +115,13 @@ __device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, 
       const float2 zk = lz[lidx(k)];
       const float2 zm = cconj(lz[lidx(k == 0 ? 0 : L - k)]);
       const float2 A = cadd(zk, zm), B = csub(zk, zm);
-      X = cscale(cadd(A, mul_mi<false>(cmul(w[it], B))), 0.5f);
+      float2 tw;
+      if constexpr (SPLIT) {
+        tw = (TS::KI * it < L) ? cmul(w[0], uniform_load2(tw2p, TS::KI * it)) : w[0];
+      } else {
+        tw = w[it];
+      }
+      X = cscale(cadd(A, mul_mi<false>(cmul(tw, B))), 0.5f);
     }
     buf_store2(spec, X, (tile_off + goff) * 8u, 0);
   }
@@ -258,7 +287,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
   tile_geom<TILED, L>(row0, a.nrows, tile_off, run_stride);
   const rsrc_t spec = make_rsrc(a.spec + (long long)b * a.Nh, (unsigned)(a.Nh * 8));
   const rsrc_t tw2 = make_rsrc(a.tw2, (unsigned)(L * 8));
-  twist_store_rows<L, C, T, TILED, RS>(lds, tw2, spec, tile_off, run_stride, rows_here, tid);
+  twist_store_rows<L, C, T, TILED, RS, false>(lds, tw2, a.tw2, spec, tile_off, run_stride, rows_here, tid);
 }
 
 // C2R along x -> normalise -> field, sign map, counts -> R2C of the +-1 row (THRESH).
@@ -288,6 +317,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   // ---- pre-twist: Z[k] = (X[k] + X*[L-k]) + i e^{+2 pi i k / 2L} (X[k] - X*[L-k])
   float2 v[E];
   {
+    const float2 tp = buf_load2(tw2, (unsigned)p * 8u, 0);
     using M = LoadMap<L, R1, P, E>;
     using MM = MirrorMap<L, R1, P, E>;
 #pragma unroll
@@ -296,7 +326,8 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
       const int k = slot_index<L, R1, P>(s, p);
       const float2 xk = M::lin ? lrow[lidx(p) + M::off(0, bb, r)] : lrow[lidx(k)];
       const float2 xc = cconj(MM::lin ? lrow[lidx(L - p) + MM::off(0, bb, r)] : lrow[lidx(L - k)]);
-      const float2 w = cconj(buf_load2(tw2, (unsigned)p * 8u, (unsigned)slot_index<L, R1, P>(s, 0) * 8u));
+      // e^{+i pi k / L} = conj(tw2[p] tw2[k - p]): the second factor is uniform (a scalar load)
+      const float2 w = cconj(cmul(tp, uniform_load2(a.tw2, slot_index<L, R1, P>(s, 0))));
       v[s] = cadd(cadd(xk, xc), mul_mi<true>(cmul(w, csub(xk, xc))));
     }
   }
@@ -358,7 +389,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
     constexpr int RLF = RadInfo<RadF>::last;
     slot_store<L, RLF, P, E>(v, lrow, p);
     __syncthreads();
-    twist_store_rows<L, C, T, TILED, RS>(lds, tw2, spec, tile_off, run_stride, rows_here, tid);
+    twist_store_rows<L, C, T, TILED, RS, true>(lds, tw2, a.tw2, spec, tile_off, run_stride, rows_here, tid);
     if (tid == 0 && cout) {
       unsigned long long np = 0, nn = 0;
       for (int w = 0; w < (T + 63) / 64; ++w) { np += red_u[0][w]; nn += red_u[1][w]; }

@@ -104,6 +104,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
   double* cont_out = a.io ? a.io[b].cont_sum : field_ptr(a.cont_sum, a.nb, b);
   double G = 0.0, F0 = 0.0;
   float lm = -1.0e30f;
+#pragma unroll 4
   for (int w = tid; w < a.ntiles; w += 256) {
     G += part[4 * w + 0];
     F0 += part[4 * w + 1];
@@ -145,7 +146,9 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
   }
   __syncthreads();
   if (cont_out) {
-    for (int i = tid; i < a.nb; i += 256) cont_out[i] *= fac;
+    const double f = fac;
+#pragma unroll 8
+    for (int i = tid; i < a.nb; i += 256) cont_out[i] *= f;
   }
 }
 

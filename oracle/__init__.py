@@ -16,7 +16,10 @@ Spectral Filtering" (arXiv 2509.08675):
 * demean and rescale, Eq. (15);
 * the sign map to a +-1 two-phase medium (Sec. II.B, last paragraphs);
 * binned power spectra of the continuous and the +-1 field (the figure rows of
-  Sec. III).
+  Sec. III);
+* the hyperuniformity diagnostics of Sec. II.A: the local variance over a spherical window
+  (Eq. (1)) in its Fourier form, the small-k exponent of a binned spectrum and the class of
+  Eqs. (6)-(7).
 
 Where the paper is silent (noise generator, FFT sign, band centre, rotation,
 Nyquist handling, binning) the readings are stated in each function.  Every
@@ -32,6 +35,7 @@ from .field import gen_field, threshold, pipeline
 from .spectrum import bin_table, bin_power, power_spectrum, continuous_spectrum_fused
 from .loss import (target_bins, spectrum_loss, spectrum_loss_grad, dlnH_half,
                    PARAM_NAMES)
+from .diagnostics import form_factor, window_variance, small_k_exponent, hyperuniformity_class, CLASSES
 
 __all__ = [
     "philox4x32_10", "uniforms_from_words", "box_muller", "white_noise",
@@ -40,4 +44,5 @@ __all__ = [
     "gen_field", "threshold", "pipeline",
     "bin_table", "bin_power", "power_spectrum", "continuous_spectrum_fused",
     "target_bins", "spectrum_loss", "spectrum_loss_grad", "dlnH_half", "PARAM_NAMES",
+    "form_factor", "window_variance", "small_k_exponent", "hyperuniformity_class", "CLASSES",
 ]

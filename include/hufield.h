@@ -72,7 +72,11 @@ enum {
 enum { HU_F32 = 0, HU_I8 = 1 };
 
 /* Operations for hu_workspace_size. */
-enum { HU_OP_GEN_FIELD = 0, HU_OP_PIPELINE = 1, HU_OP_POWER_SPECTRUM = 2, HU_OP_LOSS = 3, HU_OP_FILTER_SPECTRUM = 4 };
+enum { HU_OP_GEN_FIELD = 0, HU_OP_PIPELINE = 1, HU_OP_POWER_SPECTRUM = 2, HU_OP_LOSS = 3, HU_OP_FILTER_SPECTRUM = 4,
+       HU_OP_WINDOW_VARIANCE = 5 };
+
+/* Most window radii of one hu_window_variance call. */
+#define HU_MAX_RADII 32
 
 typedef struct hu_dims {
   int32_t ndim;   /* 2 or 3 */
@@ -151,6 +155,35 @@ int hu_pipeline(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64
  * Workspace: hu_workspace_size(HU_OP_FILTER_SPECTRUM, dims, 1, &bins, ...). */
 int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double* sum, uint64_t* cnt,
                        void* work, size_t work_bytes, void* stream);
+
+/* Hyperuniformity diagnostics (Sec. II.A).
+ *
+ * hu_window_variance: the local variance of Eq. (1) over a spherical window (a disk in 2D, a ball
+ * in 3D) of radius R, for each of n_radii radii (lattice units, finite, >= 0), of `batch` real
+ * periodic fields x (dtype HU_F32 or HU_I8, [B][N] device).  Averaging one Fourier mode of
+ * wavevector k over the window multiplies it by W(|k| R), W = 2 J_1(u)/u (2D) or
+ * 3 (sin u - u cos u)/u^3 (3D), so with X the unnormalised DFT and k_m = 2 pi m / n per axis
+ *   out[b][j] = sum_{m != 0} |X(m)|^2 / N^2 * W(|k_m| R_j)^2,
+ * the variance over all window positions of the window average of the field's trigonometric
+ * interpolant (R = 0 gives the field's variance).  radii: host array of n_radii (1..HU_MAX_RADII)
+ * values; out: device FP64 [B][n_radii].  W in FP32, sums in FP64, reduced in a fixed order
+ * (bit-reproducible).  Workspace: hu_workspace_size(HU_OP_WINDOW_VARIANCE, dims, batch, NULL, ...).
+ * HU_ERR_ARG for a bad radius count or value, HU_ERR_ALIGN for x or out not 16-byte aligned. */
+int hu_window_variance(hu_dims dims, int32_t batch, const void* x, int32_t dtype, const double* radii,
+                       int32_t n_radii, double* out, void* work, size_t work_bytes, void* stream);
+
+/* Small-k exponent of a binned spectrum (the alpha of spectral density ~ |k|^alpha, Sec. II.A):
+ * the least-squares slope of ln(sum_r / cnt_r) against ln((r + 1/2) / R) over radial bins
+ * r = 1..nfit (bin 0 holds the DC mode), the angular bins of a radius pooled.  sum and cnt are
+ * HOST arrays in the [R*A+1] layout of hu_power_spectrum.  Bins with cnt = 0 or sum <= 0 are
+ * skipped; HU_ERR_ARG when fewer than two remain or nfit is outside 1..R-1.  Host only. */
+int hu_small_k_exponent(const double* sum, const uint64_t* cnt, hu_bins bins, int32_t nfit, double* alpha);
+
+/* Class of Eqs. (6)-(7) for a small-k exponent alpha in dimension d: 0 hyperuniform class I
+ * (alpha > 1), 1 class II (|alpha - 1| <= tol), 2 class III (0 < alpha < 1), 3 standard
+ * nonhyperuniform (|alpha| <= tol), 4 antihyperuniform (-d < alpha < 0), 5 outside these ranges.
+ * Host only. */
+int hu_hyperuniformity_class(double alpha, int32_t d, double tol);
 
 /* Adjoint of the binned continuous spectrum with respect to the filter parameters of
  * Eqs. (12)-(13) (the gradient a parameter-fitting loop of Sec. IV needs).  Inputs are the outputs

@@ -42,6 +42,21 @@ GradLayout grad_layout(const Geom& g, int nb) {
   return L;
 }
 
+// workspace of hu_window_variance: the half spectra of a chunk of fields, then the per-tile
+// partial sums for every radius
+struct WvarLayout {
+  size_t spec, partials, total;
+  int tiles;
+};
+WvarLayout wvar_layout(const Geom& g, int chunk) {
+  WvarLayout L{};
+  L.spec = 0;
+  L.partials = up256((size_t)chunk * g.Nhp * 8);
+  L.tiles = col_tiles(g.n[0], 0, axis0(g).ncol);
+  L.total = L.partials + up256((size_t)chunk * L.tiles * HU_MAX_RADII * 8);
+  return L;
+}
+
 // workspace of hu_filter_spectrum: the per-block totals
 constexpr int FS_MAX_BLOCKS = 1024;
 int fs_blocks(const Geom& g) {
@@ -115,6 +130,9 @@ int hu_workspace_size(int op, hu_dims dims, int32_t batch, const hu_bins* bins, 
       return HU_OK;
     case HU_OP_FILTER_SPECTRUM:
       *bytes = up256((size_t)FS_MAX_BLOCKS * 8);
+      return HU_OK;
+    case HU_OP_WINDOW_VARIANCE:
+      *bytes = wvar_layout(g, chunk).total;
       return HU_OK;
     default:
       return HU_ERR_ARG;
@@ -346,6 +364,108 @@ int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins
   GradFinalArgs fa{partials, rows, grad};
   HU_HIP(timed("grad_final", st, [&] { return launch_grad_final(fa, st); }));
   return HU_OK;
+}
+
+int hu_window_variance(hu_dims dims, int32_t batch, const void* x, int32_t dtype, const double* radii,
+                       int32_t n_radii, double* out, void* work, size_t work_bytes, void* stream) {
+  Geom g;
+  HU_TRY(make_geom(dims, &g));
+  if (batch < 1 || !x || !out || !radii) return HU_ERR_ARG;
+  if (dtype != HU_F32 && dtype != HU_I8) return HU_ERR_ARG;
+  if (n_radii < 1 || n_radii > HU_MAX_RADII) return HU_ERR_ARG;
+  for (int j = 0; j < n_radii; ++j)
+    if (!std::isfinite(radii[j]) || radii[j] < 0.0 || radii[j] > 1e30) return HU_ERR_ARG;
+  if (!aligned(x, 16) || !aligned(out, 16)) return HU_ERR_ALIGN;
+  if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
+  const int chunk = batch < MAX_CHUNK ? batch : MAX_CHUNK;
+  const WvarLayout lay = wvar_layout(g, chunk);
+  if (work_bytes < lay.total) return HU_ERR_WORKSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int Lrow = g.nx / 2;
+  const float2 *tw_row, *tw2_row, *tw_0, *tw_1 = nullptr;
+  HU_TRY(get_tw(Lrow, &tw_row));
+  HU_TRY(get_tw2(Lrow, &tw2_row));
+  HU_TRY(get_tw(g.n[0], &tw_0));
+  if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
+  char* w = reinterpret_cast<char*>(work);
+  float2* spec = reinterpret_cast<float2*>(w + lay.spec);
+  double* partials = reinterpret_cast<double*>(w + lay.partials);
+  const size_t esz = dtype == HU_F32 ? 4 : 1;
+  for (int f0 = 0; f0 < batch; f0 += MAX_CHUNK) {
+    const int B = batch - f0 < MAX_CHUNK ? batch - f0 : MAX_CHUNK;
+    RowsArgs ra{};
+    ra.spec = spec;
+    ra.Nh = g.Nhp;
+    ra.tiled = g.tiled;
+    ra.N = g.N;
+    ra.nrows = g.nrows;
+    ra.src = reinterpret_cast<const char*>(x) + (size_t)f0 * g.N * esz;
+    ra.tw = tw_row;
+    ra.tw2 = tw2_row;
+    ra.fill_spans = 0;
+    const int src = dtype == HU_F32 ? SRC_F32 : SRC_I8;
+    HU_HIP(timed("rows_r2c_load", st, [&] { return launch_rows_r2c(Lrow, src, 0, ra, B, st); }));
+    if (g.nd == 3) {
+      ColsArgs cy{};
+      cy.spec = spec;
+      cy.Nh = g.Nhp;
+      cy.ncol = g.n[0] * g.nxh;
+      cy.inner = g.nxh;
+      cy.tw = tw_1;
+      cy.sc = col_sched(g.n[1], 0, cy.ncol, B, Y_PASS_GROUP);
+      HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, 0, cy, st); }));
+    }
+    WvarArgs wa{};
+    wa.spec = spec;
+    wa.Nh = g.Nhp;
+    wa.gm = axis0(g);
+    wa.sc = col_sched(g.n[0], 0, wa.gm.ncol, B);
+    wa.tw = tw_0;
+    wa.nr = n_radii;
+    for (int j = 0; j < n_radii; ++j) wa.radii[j] = (float)radii[j];
+    wa.partials = partials;
+    HU_HIP(timed("cols_wvar", st, [&] { return launch_cols_wvar(g.n[0], wa, st); }));
+    WvarFinalArgs fa{partials, wa.sc.ntiles, n_radii, 1.0 / ((double)g.N * (double)g.N), out + (size_t)f0 * n_radii};
+    HU_HIP(timed("wvar_final", st, [&] { return launch_wvar_final(fa, B, st); }));
+  }
+  return HU_OK;
+}
+
+int hu_small_k_exponent(const double* sum, const uint64_t* cnt, hu_bins bins, int32_t nfit, double* alpha) {
+  if (!sum || !cnt || !alpha) return HU_ERR_ARG;
+  const int R = bins.n_radial, A = bins.n_angular;
+  if (R < 2 || A < 1 || nfit < 1 || nfit > R - 1) return HU_ERR_ARG;
+  // least squares of y = ln P on x = ln k over the usable bins, in FP64
+  double sx = 0.0, sy = 0.0, sxx = 0.0, sxy = 0.0;
+  int n = 0;
+  for (int r = 1; r <= nfit; ++r) {
+    double s = 0.0, c = 0.0;
+    for (int q = 0; q < A; ++q) {
+      s += sum[(size_t)r * A + q];
+      c += (double)cnt[(size_t)r * A + q];
+    }
+    if (!(c > 0.0) || !(s > 0.0)) continue;
+    const double xv = std::log((r + 0.5) / R), yv = std::log(s / c);
+    sx += xv;
+    sy += yv;
+    sxx += xv * xv;
+    sxy += xv * yv;
+    ++n;
+  }
+  if (n < 2) return HU_ERR_ARG;
+  const double den = n * sxx - sx * sx;
+  if (!(den > 0.0)) return HU_ERR_ARG;
+  *alpha = (n * sxy - sx * sy) / den;
+  return HU_OK;
+}
+
+int hu_hyperuniformity_class(double alpha, int32_t d, double tol) {
+  if (std::fabs(alpha - 1.0) <= tol) return 1;
+  if (alpha > 1.0) return 0;
+  if (std::fabs(alpha) <= tol) return 3;
+  if (alpha > 0.0) return 2;
+  if (alpha > -(double)d) return 4;
+  return 5;
 }
 
 const char* hu_strerror(int code) {

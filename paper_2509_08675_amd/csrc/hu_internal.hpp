@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "hu_device.hpp"
+#include "hufield.h"
 
 namespace hu {
 
@@ -204,6 +205,26 @@ struct FilterSpecArgs {
   uint64_t* cnt;           // [nb] out or null
 };
 
+struct WvarArgs {
+  ColSched sc;
+  const float2* spec;      // transformed along every axis but axis 0, [B][Nh]
+  long long Nh;
+  Axis0Geom gm;
+  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
+  int nr;                  // radii (1..HU_MAX_RADII)
+  float radii[HU_MAX_RADII];
+  double* partials;        // [B][tiles][nr]
+};
+
+struct WvarFinalArgs {
+  const double* partials;  // [B][ntiles][nr]
+  int ntiles, nr;
+  double scale;            // 1 / N^2
+  double* out;             // [B][nr]
+};
+
+hipError_t launch_cols_wvar(int L, const WvarArgs& a, hipStream_t st);
+hipError_t launch_wvar_final(const WvarFinalArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st, int* grid);
 // workgroups of a kernel with this block size and LDS that are resident on the current device at
 // once (cached per device, kernel and LDS size)

@@ -23,6 +23,10 @@ HU_OK, HU_ERR_ARG, HU_ERR_SIZE, HU_ERR_ALIGN, HU_ERR_WORKSPACE, HU_ERR_DEGENERAT
     HU_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 HU_F32, HU_I8 = 0, 1
 HU_OP_GEN_FIELD, HU_OP_PIPELINE, HU_OP_POWER_SPECTRUM, HU_OP_LOSS, HU_OP_FILTER_SPECTRUM = 0, 1, 2, 3, 4
+HU_OP_WINDOW_VARIANCE = 5
+HU_MAX_RADII = 32
+HU_CLASSES = ("hyperuniform class I", "hyperuniform class II", "hyperuniform class III",
+              "nonhyperuniform (standard)", "antihyperuniform", "outside the classified range")
 
 
 class hu_dims(ctypes.Structure):
@@ -71,10 +75,13 @@ _lib.hu_plan_query.argtypes = [hu_dims, _i32, _P(hu_bins), _P(_i32)]
 _lib.hu_plan_set.argtypes = [hu_dims, _i32, _P(hu_bins), _P(_i32)]
 _lib.hu_filter_spectrum.argtypes = [hu_dims, _P(hu_filter), hu_bins, _vp, _vp, _vp, _sz, _vp]
 _lib.hu_spectrum_grad.argtypes = [hu_dims, _P(hu_filter), _u64, hu_bins, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.hu_window_variance.argtypes = [hu_dims, _i32, _vp, _i32, _P(ctypes.c_double), _i32, _vp, _vp, _sz, _vp]
+_lib.hu_small_k_exponent.argtypes = [_P(ctypes.c_double), _P(_u64), hu_bins, _i32, _P(ctypes.c_double)]
+_lib.hu_hyperuniformity_class.argtypes = [ctypes.c_double, _i32, ctypes.c_double]
 for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline",
            "hu_debug_philox", "hu_profile_enable", "hu_profile_read", "hu_workspace_size_batch",
            "hu_pipeline_batch", "hu_autotune", "hu_plan_query", "hu_plan_set", "hu_filter_spectrum",
-           "hu_spectrum_grad"):
+           "hu_spectrum_grad", "hu_window_variance", "hu_small_k_exponent", "hu_hyperuniformity_class"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -233,6 +240,45 @@ def power_spectrum(x, bins, work=None):
     _check(_lib.hu_power_spectrum(make_dims(dims), B, _ptr(x), dt, make_bins(bins), _ptr(s), _ptr(c), _ptr(work),
                                   work.numel(), _stream(x.device)), "hu_power_spectrum")
     return s, c
+
+
+def window_variance(x, radii, work=None):
+    """Local variance over a spherical window of each radius (lattice units) of real fields
+    x [B, *dims] (float32 or int8 on device): [B, len(radii)] FP64 (Eq. (1) in Fourier form)."""
+    dims = tuple(x.shape[1:])
+    B = x.shape[0]
+    if x.dtype == torch.float32:
+        dt = HU_F32
+    elif x.dtype == torch.int8:
+        dt = HU_I8
+    else:
+        raise TypeError("window_variance takes float32 or int8 fields")
+    r = (ctypes.c_double * len(radii))(*[float(v) for v in radii])
+    out = torch.empty((B, len(radii)), dtype=torch.float64, device=x.device)
+    if work is None:
+        work = alloc_workspace(HU_OP_WINDOW_VARIANCE, dims, B, None, x.device)
+    _check(_lib.hu_window_variance(make_dims(dims), B, _ptr(x), dt, r, len(radii), _ptr(out), _ptr(work),
+                                   work.numel(), _stream(x.device)), "hu_window_variance")
+    return out
+
+
+def small_k_exponent(bin_sum, bin_cnt, bins, nfit):
+    """Small-k exponent of one binned spectrum (sum [nb] FP64 and cnt [nb], any device)."""
+    def host(t):
+        return t.detach().cpu().numpy() if hasattr(t, "detach") else np.asarray(t)
+    s = np.ascontiguousarray(host(bin_sum), dtype=np.float64)
+    c = np.ascontiguousarray(host(bin_cnt).astype(np.uint64))   # counts are < 2^63
+    if s.size < _nb(bins) or c.size < _nb(bins):
+        raise ValueError("binned spectrum shorter than the bin layout")
+    a = ctypes.c_double()
+    _check(_lib.hu_small_k_exponent(s.ctypes.data_as(_P(ctypes.c_double)), c.ctypes.data_as(_P(_u64)),
+                                    make_bins(bins), int(nfit), ctypes.byref(a)), "hu_small_k_exponent")
+    return a.value
+
+
+def hyperuniformity_class(alpha, d, tol=1e-6):
+    """Name of the class of Eqs. (6)-(7) for a small-k exponent alpha in dimension d."""
+    return HU_CLASSES[_lib.hu_hyperuniformity_class(float(alpha), int(d), float(tol))]
 
 
 class PipelineBuffers:

@@ -101,3 +101,46 @@ def test_argument_errors_before_any_launch(hf):
     assert rc == hf.HU_ERR_ARG
     rc = lib.hu_gen_field(d, 1, ctypes.byref(good), None, fake, None, None, None, None, fake, 1 << 30, None)
     assert rc == hf.HU_ERR_ARG
+
+
+def test_window_variance_argument_errors_and_workspace(hf):
+    lib = hf.lib_handle()
+    d = hf.make_dims((64, 64))
+    fake = ctypes.c_void_p(1 << 20)
+    radii = (ctypes.c_double * 3)(0.0, 2.0, 5.0)
+    assert lib.hu_window_variance(d, 1, fake, hf.HU_F32, radii, 0, fake, fake, 1 << 30, None) == hf.HU_ERR_ARG
+    assert lib.hu_window_variance(d, 1, fake, hf.HU_F32, radii, hf.HU_MAX_RADII + 1, fake, fake, 1 << 30,
+                                  None) == hf.HU_ERR_ARG
+    bad = (ctypes.c_double * 2)(1.0, -0.5)
+    assert lib.hu_window_variance(d, 1, fake, hf.HU_F32, bad, 2, fake, fake, 1 << 30, None) == hf.HU_ERR_ARG
+    nan = (ctypes.c_double * 1)(float("nan"))
+    assert lib.hu_window_variance(d, 1, fake, hf.HU_F32, nan, 1, fake, fake, 1 << 30, None) == hf.HU_ERR_ARG
+    assert lib.hu_window_variance(d, 1, fake, 9, radii, 3, fake, fake, 1 << 30, None) == hf.HU_ERR_ARG
+    assert lib.hu_window_variance(d, 1, ctypes.c_void_p((1 << 20) + 4), hf.HU_F32, radii, 3, fake, fake, 1 << 30,
+                                  None) == hf.HU_ERR_ALIGN
+    assert lib.hu_window_variance(d, 1, fake, hf.HU_F32, radii, 3, fake, fake, 64, None) == hf.HU_ERR_WORKSPACE
+    # workspace: the half spectrum of each field of a chunk, then tiles x HU_MAX_RADII partials per field
+    n = hf.workspace_size(hf.HU_OP_WINDOW_VARIANCE, (256, 256, 256), 4)
+    assert n >= 4 * 256 * 256 * 129 * 8 + 4 * (256 * 129 // 32) * hf.HU_MAX_RADII * 8
+
+
+def test_small_k_exponent_matches_oracle(hf):
+    import numpy as np
+    from oracle import diagnostics as D
+    rng = np.random.default_rng(3)
+    for bins, nfit in (((64, 1), 10), ((32, 6), 7)):
+        nb = bins[0] * bins[1] + 1
+        cnt = rng.integers(1, 50, nb).astype(np.uint64)
+        cnt[3] = 0                                   # an empty bin is skipped by both
+        s = rng.uniform(0.5, 2.0, nb) * cnt
+        got = hf.small_k_exponent(s, cnt, bins, nfit)
+        ref = D.small_k_exponent(s, cnt.astype(float), bins[0], nfit, n_angular=bins[1])
+        assert got == pytest.approx(ref, rel=1e-12, abs=1e-12)
+    with pytest.raises(hf.HuError):
+        hf.small_k_exponent(np.ones(65), np.zeros(65, np.uint64), (64, 1), 10)
+
+
+def test_class_table_matches_oracle(hf):
+    from oracle import diagnostics as D
+    for alpha, d in ((3.0, 2), (1.0, 3), (1.0 + 1e-9, 2), (0.4, 3), (0.0, 2), (-1.5, 2), (-2.5, 2), (-2.5, 3)):
+        assert hf.hyperuniformity_class(alpha, d) == D.CLASSES[D.hyperuniformity_class(alpha, d)]

@@ -13,8 +13,9 @@ Prints ONE JSON line.  Besides the headline value it carries
   plain_form    the same work as one call per field, and the batched speedup over it;
   also          the 3D 256^3 x 4 workload measured the same way; the uneven batch of 512 fields
                 (448 2D from 64^2..1024^2, 64 3D from 64^3..128^3) through one replayed graph after
-                autotuning, with its plain form; and the 512^3 forward plus the adjoint of the
-                spectrum-matching loss.
+                autotuning, with its plain form; the 512^3 forward plus the adjoint of the
+                spectrum-matching loss; and the local variance over spherical windows of 8 radii
+                (hyperuniformity diagnostic) of the 2D and 3D workloads' fields.
 """
 
 import argparse
@@ -273,6 +274,39 @@ def time_adjoint(hf, torch, steps, warmup=1):
                 grad=dict(zip(hf.THETA_NAMES, [float("%.6g" % g) for g in grad])))
 
 
+def time_window_variance(hf, torch, cfg, steps, radii=(1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0, 128.0)):
+    """Local variance over spherical windows of 8 radii for the workload's fields (generated by the
+    pipeline beforehand, resident in HBM): one hu_window_variance call per step."""
+    dims, seeds, bins = cfg["dims"], cfg["seeds"], cfg["bins"]
+    b = hf.PipelineBuffers(dims, len(seeds), bins)
+    hf.pipeline(b, cfg["filt"], seeds)
+    work = hf.alloc_workspace(hf.HU_OP_WINDOW_VARIANCE, dims, len(seeds))
+    fn = lambda: hf.window_variance(b.field, radii, work=work)
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    hf.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    prof = hf.profile_read()
+    hf.profile_enable(False)
+    N = math.prod(dims)
+    Nh = N // dims[-1] * (dims[-1] // 2 + 1)
+    B = len(seeds)
+    fam = {"rows_r2c_load": 4 * N * B + 8 * Nh * B, "cols_y_fwd": 16 * Nh * B, "cols_wvar": 8 * Nh * B}
+    kern = {k: dict(mean_ms=round(v[1] / v[0], 5),
+                    gbs=round(fam.get(k, 0) / (v[1] / v[0] * 1e-3) / 1e9, 1)) for k, v in prof.items()}
+    modes = Nh * B
+    return dict(radii=list(radii), ms_per_call=round(ms, 4), value=round(N * B / (ms * 1e-3), 1), unit="voxels/s",
+                kernels=kern, form_factor_evals_per_s=round(modes * len(radii) / (prof["cols_wvar"][1] /
+                                                                                   prof["cols_wvar"][0] * 1e-3), 1))
+
+
 def cpu_baseline(cfg, budget_s=12.0):
     """The FP64 oracle, as it stands, on the workload's fields in order until `budget_s` seconds
     have passed or all are done (single-threaded numpy; pocketfft runs on one core)."""
@@ -520,6 +554,8 @@ def main():
         line.setdefault("also", {})
         line["also"]["c4_uneven_512_fields"] = time_uneven_batch(hf, torch, max(args.steps // 5, 5), 2)
         line["also"]["3d_512cube_forward_and_adjoint"] = time_adjoint(hf, torch, max(args.steps // 5, 5))
+        line["also"]["window_variance_2048sq_x16_8radii"] = time_window_variance(hf, torch, C2, max(args.steps // 5, 5))
+        line["also"]["window_variance_256cube_x4_8radii"] = time_window_variance(hf, torch, C3, max(args.steps // 5, 5))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

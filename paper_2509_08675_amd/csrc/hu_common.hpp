@@ -260,6 +260,9 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
 __device__ __forceinline__ float2 buf_load2(rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
+__device__ __forceinline__ u32x4 buf_load4(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+}
 __device__ __forceinline__ void buf_store2(rsrc_t r, float2 v, unsigned voff, unsigned soff) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }

@@ -261,6 +261,40 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
         }
       }
     }
+  } else if constexpr ((SRC == SRC_F32 && L % 2 == 0) || (SRC == SRC_I8 && L % 8 == 0)) {
+    // the tile's rows are contiguous and every row is a whole number of 16-byte vectors: all of a
+    // thread's vector loads are issued first (rows past the field read 0), then written to LDS as
+    // complex pairs (a vector never crosses a row, and a pair never straddles a padded group)
+    constexpr int ESZ = SRC == SRC_F32 ? 4 : 1;
+    constexpr int SPV = 16 / ESZ;                 // samples per vector
+    constexpr int NV = C * 2 * L / SPV;           // vectors per full tile
+    constexpr int IT = (NV + T - 1) / T;
+    const char* src = reinterpret_cast<const char*>(a.src) + ((long long)b * a.N + v0) * ESZ;
+    const rsrc_t rs = make_rsrc(src, (unsigned)nv * ESZ);
+    u32x4 w[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) w[it] = buf_load4(rs, (unsigned)(tid + it * T) * 16u, 0);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int iv = tid + it * T;
+      if (NV % T != 0 && iv >= NV) break;
+      const int s0 = iv * SPV;
+      const int rc = s0 / (2 * L), j0 = (s0 - rc * 2 * L) >> 1;
+      float2* d = lds + rc * RS;
+      if constexpr (SRC == SRC_F32) {
+        using f32x4 = __attribute__((ext_vector_type(4))) float;
+        const f32x4 f = __builtin_bit_cast(f32x4, w[it]);   // the whole vector (not per element)
+        d[lidx(j0)] = make_float2(f.x, f.y);
+        d[lidx(j0 + 1)] = make_float2(f.z, f.w);
+      } else {
+        const unsigned ws[4] = {w[it].x, w[it].y, w[it].z, w[it].w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const unsigned u = ws[q >> 1] >> (16 * (q & 1));
+          d[lidx(j0 + q)] = make_float2((float)(int8_t)(u & 0xFFu), (float)(int8_t)((u >> 8) & 0xFFu));
+        }
+      }
+    }
   } else {
     const long long base = (long long)b * a.N + v0;
     for (int i = tid; i < C * 2 * L; i += T) {

@@ -19,7 +19,9 @@ Spectral Filtering" (arXiv 2509.08675):
   Sec. III);
 * the hyperuniformity diagnostics of Sec. II.A: the local variance over a spherical window
   (Eq. (1)) in its Fourier form, the small-k exponent of a binned spectrum and the class of
-  Eqs. (6)-(7).
+  Eqs. (6)-(7);
+* a general level cut for a target volume fraction and the two-point probability function of
+  the resulting two-phase map (Wiener-Khinchin, Eqs. (10)-(11)).
 
 Where the paper is silent (noise generator, FFT sign, band centre, rotation,
 Nyquist handling, binning) the readings are stated in each function.  Every
@@ -36,6 +38,7 @@ from .spectrum import bin_table, bin_power, power_spectrum, continuous_spectrum_
 from .loss import (target_bins, spectrum_loss, spectrum_loss_grad, dlnH_half,
                    PARAM_NAMES)
 from .diagnostics import form_factor, window_variance, small_k_exponent, hyperuniformity_class, CLASSES
+from .twopoint import level_threshold, level_cut, s2_map, s2_brute
 
 __all__ = [
     "philox4x32_10", "uniforms_from_words", "box_muller", "white_noise",
@@ -45,4 +48,5 @@ __all__ = [
     "bin_table", "bin_power", "power_spectrum", "continuous_spectrum_fused",
     "target_bins", "spectrum_loss", "spectrum_loss_grad", "dlnH_half", "PARAM_NAMES",
     "form_factor", "window_variance", "small_k_exponent", "hyperuniformity_class", "CLASSES",
+    "level_threshold", "level_cut", "s2_map", "s2_brute",
 ]

@@ -19,10 +19,12 @@ import scipy.special
 
 
 def level_threshold(phi, sigma_f=1.0):
-    """t_phi = sigma_f Phi^-1(1 - phi), 0 < phi < 1."""
+    """t_phi = sigma_f Phi^-1(1 - phi), 0 < phi < 1, evaluated as -sigma_f Phi^-1(phi) (the normal
+    quantile is odd about 1/2): forming 1 - phi first would drop the relative precision of a small
+    tail probability."""
     if not (0.0 < phi < 1.0):
         raise ValueError("phi must lie in (0, 1)")
-    return sigma_f * float(scipy.special.ndtri(1.0 - phi))
+    return -sigma_f * float(scipy.special.ndtri(phi))
 
 
 def level_cut(f, t):

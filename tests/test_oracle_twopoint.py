@@ -45,8 +45,11 @@ def test_s2_closed_forms():
 def test_level_threshold_inverts_the_normal_cdf(phi):
     t = TP.level_threshold(phi, sigma_f=2.0)
     # P(f >= t) for f ~ N(0, 4) is erfc(t / (2 sqrt 2)) / 2
-    assert 0.5 * math.erfc(t / (2.0 * math.sqrt(2.0))) == pytest.approx(phi, rel=1e-12)
-    assert TP.level_threshold(1.0 - phi, sigma_f=2.0) == pytest.approx(-t, abs=1e-12 * max(1.0, abs(t)))
+    assert 0.5 * math.erfc(t / (2.0 * math.sqrt(2.0))) == pytest.approx(phi, rel=1e-12, abs=0.0)
+    # oddness about 1/2: q = 1 - phi rounds, so compare with the exact tail of the value passed
+    q = 1.0 - phi
+    assert TP.level_threshold(q, sigma_f=2.0) == pytest.approx(-TP.level_threshold(1.0 - q, sigma_f=2.0),
+                                                              rel=1e-13, abs=0.0 if phi != 0.5 else 1e-300)
     if phi == 0.5:
         assert t == 0.0
 

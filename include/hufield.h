@@ -73,7 +73,7 @@ enum { HU_F32 = 0, HU_I8 = 1 };
 
 /* Operations for hu_workspace_size. */
 enum { HU_OP_GEN_FIELD = 0, HU_OP_PIPELINE = 1, HU_OP_POWER_SPECTRUM = 2, HU_OP_LOSS = 3, HU_OP_FILTER_SPECTRUM = 4,
-       HU_OP_WINDOW_VARIANCE = 5 };
+       HU_OP_WINDOW_VARIANCE = 5, HU_OP_TWO_POINT = 6 };
 
 /* Most window radii of one hu_window_variance call. */
 #define HU_MAX_RADII 32
@@ -171,6 +171,29 @@ int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double
  * HU_ERR_ARG for a bad radius count or value, HU_ERR_ALIGN for x or out not 16-byte aligned. */
 int hu_window_variance(hu_dims dims, int32_t batch, const void* x, int32_t dtype, const double* radii,
                        int32_t n_radii, double* out, void* work, size_t work_bytes, void* stream);
+
+/* General level cut (Sec. II.B, last paragraphs: the two phases may come from any functional map of
+ * the field): out = +1 where field >= t_phi, else -1, with t_phi = sigma_f Phi^-1(1 - phi), the level
+ * at which a Gaussian field of standard deviation sigma_f has expected volume fraction phi in the +1
+ * phase (phi = 1/2 is the sign map).  counts [B][2] = (n_pos, n_near), n_near = #(|field - t_phi| <
+ * near_tol), or NULL.  field, out, counts: device.  HU_ERR_ARG unless 0 < phi < 1, sigma_f > 0 and
+ * near_tol >= 0 (all finite).  Needs no workspace. */
+int hu_level_cut(hu_dims dims, int32_t batch, const float* field, double phi, double sigma_f, int8_t* out,
+                 uint64_t* counts, float near_tol, void* stream);
+
+/* t_phi = sigma_f Phi^-1(1 - phi) in FP64 on the host (Newton's method on the normal CDF from erfc,
+ * bracketed by bisection; relative error ~1e-15).  HU_ERR_ARG outside 0 < phi < 1 or sigma_f <= 0. */
+int hu_level_threshold(double phi, double sigma_f, double* t);
+
+/* Two-point probability function of the +1 phase of `batch` +-1 maps (int8, [B][N] device):
+ * s2[b][r] = (1/N) sum_x I(x) I(x + r), I = (1 + pm1) / 2, for every periodic lattice displacement r
+ * (array layout of the field, index r mod n per axis), by the Wiener-Khinchin relation
+ * (Eqs. (10)-(11)): S_2 = (1 + 2m + IDFT(|G|^2) / N^2) / 4 with G the DFT of pm1 and m its mean.
+ * s2: device FP32 [B][N] (S_2(0) is the volume fraction, the mean over r its square).  Values other
+ * than +-1 in pm1 are taken as given (the formula is the autocorrelation of (1 + x) / 2).
+ * Workspace: hu_workspace_size(HU_OP_TWO_POINT, dims, batch, NULL, ...). */
+int hu_two_point(hu_dims dims, int32_t batch, const int8_t* pm1, float* s2, void* work, size_t work_bytes,
+                 void* stream);
 
 /* Small-k exponent of a binned spectrum (the alpha of spectral density ~ |k|^alpha, Sec. II.A):
  * the least-squares slope of ln(sum_r / cnt_r) against ln((r + 1/2) / R) over radial bins

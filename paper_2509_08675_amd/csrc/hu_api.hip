@@ -134,6 +134,9 @@ int hu_workspace_size(int op, hu_dims dims, int32_t batch, const hu_bins* bins, 
     case HU_OP_WINDOW_VARIANCE:
       *bytes = wvar_layout(g, chunk).total;
       return HU_OK;
+    case HU_OP_TWO_POINT:
+      *bytes = layout(g, chunk, true, TunePlan{{0, 0, 0, 0, 0}}).total;
+      return HU_OK;
     default:
       return HU_ERR_ARG;
   }
@@ -427,6 +430,120 @@ int hu_window_variance(hu_dims dims, int32_t batch, const void* x, int32_t dtype
     HU_HIP(timed("cols_wvar", st, [&] { return launch_cols_wvar(g.n[0], wa, st); }));
     WvarFinalArgs fa{partials, wa.sc.ntiles, n_radii, 1.0 / ((double)g.N * (double)g.N), out + (size_t)f0 * n_radii};
     HU_HIP(timed("wvar_final", st, [&] { return launch_wvar_final(fa, B, st); }));
+  }
+  return HU_OK;
+}
+
+int hu_level_threshold(double phi, double sigma_f, double* t) {
+  if (!t || !std::isfinite(phi) || !std::isfinite(sigma_f) || !(phi > 0.0) || !(phi < 1.0) || !(sigma_f > 0.0))
+    return HU_ERR_ARG;
+  // the upper tail p = min(phi, 1 - phi) (1 - phi is exact for phi >= 1/2), x >= 0 with
+  // Q(x) = P(Z >= x) = erfc(x / sqrt 2) / 2 = p, and t = +-x.  Newton's method on ln Q(x) - ln p
+  // (d ln Q / dx = -exp(-x^2/2) / (sqrt(2 pi) Q)) keeps relative precision deep in the tail;
+  // a bisection bracket catches any step that leaves it.
+  const bool upper = phi <= 0.5;
+  const double p = upper ? phi : 1.0 - phi;
+  double x = 0.0;
+  if (p < 0.5) {
+    const double rt2 = std::sqrt(2.0), rt2pi = std::sqrt(2.0 * 3.14159265358979323846);
+    const double lp = std::log(p);
+    double lo = 0.0, hi = 40.0;
+    x = std::sqrt(-2.0 * lp);                              // above the root: Q(x) < exp(-x^2/2) / 2
+    for (int it = 0; it < 100; ++it) {
+      const double q = 0.5 * std::erfc(x / rt2);
+      const double gx = std::log(q) - lp;
+      if (gx > 0.0) lo = x; else hi = x;                  // ln Q decreases with x
+      double xn = x + gx * q * rt2pi * std::exp(0.5 * x * x);
+      if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+      const bool done = std::fabs(xn - x) <= 1e-15 * x;
+      x = xn;
+      if (done) break;
+    }
+  }
+  *t = sigma_f * (upper ? x : -x);
+  return HU_OK;
+}
+
+int hu_level_cut(hu_dims dims, int32_t batch, const float* field, double phi, double sigma_f, int8_t* out,
+                 uint64_t* counts, float near_tol, void* stream) {
+  Geom g;
+  HU_TRY(make_geom(dims, &g));
+  if (batch < 1 || !field || !out) return HU_ERR_ARG;
+  if (!std::isfinite(near_tol) || near_tol < 0.0f) return HU_ERR_ARG;
+  double t = 0.0;
+  HU_TRY(hu_level_threshold(phi, sigma_f, &t));
+  if (!aligned(field, 16) || !aligned(out, 16) || (counts && !aligned(counts, 16))) return HU_ERR_ALIGN;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (counts) HU_HIP(timed("zero", st, [&] { return launch_zero_u64(counts, 2LL * batch, st); }));
+  ThreshArgs a{field, out, counts, g.N, near_tol, (float)t};
+  HU_HIP(timed("threshold", st, [&] { return launch_threshold(a, batch, st); }));
+  return HU_OK;
+}
+
+int hu_two_point(hu_dims dims, int32_t batch, const int8_t* pm1, float* s2, void* work, size_t work_bytes,
+                 void* stream) {
+  Geom g;
+  HU_TRY(make_geom(dims, &g));
+  if (batch < 1 || !pm1 || !s2) return HU_ERR_ARG;
+  if (!aligned(pm1, 16) || !aligned(s2, 16)) return HU_ERR_ALIGN;
+  if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
+  const int chunk = batch < MAX_CHUNK ? batch : MAX_CHUNK;
+  const Layout lay = layout(g, chunk, true, TunePlan{{0, 0, 0, 0, 0}});
+  if (work_bytes < lay.total) return HU_ERR_WORKSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int Lrow = g.nx / 2;
+  const float2 *tw_row, *tw2_row, *tw_0, *tw_1 = nullptr;
+  HU_TRY(get_tw(Lrow, &tw_row));
+  HU_TRY(get_tw2(Lrow, &tw2_row));
+  HU_TRY(get_tw(g.n[0], &tw_0));
+  if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
+  char* w = reinterpret_cast<char*>(work);
+  float2* spec = reinterpret_cast<float2*>(w + lay.spec);
+  double* fstats = reinterpret_cast<double*>(w + lay.fstats);
+  for (int f0 = 0; f0 < batch; f0 += MAX_CHUNK) {
+    const int B = batch - f0 < MAX_CHUNK ? batch - f0 : MAX_CHUNK;
+    RowsArgs ra{};
+    ra.spec = spec;
+    ra.Nh = g.Nhp;
+    ra.tiled = g.tiled;
+    ra.N = g.N;
+    ra.nrows = g.nrows;
+    ra.src = pm1 + (size_t)f0 * g.N;
+    ra.tw = tw_row;
+    ra.tw2 = tw2_row;
+    ra.fill_spans = 0;
+    HU_HIP(timed("rows_r2c_load", st, [&] { return launch_rows_r2c(Lrow, SRC_I8, 0, ra, B, st); }));
+    ColsArgs cy{};
+    if (g.nd == 3) {
+      cy.spec = spec;
+      cy.Nh = g.Nhp;
+      cy.ncol = g.n[0] * g.nxh;
+      cy.inner = g.nxh;
+      cy.tw = tw_1;
+      cy.sc = col_sched(g.n[1], 0, cy.ncol, B, Y_PASS_GROUP);
+      HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, 0, cy, st); }));
+    }
+    SquareArgs sa{};
+    sa.spec = spec;
+    sa.Nh = g.Nhp;
+    sa.N = g.N;
+    sa.gm = axis0(g);
+    sa.sc = col_sched(g.n[0], 0, sa.gm.ncol, B);
+    sa.tw = tw_0;
+    sa.fstats = fstats;
+    HU_HIP(timed("cols_square", st, [&] { return launch_cols_square(g.n[0], sa, st); }));
+    if (g.nd == 3) HU_HIP(timed("cols_y_inv", st, [&] { return launch_cols(g.n[1], true, 0, cy, st); }));
+    RowsZArgs za{};
+    za.spec = spec;
+    za.Nh = g.Nhp;
+    za.tiled = g.tiled;
+    za.N = g.N;
+    za.nrows = g.nrows;
+    za.tw = tw_row;
+    za.tw2 = tw2_row;
+    za.fstats = fstats;
+    za.field = s2 + (size_t)f0 * g.N;
+    HU_HIP(timed("rows_c2r", st, [&] { return launch_rows_c2r(Lrow, false, 0, za, B, st); }));
   }
   return HU_OK;
 }

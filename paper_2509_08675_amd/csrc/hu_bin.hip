@@ -169,10 +169,10 @@ __global__ void __launch_bounds__(256) k_threshold(ThreshArgs a) {
   unsigned np = 0, nn = 0;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.N; i += (long long)gridDim.x * 256) {
     const float x = f[i];
-    const bool pos = x >= 0.0f;
+    const bool pos = x >= a.level;
     t[i] = pos ? (int8_t)1 : (int8_t)-1;
     np += pos;
-    nn += fabsf(x) < a.near_tol;
+    nn += fabsf(x - a.level) < a.near_tol;
   }
   np = wave_usum(np);
   nn = wave_usum(nn);

@@ -152,6 +152,16 @@ struct ThreshArgs {
   uint64_t* counts;
   long long N;
   float near_tol;
+  float level;             // +1 where field >= level (0: the sign map)
+};
+
+struct SquareArgs {
+  ColSched sc;
+  float2* spec;            // transformed along every axis but axis 0, [B][Nh]; rewritten in place
+  long long Nh, N;
+  Axis0Geom gm;
+  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
+  double* fstats;          // [B][8]: entries 4 and 5 (scale, offset of the last row pass) written
 };
 
 // Adjoint of the filter with respect to theta = (a, b, c, p, rot, k0, w): the axis-0 pass over the
@@ -223,6 +233,7 @@ struct WvarFinalArgs {
   double* out;             // [B][nr]
 };
 
+hipError_t launch_cols_square(int L, const SquareArgs& a, hipStream_t st);
 hipError_t launch_cols_wvar(int L, const WvarArgs& a, hipStream_t st);
 hipError_t launch_wvar_final(const WvarFinalArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st, int* grid);

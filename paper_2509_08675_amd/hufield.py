@@ -24,6 +24,7 @@ HU_OK, HU_ERR_ARG, HU_ERR_SIZE, HU_ERR_ALIGN, HU_ERR_WORKSPACE, HU_ERR_DEGENERAT
 HU_F32, HU_I8 = 0, 1
 HU_OP_GEN_FIELD, HU_OP_PIPELINE, HU_OP_POWER_SPECTRUM, HU_OP_LOSS, HU_OP_FILTER_SPECTRUM = 0, 1, 2, 3, 4
 HU_OP_WINDOW_VARIANCE = 5
+HU_OP_TWO_POINT = 6
 HU_MAX_RADII = 32
 HU_CLASSES = ("hyperuniform class I", "hyperuniform class II", "hyperuniform class III",
               "nonhyperuniform (standard)", "antihyperuniform", "outside the classified range")
@@ -78,10 +79,14 @@ _lib.hu_spectrum_grad.argtypes = [hu_dims, _P(hu_filter), _u64, hu_bins, _vp, _v
 _lib.hu_window_variance.argtypes = [hu_dims, _i32, _vp, _i32, _P(ctypes.c_double), _i32, _vp, _vp, _sz, _vp]
 _lib.hu_small_k_exponent.argtypes = [_P(ctypes.c_double), _P(_u64), hu_bins, _i32, _P(ctypes.c_double)]
 _lib.hu_hyperuniformity_class.argtypes = [ctypes.c_double, _i32, ctypes.c_double]
+_lib.hu_level_threshold.argtypes = [ctypes.c_double, ctypes.c_double, _P(ctypes.c_double)]
+_lib.hu_level_cut.argtypes = [hu_dims, _i32, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _f32, _vp]
+_lib.hu_two_point.argtypes = [hu_dims, _i32, _vp, _vp, _vp, _sz, _vp]
 for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline",
            "hu_debug_philox", "hu_profile_enable", "hu_profile_read", "hu_workspace_size_batch",
            "hu_pipeline_batch", "hu_autotune", "hu_plan_query", "hu_plan_set", "hu_filter_spectrum",
-           "hu_spectrum_grad", "hu_window_variance", "hu_small_k_exponent", "hu_hyperuniformity_class"):
+           "hu_spectrum_grad", "hu_window_variance", "hu_small_k_exponent", "hu_hyperuniformity_class",
+           "hu_level_threshold", "hu_level_cut", "hu_two_point"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -279,6 +284,43 @@ def small_k_exponent(bin_sum, bin_cnt, bins, nfit):
 def hyperuniformity_class(alpha, d, tol=1e-6):
     """Name of the class of Eqs. (6)-(7) for a small-k exponent alpha in dimension d."""
     return HU_CLASSES[_lib.hu_hyperuniformity_class(float(alpha), int(d), float(tol))]
+
+
+def level_threshold(phi, sigma_f=1.0):
+    """t_phi = sigma_f Phi^-1(1 - phi) (host, FP64)."""
+    t = ctypes.c_double()
+    _check(_lib.hu_level_threshold(float(phi), float(sigma_f), ctypes.byref(t)), "hu_level_threshold")
+    return t.value
+
+
+def level_cut(field, phi, sigma_f=1.0, near_tol=0.0, out=None, counts=True):
+    """+1 where field >= t_phi else -1 for fields [B, *dims] float32 on device; returns (map int8,
+    counts [B, 2] int64 holding uint64 (n_pos, n_near) or None)."""
+    dims = tuple(field.shape[1:])
+    B = field.shape[0]
+    if out is None:
+        out = torch.empty(field.shape, dtype=torch.int8, device=field.device)
+    c = torch.empty((B, 2), dtype=torch.int64, device=field.device) if counts else None
+    _check(_lib.hu_level_cut(make_dims(dims), B, _ptr(field), float(phi), float(sigma_f), _ptr(out),
+                             _ptr(c) if c is not None else None, float(near_tol), _stream(field.device)),
+           "hu_level_cut")
+    return out, c
+
+
+def two_point(pm1, work=None, out=None):
+    """S_2(r) of the +1 phase of +-1 maps pm1 [B, *dims] int8 on device: float32 [B, *dims], index
+    r mod n per axis."""
+    dims = tuple(pm1.shape[1:])
+    B = pm1.shape[0]
+    if pm1.dtype != torch.int8:
+        raise TypeError("two_point takes int8 maps")
+    if out is None:
+        out = torch.empty(pm1.shape, dtype=torch.float32, device=pm1.device)
+    if work is None:
+        work = alloc_workspace(HU_OP_TWO_POINT, dims, B, None, pm1.device)
+    _check(_lib.hu_two_point(make_dims(dims), B, _ptr(pm1), _ptr(out), _ptr(work), work.numel(),
+                             _stream(pm1.device)), "hu_two_point")
+    return out
 
 
 class PipelineBuffers:

@@ -144,3 +144,32 @@ def test_class_table_matches_oracle(hf):
     from oracle import diagnostics as D
     for alpha, d in ((3.0, 2), (1.0, 3), (1.0 + 1e-9, 2), (0.4, 3), (0.0, 2), (-1.5, 2), (-2.5, 2), (-2.5, 3)):
         assert hf.hyperuniformity_class(alpha, d) == D.CLASSES[D.hyperuniformity_class(alpha, d)]
+
+
+def test_level_threshold_matches_oracle(hf):
+    from oracle import twopoint as TP
+    for phi in (0.5, 0.3, 0.05, 0.9, 1e-6, 1.0 - 1e-9, 0.999):
+        for sf in (1.0, 2.5):
+            t = hf.level_threshold(phi, sf)
+            ref = TP.level_threshold(phi, sf)
+            assert t == pytest.approx(ref, rel=1e-12, abs=1e-13)
+    for bad in ((0.0, 1.0), (1.0, 1.0), (0.5, 0.0), (float("nan"), 1.0), (0.5, -1.0)):
+        with pytest.raises(hf.HuError):
+            hf.level_threshold(*bad)
+
+
+def test_level_cut_and_two_point_argument_errors(hf):
+    lib = hf.lib_handle()
+    d = hf.make_dims((64, 64))
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.hu_level_cut(d, 1, fake, 0.0, 1.0, fake, None, 0.0, None) == hf.HU_ERR_ARG
+    assert lib.hu_level_cut(d, 1, fake, 0.5, 0.0, fake, None, 0.0, None) == hf.HU_ERR_ARG
+    assert lib.hu_level_cut(d, 1, fake, 0.5, 1.0, fake, None, -1.0, None) == hf.HU_ERR_ARG
+    assert lib.hu_level_cut(d, 0, fake, 0.5, 1.0, fake, None, 0.0, None) == hf.HU_ERR_ARG
+    assert lib.hu_level_cut(d, 1, ctypes.c_void_p((1 << 20) + 2), 0.5, 1.0, fake, None, 0.0,
+                            None) == hf.HU_ERR_ALIGN
+    assert lib.hu_two_point(d, 1, fake, fake, fake, 64, None) == hf.HU_ERR_WORKSPACE
+    assert lib.hu_two_point(d, 1, None, fake, fake, 1 << 30, None) == hf.HU_ERR_ARG
+    assert lib.hu_two_point(d, 1, ctypes.c_void_p((1 << 20) + 8), fake, fake, 1 << 30, None) == hf.HU_ERR_ALIGN
+    n = hf.workspace_size(hf.HU_OP_TWO_POINT, (256, 256, 256), 4)
+    assert n >= 4 * 256 * 256 * 129 * 8

@@ -14,8 +14,9 @@ Prints ONE JSON line.  Besides the headline value it carries
   also          the 3D 256^3 x 4 workload measured the same way; the uneven batch of 512 fields
                 (448 2D from 64^2..1024^2, 64 3D from 64^3..128^3) through one replayed graph after
                 autotuning, with its plain form; the 512^3 forward plus the adjoint of the
-                spectrum-matching loss; and the local variance over spherical windows of 8 radii
-                (hyperuniformity diagnostic) of the 2D and 3D workloads' fields.
+                spectrum-matching loss; the local variance over spherical windows of 8 radii
+                (hyperuniformity diagnostic) of the 2D and 3D workloads' fields; and the level cut
+                at volume fraction 0.35 with the two-point function S_2 of the cut maps.
 """
 
 import argparse
@@ -307,6 +308,45 @@ def time_window_variance(hf, torch, cfg, steps, radii=(1.0, 2.0, 4.0, 8.0, 16.0,
                                                                                    prof["cols_wvar"][0] * 1e-3), 1))
 
 
+def time_two_point(hf, torch, cfg, steps, phi=0.35):
+    """Level cut of the workload's fields at volume fraction phi and the two-point function S_2 of
+    the resulting maps (fields generated by the pipeline beforehand, resident in HBM)."""
+    dims, seeds, bins = cfg["dims"], cfg["seeds"], cfg["bins"]
+    b = hf.PipelineBuffers(dims, len(seeds), bins)
+    hf.pipeline(b, cfg["filt"], seeds)
+    g = torch.empty(b.field.shape, dtype=torch.int8, device="cuda")
+    s2 = torch.empty(b.field.shape, dtype=torch.float32, device="cuda")
+    work = hf.alloc_workspace(hf.HU_OP_TWO_POINT, dims, len(seeds))
+
+    def fn():
+        hf.level_cut(b.field, phi, out=g, counts=False)
+        hf.two_point(g, work=work, out=s2)
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    hf.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    prof = hf.profile_read()
+    hf.profile_enable(False)
+    N = math.prod(dims)
+    Nh = N // dims[-1] * (dims[-1] // 2 + 1)
+    B = len(seeds)
+    t = 8 * Nh * B
+    fam = {"threshold": 5 * N * B, "rows_r2c_load": N * B + t, "cols_y_fwd": 2 * t, "cols_square": 2 * t,
+           "cols_y_inv": 2 * t, "rows_c2r": t + 4 * N * B}
+    kern = {k: dict(mean_ms=round(v[1] / v[0], 5), gbs=round(fam.get(k, 0) / (v[1] / v[0] * 1e-3) / 1e9, 1))
+            for k, v in prof.items()}
+    total = sum(fam.values()) - (0 if len(dims) == 3 else 4 * t)
+    return dict(phi=phi, ms_per_call=round(ms, 4), value=round(N * B / (ms * 1e-3), 1), unit="voxels/s",
+                bytes_min=total, roofline_frac=round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernels=kern)
+
+
 def cpu_baseline(cfg, budget_s=12.0):
     """The FP64 oracle, as it stands, on the workload's fields in order until `budget_s` seconds
     have passed or all are done (single-threaded numpy; pocketfft runs on one core)."""
@@ -556,6 +596,8 @@ def main():
         line["also"]["3d_512cube_forward_and_adjoint"] = time_adjoint(hf, torch, max(args.steps // 5, 5))
         line["also"]["window_variance_2048sq_x16_8radii"] = time_window_variance(hf, torch, C2, max(args.steps // 5, 5))
         line["also"]["window_variance_256cube_x4_8radii"] = time_window_variance(hf, torch, C3, max(args.steps // 5, 5))
+        line["also"]["level_cut_and_two_point_2048sq_x16"] = time_two_point(hf, torch, C2, max(args.steps // 5, 5))
+        line["also"]["level_cut_and_two_point_256cube_x4"] = time_two_point(hf, torch, C3, max(args.steps // 5, 5))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -167,12 +167,23 @@ __global__ void __launch_bounds__(256) k_threshold(ThreshArgs a) {
   const float* f = a.field + (long long)b * a.N;
   int8_t* t = a.out + (long long)b * a.N;
   unsigned np = 0, nn = 0;
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.N; i += (long long)gridDim.x * 256) {
-    const float x = f[i];
-    const bool pos = x >= a.level;
-    t[i] = pos ? (int8_t)1 : (int8_t)-1;
-    np += pos;
-    nn += fabsf(x - a.level) < a.near_tol;
+  // four voxels per step (N is a multiple of 4 on every supported grid): a 16-byte load, one
+  // 4-byte store of the four signs
+  const long long n4 = a.N >> 2;
+  const float4* f4 = reinterpret_cast<const float4*>(f);
+  uint32_t* t4 = reinterpret_cast<uint32_t*>(t);
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
+    const float4 x4 = f4[i];
+    const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
+    uint32_t packed = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool pos = xs[q] >= a.level;
+      packed |= (pos ? 0x01u : 0xFFu) << (8 * q);
+      np += pos;
+      nn += fabsf(xs[q] - a.level) < a.near_tol;
+    }
+    t4[i] = packed;
   }
   np = wave_usum(np);
   nn = wave_usum(nn);
@@ -187,7 +198,8 @@ __global__ void __launch_bounds__(256) k_threshold(ThreshArgs a) {
 }
 
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st) {
-  long long blocks = (a.N + 255) / 256;
+  if (a.N % 4 != 0) return hipErrorInvalidValue;   // every supported grid has an even x and another even axis
+  long long blocks = (a.N / 4 + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_threshold, dim3((unsigned)blocks, batch), dim3(256), 0, st, a);
   return hipGetLastError();

@@ -6,6 +6,11 @@ Definitions followed:
 * target spectral density, Eq. (13): chi = C exp[alpha ln K - K^2/(2 sigma^2)], C fixing max chi = 1;
 * filter amplitude, Eq. (8): A = sqrt(chi).
 
+Mask variants beyond the paper's alpha > 0 (it states it omits any offset regularisation): alpha = 0
+(the standard nonhyperuniform class of Eq. (7), chi(0) > 0), and an offset regularisation
+chi_rel + offset (offset >= 0, relative to the continuum peak), which makes chi(k -> 0) = offset.
+The DC mode gets amplitude 0 for every alpha and offset: Eq. (15) removes the mean anyway.
+
 Readings where the paper is silent or ambiguous (each is listed in the design notes):
 * wavenumbers are in units of the Nyquist wavenumber: kappa_i = 2 m~_i / n_i with m~ the
   signed index (m for m < n/2, else m - n), except along the halved last axis of the
@@ -39,10 +44,11 @@ class FilterParams:
     p      superellipse exponent (Eq. (12))
     semi   (a, b, c): semi-axes for x, y, z (c unused in 2D)
     rot    mask rotation in radians, counter-clockwise in (kappa_x, kappa_y)
-    alpha  small-k exponent (Eqs. (13)-(14)), > 0
+    alpha  small-k exponent (Eqs. (13)-(14)), >= 0 (0: standard nonhyperuniform)
     k0     band centre in Nyquist units (0 reproduces Eq. (13))
     width  Gaussian band width w (sigma of Eq. (13)) in Nyquist units
     sigma_f target standard deviation of the field (Eq. (15))
+    offset regularisation added to chi_rel (>= 0; 0 is the paper's mask)
     """
     p: float
     semi: tuple = (1.0, 1.0, 1.0)
@@ -51,10 +57,11 @@ class FilterParams:
     k0: float = 0.0
     width: float = 0.1
     sigma_f: float = 1.0
+    offset: float = 0.0
 
     def replace(self, **kw):
         d = dict(p=self.p, semi=tuple(self.semi), rot=self.rot, alpha=self.alpha,
-                 k0=self.k0, width=self.width, sigma_f=self.sigma_f)
+                 k0=self.k0, width=self.width, sigma_f=self.sigma_f, offset=self.offset)
         d.update(kw)
         d["semi"] = tuple(float(s) for s in d["semi"]) + (1.0,) * (3 - len(d["semi"]))
         return FilterParams(**d)
@@ -124,10 +131,12 @@ def k_star(filt):
 
 
 def ln_chi_unnorm(K, filt):
-    """alpha ln K - (K - k0)^2/(2 w^2); -inf at K = 0 (chi(0) = 0, Eq. (4))."""
-    with np.errstate(divide="ignore"):
+    """alpha ln K - (K - k0)^2/(2 w^2); -inf at K = 0 for alpha > 0 (chi(0) = 0, Eq. (4)); the
+    alpha ln K term is 0 for alpha = 0."""
+    with np.errstate(divide="ignore", invalid="ignore"):
         lnK = np.log(K)
-    return filt.alpha * lnK - (K - filt.k0) ** 2 / (2.0 * filt.width ** 2)
+        a = np.where(filt.alpha == 0.0, 0.0, filt.alpha * lnK)
+    return a - (K - filt.k0) ** 2 / (2.0 * filt.width ** 2)
 
 
 def ln_chi_rel(K, filt):
@@ -136,14 +145,19 @@ def ln_chi_rel(K, filt):
 
 
 def _amplitude(kappas, filt):
+    """H = sqrt(chi_rel + offset) off the DC mode, 0 at the DC mode; also returns ln(chi_rel + offset)."""
     K, _, _ = superellipse_K(kappas, filt)
     lc = ln_chi_rel(K, filt)
+    if filt.offset > 0.0:
+        lc = np.logaddexp(lc, np.log(filt.offset))
+    lc = np.where(K > 0, lc, -np.inf)
     return np.exp(0.5 * lc), lc
 
 
 def _check_degenerate(lc):
-    if not np.isfinite(np.max(lc)) or np.max(lc) < DEGENERATE_LN_CHI:
-        raise DegenerateFilter("max ln chi over the lattice is %r < %g" % (np.max(lc), DEGENERATE_LN_CHI))
+    m = np.max(lc)
+    if not np.isfinite(m) or m < DEGENERATE_LN_CHI:
+        raise DegenerateFilter("max ln chi over the lattice is %r < %g" % (m, DEGENERATE_LN_CHI))
 
 
 def amplitude_half(dims, filt, check=True):

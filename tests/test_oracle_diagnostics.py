@@ -162,3 +162,12 @@ def test_class_table():
     assert D.CLASSES[D.hyperuniformity_class(0.0, 2)] == "nonhyperuniform (standard)"
     assert D.CLASSES[D.hyperuniformity_class(-1.0, 2)] == "antihyperuniform"
     assert D.CLASSES[D.hyperuniformity_class(-2.5, 2)] == "outside the classified range"
+
+
+def test_alpha_zero_spectrum_is_flat_at_small_k():
+    # alpha = 0 (standard nonhyperuniform, Eq. (7)): chi(k -> 0) > 0, small-k slope 0
+    filt = FilterParams(p=2, semi=(1, 1, 1), alpha=0.0, k0=0.0, width=2.0)
+    T, c = target_bins((512, 512), filt, 64)
+    a = D.small_k_exponent(np.append(T * c, 0.0), np.append(c, 0), 64, 12)
+    assert abs(a) < 0.02
+    assert D.CLASSES[D.hyperuniformity_class(a, 2, tol=0.02)] == "nonhyperuniform (standard)"

@@ -107,3 +107,37 @@ def test_degenerate_filter_raises():
     with pytest.raises(O.DegenerateFilter):
         O.amplitude_half((16, 16), f)
     O.amplitude_half((16, 16), f.replace(width=0.02))
+
+
+# ---- mask variants: alpha = 0 (standard nonhyperuniform) and the offset regularisation --------
+FilterParams, DegenerateFilter, amplitude_half = O.FilterParams, O.DegenerateFilter, O.amplitude_half
+
+
+def test_alpha_zero_is_the_gaussian_band():
+    from oracle.spectral import superellipse_K, wavenumbers_half
+    for k0 in (0.0, 0.25):
+        filt = FilterParams(p=3, semi=(2, 1, 1), rot=0.0, alpha=0.0, k0=k0, width=0.1)
+        H = amplitude_half((32, 48), filt)
+        K, _, _ = superellipse_K(wavenumbers_half((32, 48)), filt)
+        off_dc = K > 0
+        ref = np.exp(-(K - k0) ** 2 / (4 * 0.1 ** 2))        # sqrt of exp(-(K - k0)^2 / (2 w^2)), peak 1
+        np.testing.assert_allclose(H[off_dc], ref[off_dc], rtol=1e-13)
+        assert H.flat[0] == 0.0 and np.all(np.isfinite(H))
+
+
+def test_offset_adds_to_chi():
+    from oracle.spectral import superellipse_K, wavenumbers_half, ln_chi_rel
+    base = FilterParams(p=4, semi=(1, 2, 1), rot=0.3, alpha=2.0, k0=0.2, width=0.05)
+    eps = 1e-3
+    H0 = amplitude_half((64, 64), base)
+    H1 = amplitude_half((64, 64), base.replace(offset=eps))
+    K, _, _ = superellipse_K(wavenumbers_half((64, 64)), base)
+    off_dc = K > 0
+    np.testing.assert_allclose(H1[off_dc] ** 2, H0[off_dc] ** 2 + eps, rtol=1e-13)
+    assert H1.flat[0] == 0.0
+    # a band far off the lattice is degenerate without the offset and not with it
+    far = FilterParams(p=2, alpha=2.0, k0=5.0, width=0.01)
+    with pytest.raises(DegenerateFilter):
+        amplitude_half((16, 16), far)
+    H = amplitude_half((16, 16), far.replace(offset=1e-6))
+    np.testing.assert_allclose(H.ravel()[1:] ** 2, 1e-6, rtol=1e-9)

@@ -88,10 +88,13 @@ typedef struct hu_filter {
   double p;        /* superellipse exponent, > 0 (Eq. (12)) */
   double semi[3];  /* semi-axes a (x), b (y), c (z), > 0; c unused in 2D */
   double rot;      /* mask rotation, radians, counter-clockwise in (kappa_x, kappa_y); about z in 3D */
-  double alpha;    /* small-k exponent, > 0 (Eqs. (13)-(14)) */
+  double alpha;    /* small-k exponent, >= 0 (Eqs. (13)-(14)); 0 is the standard nonhyperuniform
+                      class of Eq. (7) */
   double k0;       /* band centre, >= 0 (0 gives Eq. (13) exactly) */
   double width;    /* Gaussian band width w, > 0 (sigma of Eq. (13)) */
   double sigma_f;  /* target standard deviation of the field, > 0 (Eq. (15)) */
+  double offset;   /* offset regularisation >= 0 added to the peak-normalised spectral density on
+                      every mode but the DC (chi(k -> 0) = offset); 0 is the paper's mask */
 } hu_filter;
 
 typedef struct hu_bins {
@@ -215,7 +218,8 @@ int hu_hyperuniformity_class(double alpha, int32_t d, double tol);
  * P_b = cont_sum_b / cont_cnt_b (the corner slot R*A and empty bins are ignored); all device.
  * Writes grad [7] = dL/d(a, b, c, p, rot, k0, w) (device FP64; the c entry is 0 in 2D).  The
  * noise spectrum is regenerated from the seed (nothing of the forward field is read), and the
- * seven sums are FP64, reduced in a fixed order (bit-reproducible).
+ * seven sums are FP64, reduced in a fixed order (bit-reproducible).  HU_ERR_UNSUPPORTED for a filter
+ * with a nonzero offset (only the amplitude sqrt(chi) is differentiated).
  * Workspace: hu_workspace_size(HU_OP_LOSS, dims, 1, &bins, ...). */
 int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins bins, const double* dL_dP,
                      const double* cont_sum, const uint64_t* cont_cnt, const double* stats, double* grad,

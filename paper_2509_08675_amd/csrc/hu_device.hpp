@@ -474,6 +474,8 @@ struct FiltDev {
   float alpha, k0;
   float inv2w2;          // 1 / (2 w^2)
   float lnchimax;        // ln chi at K* (continuum peak)
+  float offset;          // offset regularisation added to chi / chi(K*) (0: none)
+  float lnoffset;        // ln offset, or -1e30
   int rotated;           // rot != 0 (H_sym differs from H on x / y Nyquist planes)
 };
 
@@ -525,6 +527,14 @@ __device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, fl
 
 // exp(x / 2) for ln chi -> amplitude
 __device__ __forceinline__ float amp_from_lnchi(float lnc) { return hw_exp2(lnc * 0.72134752044448170368f); }
+
+// sqrt(chi_rel + offset) with the offset regularisation (a uniform branch); the DC mode (ln chi
+// returned as -1e30) keeps amplitude 0
+__device__ __forceinline__ float amp_from_lnchi(float lnc, float offset) {
+  if (offset > 0.0f)
+    return lnc > -1.0e29f ? __builtin_sqrtf(hw_exp2(lnc * 1.44269504088896340736f) + offset) : 0.0f;
+  return amp_from_lnchi(lnc);
+}
 
 // ---------------------------------------------------------------------------------------------
 // Bin index: exact integer radial rule, FP64 angular edges tested with separately rounded

@@ -36,7 +36,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   const FiltDev filt = a.io ? a.io[b].filt : a.filt;
   const ColCoord cc = col_coord(a.gm, valid ? g : 0);
   double gsum = 0.0, f0 = 0.0;
-  float lmax = -1.0e30f;
+  float lmax = filt.lnoffset;             // the lattice maximum of ln(chi_rel + offset) is at least ln offset
   // the exchange buffer is free once every thread has its transform in registers: the power
   // values of the continuous spectrum go to LDS as they are computed
   float* pw = reinterpret_cast<float*>(lds);

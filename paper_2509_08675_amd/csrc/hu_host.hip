@@ -295,7 +295,8 @@ int check_filter(const hu_filter* f, int nd) {
   if (!f) return HU_ERR_ARG;
   if (!finite_pos(f->p) || !finite_pos(f->semi[0]) || !finite_pos(f->semi[1])) return HU_ERR_ARG;
   if (nd == 3 && !finite_pos(f->semi[2])) return HU_ERR_ARG;
-  if (!finite_pos(f->alpha) || !finite_pos(f->width) || !finite_pos(f->sigma_f)) return HU_ERR_ARG;
+  if (!std::isfinite(f->alpha) || f->alpha < 0.0 || !finite_pos(f->width) || !finite_pos(f->sigma_f)) return HU_ERR_ARG;
+  if (!std::isfinite(f->offset) || f->offset < 0.0) return HU_ERR_ARG;
   if (!std::isfinite(f->rot) || !std::isfinite(f->k0) || f->k0 < 0.0) return HU_ERR_ARG;
   return HU_OK;
 }
@@ -366,7 +367,10 @@ FiltDev filt_dev(const hu_filter& f) {
   // ln chi at the continuum peak K* = (k0 + sqrt(k0^2 + 4 alpha w^2)) / 2, in FP64
   const double ks = 0.5 * (f.k0 + std::sqrt(f.k0 * f.k0 + 4.0 * f.alpha * f.width * f.width));
   const double dd = ks - f.k0;
-  d.lnchimax = (float)(f.alpha * std::log(ks) - dd * dd / (2.0 * f.width * f.width));
+  // (the alpha ln K term is 0 for alpha = 0, also at K* = k0 = 0)
+  d.lnchimax = (float)((f.alpha > 0.0 ? f.alpha * std::log(ks) : 0.0) - dd * dd / (2.0 * f.width * f.width));
+  d.offset = (float)f.offset;
+  d.lnoffset = f.offset > 0.0 ? (float)std::log(f.offset) : -1.0e30f;
   d.rotated = (f.rot != 0.0) ? 1 : 0;
   return d;
 }

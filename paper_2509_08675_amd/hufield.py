@@ -37,7 +37,7 @@ class hu_dims(ctypes.Structure):
 class hu_filter(ctypes.Structure):
     _fields_ = [("p", ctypes.c_double), ("semi", ctypes.c_double * 3), ("rot", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("k0", ctypes.c_double), ("width", ctypes.c_double),
-                ("sigma_f", ctypes.c_double)]
+                ("sigma_f", ctypes.c_double), ("offset", ctypes.c_double)]
 
 
 class hu_bins(ctypes.Structure):
@@ -130,7 +130,8 @@ def make_dims(dims):
 
 
 def make_filter(f):
-    """hu_filter from a dict (keys p, semi, rot, alpha, k0, width, sigma_f) or an object with those attributes."""
+    """hu_filter from a dict (keys p, semi, rot, alpha, k0, width, sigma_f, offset) or an object with those
+    attributes."""
     get = (lambda k, dflt=None: f.get(k, dflt)) if isinstance(f, dict) else (lambda k, dflt=None: getattr(f, k, dflt))
     h = hu_filter()
     h.p = float(get("p"))
@@ -142,6 +143,7 @@ def make_filter(f):
     h.k0 = float(get("k0", 0.0))
     h.width = float(get("width"))
     h.sigma_f = float(get("sigma_f", 1.0))
+    h.offset = float(get("offset", 0.0))
     return h
 
 

@@ -15,10 +15,10 @@ import math
 import numpy as np
 
 
-def filt(p, semi=(1.0, 1.0, 1.0), rot=0.0, alpha=2.0, k0=0.0, width=0.1, sigma_f=1.0):
+def filt(p, semi=(1.0, 1.0, 1.0), rot=0.0, alpha=2.0, k0=0.0, width=0.1, sigma_f=1.0, offset=0.0):
     semi = tuple(float(s) for s in semi) + (1.0,) * (3 - len(semi))
     return dict(p=float(p), semi=semi, rot=float(rot), alpha=float(alpha), k0=float(k0),
-                width=float(width), sigma_f=float(sigma_f))
+                width=float(width), sigma_f=float(sigma_f), offset=float(offset))
 
 
 # 2D 128^2, one field, isotropic circle, alpha = 2, band at 0.25 k_Nyq, width 0.05; 64 radial bins.

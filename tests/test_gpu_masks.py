@@ -1,0 +1,63 @@
+"""GPU tests of the mask variants beyond the paper's alpha > 0 (alpha = 0 and the offset
+regularisation); the whole-pipeline parity cases for them are in test_gpu_parity.py.
+
+* the expected spectrum of a filter with an offset against the oracle (rtol 1e-5);
+* the adjoint refuses a filter with an offset (HU_ERR_UNSUPPORTED), and negative alpha or offset
+  are argument errors;
+* the small-k exponent of a generated alpha = 0 field is near 0 (standard nonhyperuniform; a
+  property of the method, statistical tolerance 0.15).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2509_08675_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_08675_amd import hufield
+    return hufield
+
+
+def test_filter_spectrum_with_offset_matches_oracle(hf):
+    dims, nr = (96, 64), 24
+    filt = W.filt(p=4, semi=(2, 1, 1), rot=0.4, alpha=2, k0=0.2, width=0.05, offset=5e-3)
+    s, c = hf.filter_spectrum(dims, filt, (nr, 1))
+    torch.cuda.synchronize()
+    T_ref, c_ref = O.target_bins(dims, O.FilterParams(**filt), nr)
+    cnt = hf.u64_view(c)
+    np.testing.assert_array_equal(cnt[:nr], c_ref.astype(np.uint64))
+    got = s.cpu().numpy()[:nr] / np.maximum(cnt[:nr], 1)
+    np.testing.assert_allclose(got[c_ref > 0], T_ref[c_ref > 0], rtol=1e-5)
+
+
+def test_variant_argument_errors(hf):
+    dims, bins = (32, 32), (8, 1)
+    d = torch.zeros(9, dtype=torch.float64, device="cuda")
+    c = torch.zeros(9, dtype=torch.int64, device="cuda")
+    st = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(hf.HuError) as e:
+        hf.spectrum_grad(dims, W.filt(p=2, alpha=2, k0=0.2, width=0.05, offset=1e-3), 1, bins, d, d, c, st)
+    assert e.value.code == hf.HU_ERR_UNSUPPORTED
+    for bad in (dict(alpha=-0.5), dict(offset=-1e-3), dict(offset=float("inf"))):
+        f = {**W.filt(p=2, alpha=2, k0=0.2, width=0.05), **bad}
+        with pytest.raises(hf.HuError) as e:
+            hf.gen_field(dims, f, [1])
+        assert e.value.code == hf.HU_ERR_ARG
+
+
+def test_alpha_zero_field_is_standard_nonhyperuniform(hf):
+    dims, bins = (2048, 2048), (64, 1)
+    filt = W.filt(p=2, alpha=0.0, k0=0.0, width=2.0)
+    out = hf.gen_field(dims, filt, [5], cont_bins=bins)
+    a = hf.small_k_exponent(out["cont_sum"][0], hf.u64_view(out["cont_cnt"][0]), bins, 12)
+    print("exponent", a, flush=True)
+    assert abs(a) < 0.15
+    assert hf.hyperuniformity_class(a, 2, tol=0.15) == "nonhyperuniform (standard)"

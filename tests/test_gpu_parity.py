@@ -72,6 +72,11 @@ PIPE_CASES = [
     ("3d_12x24x32_rot", (12, 24, 32), _filt(p=2.5, semi=(2, 1, 1.5), rot=0.7, alpha=4, k0=0.3, width=0.1), (20, 1), [7]),
     ("3d_64cube", (64, 64, 64), W.C3["filt"], (128, 1), [1]),
     ("3d_96x48x24", (96, 48, 24), _filt(p=4, semi=(1, 1.5, 2), rot=0.3, alpha=2, k0=0.2, width=0.06), (64, 1), [11]),
+    # mask variants: alpha = 0 (standard nonhyperuniform) and the offset regularisation
+    ("2d_64x96_alpha0", (64, 96), _filt(p=3, semi=(2, 1), rot=0.3, alpha=0, k0=0.15, width=0.05), (24, 6), [2]),
+    ("2d_128x64_offset", (128, 64), _filt(p=4, semi=(1, 2), rot=0.5, alpha=4, k0=0.2, width=0.04, offset=1e-3),
+     (32, 1), [3]),
+    ("3d_32x16x24_alpha0_offset", (32, 16, 24), _filt(p=2, alpha=0, k0=0.0, width=0.2, offset=1e-2), (16, 1), [4]),
 ]
 
 

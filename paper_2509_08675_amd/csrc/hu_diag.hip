@@ -10,14 +10,32 @@
 
 namespace hu {
 
-// W^2 at u = |k| R in FP32.  3D: below u = 1 the closed form loses digits to cancellation, so the
-// Taylor series 3 sum_{n>=1} (-1)^(n+1) 2n u^(2n-2) / (2n+1)! (through u^10; the next term is
-// below 3.3e-11 at u = 1) is used there.
+// W^2 at u = |k| R in FP32.
+// 2D: J_1 by the polynomial approximations of Abramowitz & Stegun (Handbook of Mathematical
+// Functions, 9.4.4 for u <= 3: J_1(u)/u as a polynomial in (u/3)^2, |error| < 1.3e-8; 9.4.6 for
+// u > 3: J_1(u) = u^(-1/2) f_1 cos(theta_1), f_1 and theta_1 - u polynomials in 3/u, absolute error
+// of J_1 below 1e-7), so W = 2 J_1(u) / u costs a few fused multiply-adds and three hardware
+// transcendentals.
+// 3D: below u = 1 the closed form loses digits to cancellation, so the Taylor series
+// 3 sum_{n>=1} (-1)^(n+1) 2n u^(2n-2) / (2n+1)! (through u^10; the next term is below 3.3e-11 at
+// u = 1) is used there; above, the closed form with the hardware sine and cosine.
 template <int NDIM>
 __device__ __forceinline__ float window_w2(float u) {
   float w;
   if constexpr (NDIM == 2) {
-    w = u > 0.0f ? 2.0f * j1f(u) / u : 1.0f;
+    if (u <= 3.0f) {
+      const float t = (u * (1.0f / 3.0f)) * (u * (1.0f / 3.0f));
+      w = 2.0f * (0.5f + t * (-0.56249985f + t * (0.21093573f + t * (-0.03954289f +
+                                     t * (0.00443319f + t * (-0.00031761f + t * 0.00001109f))))));
+    } else {
+      const float y = 3.0f * __builtin_amdgcn_rcpf(u);
+      const float f1 = 0.79788456f + y * (0.00000156f + y * (0.01659667f + y * (0.00017105f +
+                                     y * (-0.00249511f + y * (0.00113653f + y * (-0.00020033f))))));
+      const float th = (u - 2.35619449f) + y * (0.12499612f + y * (0.00005650f + y * (-0.00637879f +
+                                     y * (0.00074348f + y * (0.00079824f + y * (-0.00029166f))))));
+      const float ru = __builtin_amdgcn_rsqf(u);
+      w = 2.0f * f1 * __cosf(th) * ru * ru * ru;
+    }
   } else {
     if (u < 1.0f) {
       const float t = u * u;
@@ -25,8 +43,9 @@ __device__ __forceinline__ float window_w2(float u) {
                                               t * (1.0f / 1330560.0f + t * (-1.0f / 172972800.0f)))));
     } else {
       float s, c;
-      sincosf(u, &s, &c);
-      w = 3.0f * (s - u * c) / (u * u * u);
+      __sincosf(u, &s, &c);           // hardware sin / cos: ~1e-7 absolute, W is O(u^-2) beyond
+      const float ri = __builtin_amdgcn_rcpf(u);
+      w = 3.0f * (s - u * c) * (ri * ri * ri);
     }
   }
   return w * w;

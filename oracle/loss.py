@@ -85,7 +85,7 @@ def _dlnH(kappas, filt):
     up to theta-dependent constants (from C), which cancel in the loss.  Partials from
     Eqs. (12)-(13): K = S^(1/p), S = sum u_i^p, u_i = |kappa'_i| / a_i."""
     K, us, comps = superellipse_K(kappas, filt)
-    H = np.exp(0.5 * ln_chi_rel(K, filt))
+    H = np.exp(0.5 * ln_chi_rel(K, filt, kappas))
     p, al, k0, w = filt.p, filt.alpha, filt.k0, filt.width
     pos = K > 0
     Ks = np.where(pos, K, 1.0)

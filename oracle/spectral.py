@@ -7,9 +7,11 @@ Definitions followed:
 * filter amplitude, Eq. (8): A = sqrt(chi).
 
 Mask variants beyond the paper's alpha > 0 (it states it omits any offset regularisation): alpha = 0
-(the standard nonhyperuniform class of Eq. (7), chi(0) > 0), and an offset regularisation
-chi_rel + offset (offset >= 0, relative to the continuum peak), which makes chi(k -> 0) = offset.
-The DC mode gets amplitude 0 for every alpha and offset: Eq. (15) removes the mean anyway.
+(the standard nonhyperuniform class of Eq. (7), chi(0) > 0), -d < alpha < 0 (antihyperuniform,
+chi diverging as k -> 0; the continuum then has no maximum, so C is fixed by the bound of
+``ln_chi_ref`` on the lattice), and an offset regularisation chi_rel + offset (offset >= 0,
+relative to the continuum peak; alpha >= 0 only), which makes chi(k -> 0) = offset.  The DC mode
+gets amplitude 0 for every alpha and offset: Eq. (15) removes the mean anyway.
 
 Readings where the paper is silent or ambiguous (each is listed in the design notes):
 * wavenumbers are in units of the Nyquist wavenumber: kappa_i = 2 m~_i / n_i with m~ the
@@ -44,7 +46,7 @@ class FilterParams:
     p      superellipse exponent (Eq. (12))
     semi   (a, b, c): semi-axes for x, y, z (c unused in 2D)
     rot    mask rotation in radians, counter-clockwise in (kappa_x, kappa_y)
-    alpha  small-k exponent (Eqs. (13)-(14)), >= 0 (0: standard nonhyperuniform)
+    alpha  small-k exponent (Eqs. (13)-(14)), > -d (0: standard nonhyperuniform, < 0 antihyperuniform)
     k0     band centre in Nyquist units (0 reproduces Eq. (13))
     width  Gaussian band width w (sigma of Eq. (13)) in Nyquist units
     sigma_f target standard deviation of the field (Eq. (15))
@@ -126,8 +128,33 @@ def superellipse_K(kappas, filt):
 
 
 def k_star(filt):
-    """Continuum peak of alpha ln K - (K - k0)^2/(2 w^2): root of K^2 - k0 K - alpha w^2 = 0."""
+    """Continuum peak of alpha ln K - (K - k0)^2/(2 w^2): root of K^2 - k0 K - alpha w^2 = 0 (for
+    alpha < 0 the band's local maximum, when k0^2 + 4 alpha w^2 >= 0)."""
     return 0.5 * (filt.k0 + np.sqrt(filt.k0 ** 2 + 4.0 * filt.alpha * filt.width ** 2))
+
+
+def k_low(kappas, filt):
+    """For alpha < 0: a lower bound of K over every nonzero lattice wavenumber,
+    min_i (smallest nonzero |kappa_i|) / (sqrt(d) max_i semi_i), since K >= max_i u_i >= |kappa'| /
+    (sqrt(d) max semi)."""
+    d = len(kappas)
+    kmin = min(float(np.min(np.abs(k[k != 0]))) for k in kappas)
+    return kmin / (np.sqrt(d) * max(filt.semi[:d]))
+
+
+def ln_chi_ref(filt, kappas=None):
+    """The normalisation of Eq. (13) (ln C = -ln chi_ref): the continuum peak for alpha >= 0; for
+    alpha < 0, where the continuum has no maximum as K -> 0, the larger of chi at k_low and at the
+    band's local maximum, which bounds chi on the lattice."""
+    if filt.alpha >= 0.0:
+        return float(ln_chi_unnorm(np.float64(k_star(filt)), filt))
+    if kappas is None:
+        raise ValueError("alpha < 0 needs the lattice for its normalisation")
+    ref = float(ln_chi_unnorm(np.float64(k_low(kappas, filt)), filt))
+    disc = filt.k0 ** 2 + 4.0 * filt.alpha * filt.width ** 2
+    if disc >= 0.0:
+        ref = max(ref, float(ln_chi_unnorm(np.float64(k_star(filt)), filt)))
+    return ref
 
 
 def ln_chi_unnorm(K, filt):
@@ -139,15 +166,15 @@ def ln_chi_unnorm(K, filt):
     return a - (K - filt.k0) ** 2 / (2.0 * filt.width ** 2)
 
 
-def ln_chi_rel(K, filt):
-    """ln chi - ln chi_max, i.e. ln chi of Eq. (13) with C = 1/chi_max (max chi = 1)."""
-    return ln_chi_unnorm(K, filt) - ln_chi_unnorm(k_star(filt), filt)
+def ln_chi_rel(K, filt, kappas=None):
+    """ln chi - ln chi_ref, i.e. ln chi of Eq. (13) with C = 1/chi_ref (max chi = 1 for alpha >= 0)."""
+    return ln_chi_unnorm(K, filt) - ln_chi_ref(filt, kappas)
 
 
 def _amplitude(kappas, filt):
     """H = sqrt(chi_rel + offset) off the DC mode, 0 at the DC mode; also returns ln(chi_rel + offset)."""
     K, _, _ = superellipse_K(kappas, filt)
-    lc = ln_chi_rel(K, filt)
+    lc = ln_chi_rel(K, filt, kappas)
     if filt.offset > 0.0:
         lc = np.logaddexp(lc, np.log(filt.offset))
     lc = np.where(K > 0, lc, -np.inf)

@@ -171,3 +171,12 @@ def test_alpha_zero_spectrum_is_flat_at_small_k():
     a = D.small_k_exponent(np.append(T * c, 0.0), np.append(c, 0), 64, 12)
     assert abs(a) < 0.02
     assert D.CLASSES[D.hyperuniformity_class(a, 2, tol=0.02)] == "nonhyperuniform (standard)"
+
+
+def test_negative_alpha_spectrum_slope_is_alpha():
+    # -d < alpha < 0 (antihyperuniform, Eq. (7)): chi ~ |k|^alpha diverges at small k
+    filt = FilterParams(p=2, semi=(1, 1, 1), alpha=-1.0, k0=0.0, width=2.0)
+    T, c = target_bins((512, 512), filt, 64)
+    a = D.small_k_exponent(np.append(T * c, 0.0), np.append(c, 0), 64, 12)
+    assert a == pytest.approx(-1.0, rel=0.03)
+    assert D.CLASSES[D.hyperuniformity_class(a, 2)] == "antihyperuniform"

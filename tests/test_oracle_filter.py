@@ -141,3 +141,17 @@ def test_offset_adds_to_chi():
         amplitude_half((16, 16), far)
     H = amplitude_half((16, 16), far.replace(offset=1e-6))
     np.testing.assert_allclose(H.ravel()[1:] ** 2, 1e-6, rtol=1e-9)
+
+
+def test_negative_alpha_normalisation_bounds_chi_on_the_lattice():
+    from oracle.spectral import superellipse_K, wavenumbers_half, ln_chi_rel
+    for filt in (FilterParams(p=3, semi=(2, 1, 1), rot=0.4, alpha=-1.0, k0=0.0, width=0.3),
+                 FilterParams(p=2, semi=(1, 1, 1), rot=0.0, alpha=-0.5, k0=0.5, width=0.01),   # band far above k_low
+                 FilterParams(p=6, semi=(1, 3, 1), rot=1.0, alpha=-1.5, k0=0.2, width=0.05)):
+        ks = wavenumbers_half((64, 96))
+        K, _, _ = superellipse_K(ks, filt)
+        lc = ln_chi_rel(K[K > 0], filt, ks)
+        assert np.max(lc) <= 1e-12                       # chi_rel <= 1 on the lattice
+        assert np.max(lc) > -20.0                        # and the bound is not far above the maximum
+        H = amplitude_half((64, 96), filt)
+        assert H.flat[0] == 0.0 and np.all(np.isfinite(H))

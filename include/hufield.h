@@ -88,13 +88,14 @@ typedef struct hu_filter {
   double p;        /* superellipse exponent, > 0 (Eq. (12)) */
   double semi[3];  /* semi-axes a (x), b (y), c (z), > 0; c unused in 2D */
   double rot;      /* mask rotation, radians, counter-clockwise in (kappa_x, kappa_y); about z in 3D */
-  double alpha;    /* small-k exponent, >= 0 (Eqs. (13)-(14)); 0 is the standard nonhyperuniform
-                      class of Eq. (7) */
+  double alpha;    /* small-k exponent, > -d (Eqs. (13)-(14)); 0 is the standard nonhyperuniform
+                      class and -d < alpha < 0 the antihyperuniform one of Eq. (7) */
   double k0;       /* band centre, >= 0 (0 gives Eq. (13) exactly) */
   double width;    /* Gaussian band width w, > 0 (sigma of Eq. (13)) */
   double sigma_f;  /* target standard deviation of the field, > 0 (Eq. (15)) */
   double offset;   /* offset regularisation >= 0 added to the peak-normalised spectral density on
-                      every mode but the DC (chi(k -> 0) = offset); 0 is the paper's mask */
+                      every mode but the DC (chi(k -> 0) = offset); 0 is the paper's mask;
+                      HU_ERR_UNSUPPORTED together with alpha < 0 */
 } hu_filter;
 
 typedef struct hu_bins {

@@ -269,7 +269,7 @@ int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double
   FilterSpecArgs a{};
   a.gm = axis0(g);
   a.Nh = (long long)a.gm.ncol * a.gm.n0;
-  a.filt = filt_dev(*filt);
+  a.filt = filt_dev(*filt, g);
   a.bd = bd;
   a.nb = nb;
   a.table = geo.table;
@@ -355,7 +355,7 @@ int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins
   aa.ntiles = lay.tiles;
   aa.spec = spec;
   aa.Nh = g.Nhp;
-  aa.filt = filt_dev(*filt);
+  aa.filt = filt_dev(*filt, g);
   aa.width = (float)filt->width;
   aa.bd = bd;
   aa.nb = nb;

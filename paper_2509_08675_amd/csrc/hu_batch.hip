@@ -161,7 +161,7 @@ int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t
       f.seed = jb.seed;
       f.sigma_f = jb.filt.sigma_f;
       f.near_abs = (float)(near_tol * jb.filt.sigma_f);
-      f.filt = filt_dev(jb.filt);
+      f.filt = filt_dev(jb.filt, c.g);
       io.push_back(f);
     }
   FieldIO* io_dev = reinterpret_cast<FieldIO*>(w);

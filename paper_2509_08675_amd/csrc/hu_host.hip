@@ -295,8 +295,10 @@ int check_filter(const hu_filter* f, int nd) {
   if (!f) return HU_ERR_ARG;
   if (!finite_pos(f->p) || !finite_pos(f->semi[0]) || !finite_pos(f->semi[1])) return HU_ERR_ARG;
   if (nd == 3 && !finite_pos(f->semi[2])) return HU_ERR_ARG;
-  if (!std::isfinite(f->alpha) || f->alpha < 0.0 || !finite_pos(f->width) || !finite_pos(f->sigma_f)) return HU_ERR_ARG;
+  if (!std::isfinite(f->alpha) || !(f->alpha > -(double)nd) || !finite_pos(f->width) || !finite_pos(f->sigma_f))
+    return HU_ERR_ARG;
   if (!std::isfinite(f->offset) || f->offset < 0.0) return HU_ERR_ARG;
+  if (f->offset > 0.0 && f->alpha < 0.0) return HU_ERR_UNSUPPORTED;   // the offset is relative to a continuum peak
   if (!std::isfinite(f->rot) || !std::isfinite(f->k0) || f->k0 < 0.0) return HU_ERR_ARG;
   return HU_OK;
 }
@@ -352,7 +354,7 @@ hipError_t resident_blocks(const void* kern, int threads, size_t lds, int* slots
   return hipSuccess;
 }
 
-FiltDev filt_dev(const hu_filter& f) {
+FiltDev filt_dev(const hu_filter& f, const Geom& g) {
   FiltDev d{};
   d.cr = (float)std::cos(f.rot);
   d.sr = (float)std::sin(f.rot);
@@ -364,11 +366,30 @@ FiltDev filt_dev(const hu_filter& f) {
   d.alpha = (float)f.alpha;
   d.k0 = (float)f.k0;
   d.inv2w2 = (float)(1.0 / (2.0 * f.width * f.width));
-  // ln chi at the continuum peak K* = (k0 + sqrt(k0^2 + 4 alpha w^2)) / 2, in FP64
-  const double ks = 0.5 * (f.k0 + std::sqrt(f.k0 * f.k0 + 4.0 * f.alpha * f.width * f.width));
-  const double dd = ks - f.k0;
-  // (the alpha ln K term is 0 for alpha = 0, also at K* = k0 = 0)
-  d.lnchimax = (float)((f.alpha > 0.0 ? f.alpha * std::log(ks) : 0.0) - dd * dd / (2.0 * f.width * f.width));
+  // the normalisation of Eq. (13), in FP64: ln chi at the continuum peak
+  // K* = (k0 + sqrt(k0^2 + 4 alpha w^2)) / 2 for alpha >= 0 (the alpha ln K term is 0 for alpha = 0,
+  // also at K* = k0 = 0); for alpha < 0 the continuum has no maximum as K -> 0, and the larger of
+  // ln chi at k_low = min_i(2 / n_i) / (sqrt(d) max semi) -- a lower bound of every nonzero lattice
+  // K -- and at the band's local maximum (when it exists) bounds chi on the lattice
+  const double w2 = 2.0 * f.width * f.width;
+  auto lnchi = [&](double K) { return (f.alpha != 0.0 ? f.alpha * std::log(K) : 0.0) - (K - f.k0) * (K - f.k0) / w2; };
+  const double disc = f.k0 * f.k0 + 4.0 * f.alpha * f.width * f.width;
+  const double ks = disc >= 0.0 ? 0.5 * (f.k0 + std::sqrt(disc)) : 0.0;
+  double ref;
+  if (f.alpha >= 0.0) {
+    ref = f.alpha > 0.0 ? lnchi(ks) : 0.0;
+  } else {
+    int nmax = 0;
+    double smax = 0.0;
+    for (int i = 0; i < g.nd; ++i) {
+      nmax = g.n[i] > nmax ? g.n[i] : nmax;
+      smax = f.semi[i] > smax ? f.semi[i] : smax;
+    }
+    const double klow = (2.0 / nmax) / (std::sqrt((double)g.nd) * smax);
+    ref = lnchi(klow);
+    if (disc >= 0.0 && ks > 0.0) ref = std::fmax(ref, lnchi(ks));
+  }
+  d.lnchimax = (float)ref;
   d.offset = (float)f.offset;
   d.lnoffset = f.offset > 0.0 ? (float)std::log(f.offset) : -1.0e30f;
   d.rotated = (f.rot != 0.0) ? 1 : 0;
@@ -563,7 +584,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fa.N = g.N;
   fa.gm = axis0(g);
   fa.sc = col_sched(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B);
-  if (!batch_mode) fa.filt = filt_dev(r.filt);
+  if (!batch_mode) fa.filt = filt_dev(r.filt, g);
   fa.io = r.io;
   fa.bd = bd;
   fa.nb = nb;

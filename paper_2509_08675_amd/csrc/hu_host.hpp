@@ -54,7 +54,7 @@ int check_bins(const hu_bins* b, int nd);
 bool aligned(const void* p, size_t a);
 size_t up256(size_t x);
 Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan);
-FiltDev filt_dev(const hu_filter& f);
+FiltDev filt_dev(const hu_filter& f, const Geom& g);
 Axis0Geom axis0(const Geom& g);
 int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd);
 int get_tw(int L, const float2** tw);

@@ -1,11 +1,11 @@
-"""GPU tests of the mask variants beyond the paper's alpha > 0 (alpha = 0 and the offset
-regularisation); the whole-pipeline parity cases for them are in test_gpu_parity.py.
+"""GPU tests of the mask variants beyond the paper's alpha > 0 (alpha = 0, -d < alpha < 0 and the
+offset regularisation); the whole-pipeline parity cases for them are in test_gpu_parity.py.
 
 * the expected spectrum of a filter with an offset against the oracle (rtol 1e-5);
 * the adjoint refuses a filter with an offset (HU_ERR_UNSUPPORTED), and negative alpha or offset
   are argument errors;
-* the small-k exponent of a generated alpha = 0 field is near 0 (standard nonhyperuniform; a
-  property of the method, statistical tolerance 0.15).
+* the small-k exponents of generated alpha = 0 and alpha = -1 fields are near 0 and -1 (standard
+  nonhyperuniform and antihyperuniform; properties of the method, statistical tolerance 0.15).
 """
 
 import numpy as np
@@ -46,11 +46,24 @@ def test_variant_argument_errors(hf):
     with pytest.raises(hf.HuError) as e:
         hf.spectrum_grad(dims, W.filt(p=2, alpha=2, k0=0.2, width=0.05, offset=1e-3), 1, bins, d, d, c, st)
     assert e.value.code == hf.HU_ERR_UNSUPPORTED
-    for bad in (dict(alpha=-0.5), dict(offset=-1e-3), dict(offset=float("inf"))):
+    for bad in (dict(alpha=-2.0), dict(offset=-1e-3), dict(offset=float("inf"))):
         f = {**W.filt(p=2, alpha=2, k0=0.2, width=0.05), **bad}
         with pytest.raises(hf.HuError) as e:
             hf.gen_field(dims, f, [1])
         assert e.value.code == hf.HU_ERR_ARG
+    with pytest.raises(hf.HuError) as e:                    # the offset is relative to a continuum peak
+        hf.gen_field(dims, W.filt(p=2, alpha=-1.0, k0=0.2, width=0.05, offset=1e-3), [1])
+    assert e.value.code == hf.HU_ERR_UNSUPPORTED
+
+
+def test_negative_alpha_field_is_antihyperuniform(hf):
+    dims, bins = (2048, 2048), (64, 1)
+    filt = W.filt(p=2, alpha=-1.0, k0=0.0, width=2.0)
+    out = hf.gen_field(dims, filt, [6], cont_bins=bins)
+    a = hf.small_k_exponent(out["cont_sum"][0], hf.u64_view(out["cont_cnt"][0]), bins, 12)
+    print("exponent", a, flush=True)
+    assert abs(a + 1.0) < 0.15
+    assert hf.hyperuniformity_class(a, 2) == "antihyperuniform"
 
 
 def test_alpha_zero_field_is_standard_nonhyperuniform(hf):

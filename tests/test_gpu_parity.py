@@ -77,6 +77,8 @@ PIPE_CASES = [
     ("2d_128x64_offset", (128, 64), _filt(p=4, semi=(1, 2), rot=0.5, alpha=4, k0=0.2, width=0.04, offset=1e-3),
      (32, 1), [3]),
     ("3d_32x16x24_alpha0_offset", (32, 16, 24), _filt(p=2, alpha=0, k0=0.0, width=0.2, offset=1e-2), (16, 1), [4]),
+    ("2d_96x128_alpha_neg", (96, 128), _filt(p=3, semi=(1, 2), rot=0.6, alpha=-1.0, k0=0.3, width=0.05), (32, 6), [5]),
+    ("3d_24x32x16_alpha_neg", (24, 32, 16), _filt(p=4, semi=(1, 1.5, 2), alpha=-1.5, k0=0.0, width=0.3), (16, 1), [6]),
 ]
 
 

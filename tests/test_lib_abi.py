@@ -79,7 +79,7 @@ def test_argument_errors_before_any_launch(hf):
     seeds = (ctypes.c_uint64 * 1)(1)
     good = hf.make_filter(dict(p=2, semi=(1, 1, 1), rot=0, alpha=2, k0=0.2, width=0.05))
     fake = ctypes.c_void_p(1 << 20)           # never dereferenced: validation fails first
-    for bad in (dict(p=0.0), dict(alpha=-1.0), dict(width=0.0), dict(k0=-0.1), dict(sigma_f=float("nan"))):
+    for bad in (dict(p=0.0), dict(alpha=-2.0), dict(width=0.0), dict(k0=-0.1), dict(sigma_f=float("nan"))):
         f = hf.make_filter({**dict(p=2, semi=(1, 1, 1), rot=0, alpha=2, k0=0.2, width=0.05), **bad})
         rc = lib.hu_gen_field(d, 1, ctypes.byref(f), seeds, fake, None, None, None, None, fake, 1 << 30, None)
         assert rc == hf.HU_ERR_ARG

@@ -118,3 +118,12 @@ def test_small_k_exponent_of_a_generated_field(hf):
     _say("exponent", a)
     assert abs(a - 2.0) < 0.15
     assert hf.hyperuniformity_class(a, 2, tol=0.05) == "hyperuniform class I"
+
+
+def test_window_variance_batch_beyond_one_chunk(hf):
+    # 70 fields: two chunks of the 64-field launch limit
+    dims = (16, 24)
+    x = _random_fields(dims, 70, 13)
+    got = hf.window_variance(torch.from_numpy(x).cuda(), RADII[:4]).cpu().numpy()
+    for b in (0, 63, 64, 69):
+        np.testing.assert_allclose(got[b], D.window_variance(x[b].astype(np.float64), RADII[:4]), rtol=2e-5)

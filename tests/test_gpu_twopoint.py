@@ -96,3 +96,12 @@ def test_two_point_full_size_sampled(hf, dims):
         assert abs(float(s2[r]) - ref) < 2e-6, (r, float(s2[r]), ref)
     phi = float(I.mean())
     assert abs(float(s2.flat[0]) - phi) < 2e-6
+
+
+def test_two_point_batch_beyond_one_chunk(hf):
+    # 70 maps: two chunks of the 64-field launch limit
+    dims = (8, 16, 12)
+    g = np.stack([_random_map(dims, 0.3 + 0.005 * i, 100 + i) for i in range(70)])
+    s2 = hf.two_point(torch.from_numpy(g).cuda()).cpu().numpy()
+    for b in (0, 63, 64, 69):
+        np.testing.assert_allclose(s2[b], TP.s2_map(g[b]), rtol=0, atol=2e-6)

@@ -66,7 +66,7 @@ enum {
   HU_ERR_WORKSPACE = -4,  /* workspace smaller than hu_workspace_size */
   HU_ERR_DEGENERATE = -5, /* reserved: returned by host-side helpers for a filter with no lattice support */
   HU_ERR_HIP = -6,        /* a HIP runtime call failed */
-  HU_ERR_UNSUPPORTED = -7 /* valid request that this build does not implement */
+  HU_ERR_UNSUPPORTED = -7 /* valid request that the library does not implement */
 };
 
 enum { HU_F32 = 0, HU_I8 = 1 };

@@ -8,6 +8,10 @@
  *   -> inverse FFT to a real field                                     (Eq. (9))
  *   -> f <- sigma_f (f - <f>) / sqrt(Var f)                           (Eq. (15))
  *   -> sign map f -> +-1 and binned power spectra                      (Sec. II.B end, Sec. III figures)
+ * plus the adjoint of the binned spectrum with respect to the filter parameters, the
+ * hyperuniformity diagnostics of Sec. II.A (local variance over a spherical window, small-k
+ * exponent, class of Eqs. (6)-(7)), a level cut for a target volume fraction with the two-point
+ * function of the resulting phases, and the mask variants alpha = 0, alpha < 0 and an offset.
  *
  * Conventions used by every entry point
  * -------------------------------------

@@ -423,6 +423,11 @@ __device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[E], float2* 
 // ---------------------------------------------------------------------------------------------
 struct U4 { uint32_t x, y, z, w; };
 
+// a ^ b ^ c as one three-input bitwise instruction (truth table 0x96: odd parity of the inputs)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ U4 philox4x32_10(uint64_t block, uint64_t seed) {
   uint32_t c0 = (uint32_t)block, c1 = (uint32_t)(block >> 32), c2 = 0u, c3 = 0u;
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -431,7 +436,7 @@ __device__ __forceinline__ U4 philox4x32_10(uint64_t block, uint64_t seed) {
     // one 32x32 -> 64-bit product per multiplier (a single v_mad_u64_u32 each)
     const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
     const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0), n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -442,9 +447,11 @@ __device__ __forceinline__ U4 philox4x32_10(uint64_t block, uint64_t seed) {
   return U4{c0, c1, c2, c3};
 }
 
-// u = (2 (x >> 9) + 1) 2^-24: an odd multiple of 2^-24, exact in FP32
+// u = (2 (x >> 9) + 1) 2^-24: an odd multiple of 2^-24, exact in FP32.  Formed as
+// (1 + (x >> 9) 2^-23) - (1 - 2^-24): the first operand is the 23 bits under the exponent of 1,
+// and the difference is exact (the operands lie within a factor of two of each other).
 __device__ __forceinline__ float word_to_uniform(uint32_t x) {
-  return (float)((x >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
+  return __uint_as_float(0x3F800000u | (x >> 9)) - 0.999999940395355224609375f;
 }
 
 // Box-Muller on the hardware transcendentals: v_log_f32 (log2), v_sqrt_f32 and v_sin_f32 /

@@ -403,7 +403,7 @@ def kernel_family(name):
     if not m:
         return None
     k, args = m.group(1), [t.strip() for t in (m.group(2) or "").split(",")]
-    if k in ("k_finalize", "k_grad_coef", "k_grad_final", "k_cols_adjoint"):
+    if k in ("k_finalize", "k_count_final", "k_grad_coef", "k_grad_final", "k_cols_adjoint"):
         return k[2:]
     if k == "k_rows_r2c":
         return "rows_r2c_noise" if args[1] == "0" else "rows_r2c"

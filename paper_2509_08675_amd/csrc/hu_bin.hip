@@ -161,29 +161,42 @@ hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------------------------
 // standalone threshold: grid-stride over N values of each field
 // ---------------------------------------------------------------------------------------------
+constexpr int THR_UNROLL = 4;                 // 16-byte vectors per thread per step, loads first
+
 __global__ void __launch_bounds__(256) k_threshold(ThreshArgs a) {
   __shared__ unsigned red[2][4];
   const int b = blockIdx.y;
   const float* f = a.field + (long long)b * a.N;
   int8_t* t = a.out + (long long)b * a.N;
   unsigned np = 0, nn = 0;
-  // four voxels per step (N is a multiple of 4 on every supported grid): a 16-byte load, one
+  // four voxels per vector (N is a multiple of 4 on every supported grid): a 16-byte load, one
   // 4-byte store of the four signs
   const long long n4 = a.N >> 2;
   const float4* f4 = reinterpret_cast<const float4*>(f);
   uint32_t* t4 = reinterpret_cast<uint32_t*>(t);
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
-    const float4 x4 = f4[i];
-    const float xs[4] = {x4.x, x4.y, x4.z, x4.w};
-    uint32_t packed = 0;
+  const long long step = (long long)gridDim.x * 256 * THR_UNROLL;
+  for (long long i0 = (long long)blockIdx.x * 256 * THR_UNROLL + threadIdx.x; i0 < n4; i0 += step) {
+    float4 x4[THR_UNROLL];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool pos = xs[q] >= a.level;
-      packed |= (pos ? 0x01u : 0xFFu) << (8 * q);
-      np += pos;
-      nn += fabsf(xs[q] - a.level) < a.near_tol;
+    for (int u = 0; u < THR_UNROLL; ++u) {
+      const long long i = i0 + u * 256;
+      x4[u] = i < n4 ? f4[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    t4[i] = packed;
+#pragma unroll
+    for (int u = 0; u < THR_UNROLL; ++u) {
+      const long long i = i0 + u * 256;
+      if (i >= n4) break;
+      const float xs[4] = {x4[u].x, x4[u].y, x4[u].z, x4[u].w};
+      uint32_t packed = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool pos = xs[q] >= a.level;
+        packed |= (pos ? 0x01u : 0xFFu) << (8 * q);
+        np += pos;
+        nn += fabsf(xs[q] - a.level) < a.near_tol;
+      }
+      t4[i] = packed;
+    }
   }
   np = wave_usum(np);
   nn = wave_usum(nn);
@@ -199,8 +212,12 @@ __global__ void __launch_bounds__(256) k_threshold(ThreshArgs a) {
 
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st) {
   if (a.N % 4 != 0) return hipErrorInvalidValue;   // every supported grid has an even x and another even axis
-  long long blocks = (a.N / 4 + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (batch <= 0) return hipSuccess;
+  // about 1024 workgroups over the whole batch: enough loads in flight to stream at full rate,
+  // and few count atomics per field (they serialise on the counters' cache line)
+  long long blocks = (a.N / 4 + 256 * THR_UNROLL - 1) / (256 * THR_UNROLL);
+  const long long cap = 1024 / batch > 0 ? 1024 / batch : 1;
+  if (blocks > cap) blocks = cap;
   hipLaunchKernelGGL(k_threshold, dim3((unsigned)blocks, batch), dim3(256), 0, st, a);
   return hipGetLastError();
 }

@@ -326,6 +326,10 @@ Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan) {
     off += up256((size_t)batch * L.tiles * 4 * sizeof(double));
     L.fstats = off;
     off += up256((size_t)batch * 8 * sizeof(double));
+    // per-tile counts of the last row pass, for either row-tile width
+    const int rt0 = row_tiles(g.nx / 2, 0, g.nrows), rt1 = row_tiles(g.nx / 2, 1, g.nrows);
+    L.cpart = off;
+    off += up256((size_t)batch * (rt0 > rt1 ? rt0 : rt1) * 2 * sizeof(uint32_t));
   }
   L.total = off;
   return L;
@@ -562,7 +566,6 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     if (o.cont_cnt) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.cont_cnt), cnt_src, 2 * nb};
     if (o.pm1_sum) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_sum), nullptr, 2 * nb};
     if (o.pm1_cnt) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_cnt), cnt_src, 2 * nb};
-    if (o.counts) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.counts), nullptr, 4};
     ra.fill_spans = fs;
   }
   HU_HIP(timed("rows_r2c_noise", st, [&] { return launch_rows_r2c(Lrow, SRC_NOISE, r.plan.v[P_R2C], ra, B, st); }));
@@ -621,11 +624,17 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   if (!batch_mode) {
     za.field = o.field;
     za.pm1 = o.pm1;
-    za.counts = o.counts;
     za.near_tol = r.near_abs;
   }
+  const bool want_counts = r.thresh && (batch_mode || o.counts != nullptr);
+  uint32_t* cpart = reinterpret_cast<uint32_t*>(r.work + r.lay.cpart);
+  za.cpart = want_counts ? cpart : nullptr;
   HU_HIP(timed(r.thresh ? "rows_c2r_thresh" : "rows_c2r", st,
                [&] { return launch_rows_c2r(Lrow, r.thresh, r.plan.v[P_C2R], za, B, st); }));
+  if (want_counts) {
+    CountFinalArgs cf{cpart, row_tiles(Lrow, r.plan.v[P_C2R], g.nrows), batch_mode ? nullptr : o.counts, r.io};
+    HU_HIP(timed("count_final", st, [&] { return launch_count_final(cf, B, st); }));
+  }
 
   if (want_pm1) {
     if (g.nd == 3) HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st); }));

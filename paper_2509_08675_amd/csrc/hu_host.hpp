@@ -39,7 +39,7 @@ struct TunePlan {
 };
 
 struct Layout {
-  size_t spec, partials, fstats, total;
+  size_t spec, partials, fstats, cpart, total;
   int tiles;
 };
 

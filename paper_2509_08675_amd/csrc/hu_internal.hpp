@@ -141,8 +141,16 @@ struct RowsZArgs {
   const double* fstats;
   float* field;
   int8_t* pm1;
-  uint64_t* counts;
+  uint32_t* cpart;         // [B][row tiles][2]: n_pos, n_near of each tile (THRESH), or null
   float near_tol;          // absolute
+  const FieldIO* io;       // per-field outputs (batch path) or null
+};
+
+// per-field totals of the last row pass's per-tile counts
+struct CountFinalArgs {
+  const uint32_t* cpart;   // [B][ntiles][2]
+  int ntiles;
+  uint64_t* counts;        // [B][2] (plain path) or null
   const FieldIO* io;       // per-field outputs (batch path) or null
 };
 
@@ -249,6 +257,8 @@ hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream
 hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st);
 hipError_t launch_rows_c2r(int L, bool thresh, int variant, const RowsZArgs& a, int batch, hipStream_t st);
+int row_tiles(int L, int variant, long long nrows);
+hipError_t launch_count_final(const CountFinalArgs& a, int batch, hipStream_t st);
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st);
 hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st);
 // `group` tiles in a row per XCD (see ColSched)

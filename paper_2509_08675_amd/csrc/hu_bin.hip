@@ -38,7 +38,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
     pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = wm * (v[s].x * v[s].x + v[s].y * v[s].y);
   for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
   __syncthreads();
-  if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, g, p);
+  bin_tile<L, E, C, LP>(pw, hs, a.table, (int)tile * C, a.gm.ncol, tid);
   __syncthreads();
   double* out = a.io ? a.io[b].pm1_sum : field_ptr(a.sum, a.nb, b);
   if (out) hist_flush(hs, a.nb, 1.0 / (double)a.N, out, tid, T);
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin_keep(BinArgs a)
     ++lin;
     const int bn = lin / a.sc.ntiles, tn = lin - bn * a.sc.ntiles;
     if (lin < end) col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)bn * a.Nh, a.Nh, a.gm.inner0, tn * C + c, p));
-    if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, g, p);
+    bin_tile<L, E, C, LP>(pw, hs, a.table, tile * C, a.gm.ncol, tid);
     __syncthreads();
     if (lin == end || bn != b) {
       double* out = a.io ? a.io[b].pm1_sum : field_ptr(a.sum, a.nb, b);

@@ -198,30 +198,50 @@ template <int L, int E>
 __device__ __forceinline__ void bin_runs(const float* pw, double* hs, const uint16_t* __restrict__ table, int g, int p) {
   const int e0 = p * E;
   const uint16_t* t = table + (unsigned)(g * L + e0);
-  int cur = -1;
-  double acc = 0.0;
-  auto step = [&](int bin, int e) {
-    const double v = (double)pw[pw_index(e)];
-    if (bin != cur) {
-      if (cur >= 0) atomicAdd(hs + cur, acc);
-      cur = bin;
-      acc = 0.0;
-    }
-    acc += v;
-  };
+  // every bin and power value of the thread's E modes first, so all their loads are in flight
+  // together (the histogram atomics below share LDS with the power values and would otherwise
+  // order each read after the previous atomic)
+  int bin[E];
+  float v[E];
   if constexpr ((L % 8) == 0 && (E % 8) == 0) {
+    uint4 w[E / 8];
+#pragma unroll
+    for (int q = 0; q < E / 8; ++q) w[q] = *reinterpret_cast<const uint4*>(t + 8 * q);
 #pragma unroll
     for (int q = 0; q < E / 8; ++q) {
-      const uint4 w = *reinterpret_cast<const uint4*>(t + 8 * q);
-      const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+      const uint32_t ws[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
 #pragma unroll
-      for (int h = 0; h < 8; ++h) step((int)((ws[h >> 1] >> (16 * (h & 1))) & 0xFFFFu), e0 + 8 * q + h);
+      for (int h = 0; h < 8; ++h) bin[8 * q + h] = (int)((ws[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < E; ++i) step((int)t[i], e0 + i);
+    for (int i = 0; i < E; ++i) bin[i] = (int)t[i];
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = pw[pw_index(e0 + i)];
+  int cur = bin[0];
+  double acc = (double)v[0];
+#pragma unroll
+  for (int i = 1; i < E; ++i) {
+    if (bin[i] != cur) {
+      atomicAdd(hs + cur, acc);
+      cur = bin[i];
+      acc = 0.0;
+    }
+    acc += (double)v[i];
   }
   atomicAdd(hs + cur, acc);
+}
+
+// Binning of a tile's C columns from their power values in LDS.  Thread t walks segment t % P of
+// column t / P, so the lanes of one instruction span as few columns as possible: neighbouring
+// columns of a tile share most bins, and lanes of one LDS atomic that hit the same bin serialise.
+template <int L, int E, int C, int LP>
+__device__ __forceinline__ void bin_tile(const float* pw, double* hs, const uint16_t* __restrict__ table, int col0,
+                                         int ncol, int tid) {
+  constexpr int P = Plan<L>::P;
+  const int cb = tid / P, pb = tid - cb * P;
+  if (cb < C && col0 + cb < ncol) bin_runs<L, E>(pw + cb * LP, hs, table, col0 + cb, pb);
 }
 
 __device__ __forceinline__ void hist_flush(const double* hs, int nb, double scale, double* out_sum, int tid, int T) {

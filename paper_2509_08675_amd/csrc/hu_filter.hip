@@ -68,7 +68,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   // ---- continuous-spectrum histogram (run-length over contiguous modes of each column)
   __syncthreads();
   if (do_bins) {
-    if (valid) bin_runs<L, E>(pw + c * LP, hs, a.table, g, p);
+    bin_tile<L, E, C, LP>(pw, hs, a.table, (int)tile * C, a.gm.ncol, tid);
     __syncthreads();
     hist_flush(hs, a.nb, 1.0, cont_out, tid, T);
   }

@@ -286,6 +286,9 @@ __device__ __forceinline__ u32x4 buf_load4(rsrc_t r, unsigned voff, unsigned sof
 __device__ __forceinline__ void buf_store2(rsrc_t r, float2 v, unsigned voff, unsigned soff) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
+__device__ __forceinline__ void buf_store4(rsrc_t r, u32x4 v, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+}
 
 // Column g of a column pass over one field's half spectrum: element e sits at
 // (g / inner) L inner + g mod inner + e inner -- in 2D (column groups of four, inner = 4) element

@@ -393,20 +393,50 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   const bool row_ok = c < rows_here;
   const unsigned vox0 = (unsigned)(c * 2 * L + 2 * p);      // voxel of this thread's slot-0 element
   unsigned npos = 0, nnear = 0;
+  // STAGE: the rows of a wave are contiguous in the field and the sign map, so the wave writes its
+  // normalised values to its own LDS regions and stores them back in address order, 16 bytes of
+  // the field and 4 of the map per lane (rather than 2P-voxel pieces of 64 / P rows per store)
+  constexpr int NRW = 64 / P;                        // rows per wave
+  constexpr int NQW = NRW * 2 * L / 4;               // four-voxel groups per wave
+  constexpr bool STAGE = WV && NRW > 1 && (L % 2) == 0 && (NQW % 64) == 0 && (RS >= L);
 #pragma unroll
   for (int s = 0; s < E; ++s) {
     const unsigned so = 2u * (unsigned)slot_index<L, RL, P>(s, 0);
     const float x0 = fmaf(v[s].x, scale, offset);
     const float x1 = fmaf(v[s].y, scale, offset);
-    buf_store2(fo, make_float2(x0, x1), vox0 * 4u, so * 4u);
+    if constexpr (STAGE) lrow[slot_index<L, RL, P>(s, 0) + p] = make_float2(x0, x1);
+    else buf_store2(fo, make_float2(x0, x1), vox0 * 4u, so * 4u);
     if constexpr (THRESH) {
       const bool p0 = x0 >= 0.0f, p1 = x1 >= 0.0f;
       npos += (unsigned)p0 + (unsigned)p1;
       nnear += (unsigned)(fabsf(x0) < near_tol) + (unsigned)(fabsf(x1) < near_tol);
-      const unsigned b0 = p0 ? 0x01u : 0xFFu, b1 = p1 ? 0x0100u : 0xFF00u;
-      __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(b0 | b1), to, vox0, so, 0);
+      if constexpr (!STAGE) {
+        const unsigned b0 = p0 ? 0x01u : 0xFFu, b1 = p1 ? 0x0100u : 0xFF00u;
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(b0 | b1), to, vox0, so, 0);
+      }
       v[s] = make_float2(p0 ? 1.0f : -1.0f, p1 ? 1.0f : -1.0f);
     }
+  }
+  if constexpr (STAGE) {
+    xchg_sync<WV>();
+    const int lane = tid & 63;
+    const int cw = (tid >> 6) * NRW;                 // first tile row of this wave
+    const float2* lw = lds + cw * RS;
+#pragma unroll
+    for (int k = 0; k < NQW / 64; ++k) {
+      const int q = lane + 64 * k;                   // four-voxel group q of the wave's rows
+      const int j = (4 * q) / (2 * L), x = 4 * q - j * (2 * L);
+      const float2 a0 = lw[j * RS + x / 2], a1 = lw[j * RS + x / 2 + 1];
+      const unsigned vox = (unsigned)(cw * 2 * L + 4 * q);
+      buf_store4(fo, u32x4{__float_as_uint(a0.x), __float_as_uint(a0.y), __float_as_uint(a1.x), __float_as_uint(a1.y)},
+                 vox * 4u, 0u);
+      if constexpr (THRESH) {
+        const unsigned packed = (a0.x >= 0.0f ? 0x01u : 0xFFu) | (a0.y >= 0.0f ? 0x0100u : 0xFF00u) |
+                                (a1.x >= 0.0f ? 0x010000u : 0xFF0000u) | (a1.y >= 0.0f ? 0x01000000u : 0xFF000000u);
+        __builtin_amdgcn_raw_buffer_store_b32(packed, to, vox, 0u, 0);
+      }
+    }
+    xchg_sync<WV>();                                 // the regions are the next transform's exchange buffer
   }
   if constexpr (THRESH) {
     if (!row_ok) npos = nnear = 0;

@@ -72,6 +72,11 @@ PIPE_CASES = [
     ("3d_12x24x32_rot", (12, 24, 32), _filt(p=2.5, semi=(2, 1, 1.5), rot=0.7, alpha=4, k0=0.3, width=0.1), (20, 1), [7]),
     ("3d_64cube", (64, 64, 64), W.C3["filt"], (128, 1), [1]),
     ("3d_96x48x24", (96, 48, 24), _filt(p=4, semi=(1, 1.5, 2), rot=0.3, alpha=2, k0=0.2, width=0.06), (64, 1), [11]),
+    # row tiles with a ragged tail: 256-voxel rows (eight rows per wave, stores staged through LDS)
+    # and 2048-voxel rows (one row per wave)
+    ("3d_6x12x256_ragged", (6, 12, 256), _filt(p=3, semi=(1, 2, 1.5), rot=0.2, alpha=2, k0=0.2, width=0.05), (32, 1),
+     [8, 9]),
+    ("2d_6x2048_ragged", (6, 2048), _filt(p=2, semi=(2, 1), rot=0.4, alpha=4, k0=0.2, width=0.05), (40, 6), [10]),
     # mask variants: alpha = 0 (standard nonhyperuniform) and the offset regularisation
     ("2d_64x96_alpha0", (64, 96), _filt(p=3, semi=(2, 1), rot=0.3, alpha=0, k0=0.15, width=0.05), (24, 6), [2]),
     ("2d_128x64_offset", (128, 64), _filt(p=4, semi=(1, 2), rot=0.5, alpha=4, k0=0.2, width=0.04, offset=1e-3),
@@ -109,6 +114,9 @@ def _compare_pipeline(hf, name, dims, filt, bins, seeds):
         flips = int(np.sum(diff))
         cnt = hf.u64_view(bufs.counts[i])
         assert abs(int(cnt[0]) - ref["n_pos"]) <= flips
+        # n_near (|f| < 1e-5 sigma_f): exact up to the sites within the field tolerance of the edge
+        edge = int(np.sum(np.abs(np.abs(ref["f"]) - 1e-5 * fp.sigma_f) <= 2e-5 * rms))
+        assert abs(int(cnt[1]) - ref["n_near"]) <= edge, (int(cnt[1]), ref["n_near"], edge)
         # continuous spectrum
         cs = bufs.cont_sum[i].cpu().numpy()
         cc = hf.u64_view(bufs.cont_cnt[i])

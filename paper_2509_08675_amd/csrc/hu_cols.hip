@@ -35,6 +35,7 @@ static ColSched col_sched_L(long long ncol, int batch, int group) {
   s.G = group > 0 ? group : 1;
   s.ntiles_pad = (s.ntiles + s.G - 1) / s.G * s.G;
   s.batch = batch;
+  s.finner = 0;
   return s;
 }
 
@@ -44,8 +45,20 @@ ColSched col_sched(int L, int variant, long long ncol, int batch, int group) {
   case LL: return variant ? col_sched_L<LL, 1>(ncol, batch, group) : col_sched_L<LL, 0>(ncol, batch, group);
     HU_COL_LENGTHS(X)
 #undef X
-    default: return ColSched{0, 0, 1, 0};
+    default: return ColSched{0, 0, 1, 0, 0};
   }
+}
+
+// The B fields of a tile get consecutive ids on one XCD, so a per-geometry table slice read by the
+// tile (the bin indices of its modes) is fetched into that XCD's L2 once for all the fields.
+ColSched col_sched_fields(int L, int variant, long long ncol, int batch) {
+  ColSched s = col_sched(L, variant, ncol, batch, 1);
+  if (batch > 1) {
+    s.G = batch;
+    s.ntiles_pad = s.ntiles;
+    s.finner = 1;
+  }
+  return s;
 }
 
 int col_tiles(int L, int variant, long long ncol) { return col_sched(L, variant, ncol, 1).ntiles; }

@@ -102,6 +102,11 @@ __device__ __forceinline__ bool map_tile(const ColSched& s, int& b, long long& t
   const unsigned xcd = id & 7u, round = id >> 3;
   const unsigned j = round % (unsigned)s.G;
   const long long grp = (long long)(round / (unsigned)s.G) * 8 + xcd;
+  if (s.finner) {                                 // G = batch: group grp is tile grp, j its field
+    b = (int)j;
+    tile = grp;
+    return tile < s.ntiles;
+  }
   const long long lin = grp * s.G + j;
   b = (int)(lin / s.ntiles_pad);
   tile = lin % s.ntiles_pad;

@@ -586,7 +586,10 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fa.Nh = g.Nhp;
   fa.N = g.N;
   fa.gm = axis0(g);
-  fa.sc = col_sched(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B);
+  // 2D: the fields of a tile share its slice of the bin table in one XCD's L2 (the 2D binning
+  // pass 111 -> 103 us at 16 x 2048^2); 3D fields, 67 MB apart at 256^3, ran 3 % slower that way
+  fa.sc = g.nd == 2 ? col_sched_fields(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B)
+                    : col_sched(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B);
   if (!batch_mode) fa.filt = filt_dev(r.filt, g);
   fa.io = r.io;
   fa.bd = bd;
@@ -643,7 +646,8 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     ba.Nh = g.Nhp;
     ba.N = g.N;
     ba.gm = axis0(g);
-    ba.sc = col_sched(g.n[0], r.plan.v[P_BIN], ba.gm.ncol, B);
+    ba.sc = g.nd == 2 ? col_sched_fields(g.n[0], r.plan.v[P_BIN], ba.gm.ncol, B)
+                      : col_sched(g.n[0], r.plan.v[P_BIN], ba.gm.ncol, B);
     ba.bd = bd;
     ba.nb = nb;
     ba.table = geo.table;

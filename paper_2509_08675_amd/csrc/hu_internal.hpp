@@ -44,6 +44,7 @@ struct FillSpan {
 // 128-byte line), for `batch` fields; grid = ceil(batch * ntiles_pad / (8 G)) * 8 G workgroups.
 struct ColSched {
   int ntiles, ntiles_pad, G, batch;
+  int finner;              // 1: the fields of one tile are consecutive (G = batch, same XCD)
 };
 
 struct RowsArgs {
@@ -263,6 +264,7 @@ hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st);
 hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st);
 // `group` tiles in a row per XCD (see ColSched)
 ColSched col_sched(int L, int variant, long long ncol, int batch, int group = 1);
+ColSched col_sched_fields(int L, int variant, long long ncol, int batch);
 // tile group of the 3D y passes: their columns run over x rows of n_x / 2 + 1 complex values,
 // which do not start on 128-byte lines, so neighbouring tiles share lines
 constexpr int Y_PASS_GROUP = 8;

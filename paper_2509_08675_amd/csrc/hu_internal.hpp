@@ -267,7 +267,7 @@ ColSched col_sched(int L, int variant, long long ncol, int batch, int group = 1)
 ColSched col_sched_fields(int L, int variant, long long ncol, int batch);
 // tile group of the 3D y passes: their columns run over x rows of n_x / 2 + 1 complex values,
 // which do not start on 128-byte lines, so neighbouring tiles share lines
-constexpr int Y_PASS_GROUP = 8;
+constexpr int Y_PASS_GROUP = 16;
 hipError_t launch_zero_u64(uint64_t* p, long long n, hipStream_t st);
 hipError_t launch_debug_philox(uint64_t seed, uint64_t first, uint64_t count, uint32_t* words, float* normals,
                                hipStream_t st);

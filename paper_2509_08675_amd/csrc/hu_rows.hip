@@ -87,6 +87,41 @@ __device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, 
   using W = RowWalk<L, C, T, TILED>;
   using TS = TwistSplit<L, C, T, TILED>;
   constexpr bool SPLIT = FACT && TS::ok;
+  if constexpr (SPLIT && W::STEADY && (L % 4) == 0) {
+    // 2D: each lane forms the pair X[k], X[k + 1] (k even) of one row and stores it as 16 bytes;
+    // k = kt + KI2 it, so the twist factors are tw2[kt] tw2[KI2 it] and tw2[kt + 1] tw2[KI2 it]
+    constexpr int GP = W::GS / 2, QP = T / GP, IT2 = (W::NG + QP - 1) / QP, KI2 = 4 * QP;
+    const int w = tid % GP;
+    const int cc = w >> 1, kl = 2 * (w & 1);
+    const int kt = 4 * (tid / GP) + kl;
+    const float2 wa = buf_load2(tw2, (unsigned)(kt < L ? kt : 0) * 8u, 0);
+    const float2 wb = buf_load2(tw2, (unsigned)(kt + 1 < L ? kt + 1 : 0) * 8u, 0);
+    const float2* lz = lds + cc * RS;
+    auto twist = [&](int k, float2 tw) {
+      const float2 zk = lz[lidx(k)];
+      const float2 zm = cconj(lz[lidx(k == 0 ? 0 : L - k)]);
+      const float2 A = cadd(zk, zm), B = csub(zk, zm);
+      return cscale(cadd(A, mul_mi<false>(cmul(tw, B))), 0.5f);
+    };
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int q = tid / GP + it * QP;
+      const int k = 4 * q + kl;
+      if (!(q < W::NG && cc < rows_here) || k > L) continue;
+      const unsigned off = (tile_off + (unsigned)q * run_stride + 2u * w) * 8u;
+      if (k == L) {
+        const float2 z0 = lz[0];
+        buf_store2(spec, make_float2(z0.x - z0.y, 0.0f), off, 0);
+        continue;
+      }
+      const float2 tu = (KI2 * it < L) ? uniform_load2(tw2p, KI2 * it) : make_float2(1.0f, 0.0f);
+      const float2 X0 = twist(k, (KI2 * it < L) ? cmul(wa, tu) : wa);
+      const float2 X1 = twist(k + 1, (KI2 * it < L) ? cmul(wb, tu) : wb);
+      buf_store4(spec, u32x4{__float_as_uint(X0.x), __float_as_uint(X0.y), __float_as_uint(X1.x), __float_as_uint(X1.y)},
+                 off, 0);
+    }
+    return;
+  }
   constexpr int NW = SPLIT ? 1 : W::ITERS;
   float2 w[NW];
   if constexpr (SPLIT) {
@@ -134,6 +169,34 @@ template <int L, int C, int T, bool TILED, int RS>
 __device__ __forceinline__ void load_rows(float2* lds, rsrc_t spec, unsigned tile_off, unsigned run_stride,
                                           int rows_here, int tid) {
   using W = RowWalk<L, C, T, TILED>;
+  if constexpr (W::STEADY && (L % 4) == 0) {
+    // 2D: 16-byte loads, each the pair k, k + 1 (k even) of one row inside a run of the tile
+    constexpr int GP = W::GS / 2;                  // pairs per run
+    constexpr int QP = T / GP;                     // runs per sweep
+    constexpr int IT2 = (W::NG + QP - 1) / QP;
+    const int w = tid % GP;
+    const int cc = w >> 1, kl = 2 * (w & 1);       // row and k & 3 of the pair's first element
+    u32x4 x[IT2];
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int q = tid / GP + it * QP;
+      const bool in = q < W::NG && cc < rows_here;
+      x[it] = buf_load4(spec, in ? (tile_off + (unsigned)q * run_stride + 2u * w) * 8u : 0xFFFFFFF0u, 0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int q = tid / GP + it * QP;
+      if (!(q < W::NG && cc < rows_here)) continue;
+      const int k = 4 * q + kl;                    // k + 1 is odd, so never L
+      if (k > L) continue;
+      float2 v0 = make_float2(__uint_as_float(x[it].x), __uint_as_float(x[it].y));
+      const float2 v1 = make_float2(__uint_as_float(x[it].z), __uint_as_float(x[it].w));
+      if (k == 0 || k == L) v0.y = 0.0f;
+      lds[cc * RS + lidx(k)] = v0;
+      if (k < L) lds[cc * RS + lidx(k + 1)] = v1;
+    }
+    return;
+  }
   float2 x[W::ITERS];
 #pragma unroll
   for (int it = 0; it < W::ITERS; ++it) {

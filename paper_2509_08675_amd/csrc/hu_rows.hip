@@ -87,15 +87,24 @@ __device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, 
   using W = RowWalk<L, C, T, TILED>;
   using TS = TwistSplit<L, C, T, TILED>;
   constexpr bool SPLIT = FACT && TS::ok;
-  if constexpr (SPLIT && W::STEADY && (L % 4) == 0) {
-    // 2D: each lane forms the pair X[k], X[k + 1] (k even) of one row and stores it as 16 bytes;
-    // k = kt + KI2 it, so the twist factors are tw2[kt] tw2[KI2 it] and tw2[kt + 1] tw2[KI2 it]
+  if constexpr (W::STEADY && (L % 4) == 0) {
+    // 2D: each lane forms the pair X[k], X[k + 1] (k even) of one row and stores it as 16 bytes.
+    // FACT: k = kt + KI2 it, so the twist factors are tw2[kt] tw2[KI2 it] and tw2[kt + 1]
+    // tw2[KI2 it]; otherwise the pair tw2[k], tw2[k + 1] is loaded for every step (all first)
     constexpr int GP = W::GS / 2, QP = T / GP, IT2 = (W::NG + QP - 1) / QP, KI2 = 4 * QP;
     const int w = tid % GP;
     const int cc = w >> 1, kl = 2 * (w & 1);
     const int kt = 4 * (tid / GP) + kl;
     const float2 wa = buf_load2(tw2, (unsigned)(kt < L ? kt : 0) * 8u, 0);
     const float2 wb = buf_load2(tw2, (unsigned)(kt + 1 < L ? kt + 1 : 0) * 8u, 0);
+    u32x4 tp[FACT ? 1 : IT2];
+    if constexpr (!FACT) {
+#pragma unroll
+      for (int it = 0; it < IT2; ++it) {
+        const int k = kt + KI2 * it;
+        tp[it] = buf_load4(tw2, (unsigned)(k + 1 < L ? k : 0) * 8u, 0);
+      }
+    }
     const float2* lz = lds + cc * RS;
     auto twist = [&](int k, float2 tw) {
       const float2 zk = lz[lidx(k)];
@@ -114,9 +123,17 @@ __device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, 
         buf_store2(spec, make_float2(z0.x - z0.y, 0.0f), off, 0);
         continue;
       }
-      const float2 tu = (KI2 * it < L) ? uniform_load2(tw2p, KI2 * it) : make_float2(1.0f, 0.0f);
-      const float2 X0 = twist(k, (KI2 * it < L) ? cmul(wa, tu) : wa);
-      const float2 X1 = twist(k + 1, (KI2 * it < L) ? cmul(wb, tu) : wb);
+      float2 ta, tb;
+      if constexpr (FACT) {
+        const float2 tu = (KI2 * it < L) ? uniform_load2(tw2p, KI2 * it) : make_float2(1.0f, 0.0f);
+        ta = (KI2 * it < L) ? cmul(wa, tu) : wa;
+        tb = (KI2 * it < L) ? cmul(wb, tu) : wb;
+      } else {
+        ta = make_float2(__uint_as_float(tp[it].x), __uint_as_float(tp[it].y));
+        tb = make_float2(__uint_as_float(tp[it].z), __uint_as_float(tp[it].w));
+      }
+      const float2 X0 = twist(k, ta);
+      const float2 X1 = twist(k + 1, tb);
       buf_store4(spec, u32x4{__float_as_uint(X0.x), __float_as_uint(X0.y), __float_as_uint(X1.x), __float_as_uint(X1.y)},
                  off, 0);
     }

@@ -479,6 +479,22 @@ def summarize_profiles(d):
                 continue                # the harness's own small torch kernels
             md.append("| `%s` | %s | %s | %.2f | %s |" % (r["Name"].replace("|", "/")[:90], kernel_family(r["Name"]),
                                                         r["Calls"], float(r["AverageNs"]) / 1e3, r["Percentage"]))
+        # per-launch durations from the dispatch trace; the last `last` launches of each family are
+        # the loop that the bench times with HIP events (the earlier ones are warm-up and the
+        # untimed steps)
+        last = 10 if cfg is C5 else 20
+        per = {}
+        for r in _csv_rows(os.path.join(wd, "trace"), "_kernel_trace.csv"):
+            f = kernel_family(r["Kernel_Name"])
+            if f:
+                per.setdefault(f, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+        md += ["", "### Per-launch durations (`--kernel-trace` dispatch records)", "",
+               "| family | launches | mean us, all | mean us, last %d (the event-timed loop) |" % last,
+               "|---|---|---|---|"]
+        for f in sorted(per):
+            v = per[f]
+            tail = v[-last:]
+            md.append("| %s | %d | %.2f | %.2f |" % (f, len(v), sum(v) / len(v), sum(tail) / len(tail)))
         fe = _per_dispatch(os.path.join(wd, "fetch"), "FETCH_SIZE")
         wr = _per_dispatch(os.path.join(wd, "write"), "WRITE_SIZE")
         md += ["", "### HBM traffic per launch (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`, calibrated)", "",

@@ -105,11 +105,17 @@ def field_bytes_min(dims):
 
 
 def kernel_source_hash():
+    """Hash of the code of the pipeline's kernel sources: line comments and blank lines are left
+    out, so an edit of the documentation does not disown counters taken on the same code."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2509_08675_amd", "csrc")
     for f in PIPELINE_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*$", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -4,8 +4,9 @@
 //              transform of each x row: an n_x/2-point complex FFT of the packed samples
 //              x[2n] + i x[2n+1] followed by the split twist;
 //   rows_c2r   inverse of that for each x row, then the normalisation of Eq. (15) with the
-//              statistics of the filter pass, the FP32 field and the +-1 sign map with counts
-//              (stored straight from the transform's registers), and the real-to-complex
+//              statistics of the filter pass, the FP32 field and the +-1 sign map (stored from
+//              the transform's registers, or through the wave's LDS regions in address order
+//              when a wave holds several rows) with per-tile counts, and the real-to-complex
 //              transform of the +-1 row written back in place.
 //
 // Half-spectrum layout seen by the row passes: element k of row r sits at
@@ -16,7 +17,7 @@
 // lines), and in 3D one contiguous run of C (L + 1) elements.  Global loads and stores walk these
 // runs in address order through buffer descriptors, decoupled from the FFT's thread mapping by
 // LDS; the walk advances by constant steps, so no per-element division or 64-bit address is
-// formed.
+// formed.  In 2D a lane moves the pair k, k + 1 (k even) of one row as one 16-byte access.
 #include "hu_common.hpp"
 
 namespace hu {
@@ -447,9 +448,10 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   constexpr bool WV = (64 % P) == 0;             // each row inside one wave
   fft_run<L, P, E, true, WV>(Rad{}, v, lrow, p, a.tw);
 
-  // ---- normalise (Eq. (15)) in registers.  The field and the sign map go out straight from the
-  //      slots: in slot s the P threads of a row hold P consecutive complex elements, i.e. 2P
-  //      consecutive voxels, so each store instruction writes contiguous memory.
+  // ---- normalise (Eq. (15)) in registers.  With one row per wave the field and the sign map go
+  //      out straight from the slots: in slot s the P threads of a row hold P consecutive complex
+  //      elements, i.e. 2P consecutive voxels, so each store instruction writes contiguous memory
+  //      (with several rows per wave, see STAGE below).
   const double* fs = a.fstats + (long long)b * 8;
   const float scale = (float)fs[4], offset = (float)fs[5];
   float* fout;

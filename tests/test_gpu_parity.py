@@ -77,6 +77,9 @@ PIPE_CASES = [
     ("3d_6x12x256_ragged", (6, 12, 256), _filt(p=3, semi=(1, 2, 1.5), rot=0.2, alpha=2, k0=0.2, width=0.05), (32, 1),
      [8, 9]),
     ("2d_6x2048_ragged", (6, 2048), _filt(p=2, semi=(2, 1), rot=0.4, alpha=4, k0=0.2, width=0.05), (40, 6), [10]),
+    # rows of 3 * 2^k voxels on the 16-byte row path (transforms of 96 and 192 complex points)
+    ("2d_48x192_radix3", (48, 192), _filt(p=3, semi=(1, 2), rot=0.8, alpha=2, k0=0.25, width=0.05), (24, 12), [12]),
+    ("2d_24x384_radix3", (24, 384), _filt(p=5, semi=(2, 1), rot=0.2, alpha=4, k0=0.2, width=0.04), (32, 6), [13]),
     # mask variants: alpha = 0 (standard nonhyperuniform) and the offset regularisation
     ("2d_64x96_alpha0", (64, 96), _filt(p=3, semi=(2, 1), rot=0.3, alpha=0, k0=0.15, width=0.05), (24, 6), [2]),
     ("2d_128x64_offset", (128, 64), _filt(p=4, semi=(1, 2), rot=0.5, alpha=4, k0=0.2, width=0.04, offset=1e-3),

@@ -158,16 +158,18 @@ struct AdjLds {
 
 // per-mode accumulation: one evaluation of H, or the mean of two on a Nyquist plane of a rotated
 // filter (H_sym, differentiated term by term); cb = w_m omega 2 |W|^2
-__device__ __forceinline__ void adj_acc(double (&acc)[7], float cb, const LnhOut& o) {
+// a mode's seven terms into the thread's FP32 partials of one tile (its E modes); the partials go
+// into the FP64 sums once per tile
+__device__ __forceinline__ void adj_acc(float (&acc)[7], float cb, const LnhOut& o) {
   const float wt = cb * o.H * o.H;
 #pragma unroll
-  for (int j = 0; j < 7; ++j) acc[j] += (double)(wt * o.r[j]);
+  for (int j = 0; j < 7; ++j) acc[j] = fmaf(wt, o.r[j], acc[j]);
 }
-__device__ __forceinline__ void adj_acc2(double (&acc)[7], float cb, const LnhOut& o1, const LnhOut& o2) {
+__device__ __forceinline__ void adj_acc2(float (&acc)[7], float cb, const LnhOut& o1, const LnhOut& o2) {
   const float hs = 0.5f * (o1.H + o2.H);
   const float w1 = 0.5f * cb * hs * o1.H, w2 = 0.5f * cb * hs * o2.H;
 #pragma unroll
-  for (int j = 0; j < 7; ++j) acc[j] += (double)fmaf(w1, o1.r[j], w2 * o2.r[j]);
+  for (int j = 0; j < 7; ++j) acc[j] += fmaf(w1, o1.r[j], w2 * o2.r[j]);
 }
 
 // Persistent over tiles (tile = blockIdx.x + k gridDim.x, a fixed assignment, so the sums are
@@ -222,6 +224,7 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
     if (tile + (int)gridDim.x < a.ntiles)
       col_load<L, R1, P, E>(v, col_io<L>(a.spec, a.Nh, a.gm.inner0, (tile + (int)gridDim.x) * C + c, p));
     if (g < a.gm.ncol) {
+      float pa[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       const ColCoord cc = col_coord(a.gm, g);
       const double gamma = cf[a.nb];
       const float* pc = pw + c * PS;
@@ -242,9 +245,9 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
           if (partner) {
             LnhOut o2;
             lnh3(f, c2, kz, o2);
-            adj_acc2(acc, cb, o1, o2);
+            adj_acc2(pa, cb, o1, o2);
           } else {
-            adj_acc(acc, cb, o1);
+            adj_acc(pa, cb, o1);
           }
         }
       } else {
@@ -258,12 +261,14 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
           if (f.rotated && (cc.nyq_x || 2 * e == n0)) {
             LnhOut o2;
             lnh2(f, cc.nyq_x ? -kx : kx, 2 * e == n0 ? -ky : ky, o2);
-            adj_acc2(acc, cb, o1, o2);
+            adj_acc2(pa, cb, o1, o2);
           } else {
-            adj_acc(acc, cb, o1);
+            adj_acc(pa, cb, o1);
           }
         }
       }
+#pragma unroll
+      for (int j = 0; j < 7; ++j) acc[j] += (double)pa[j];
     }
     __syncthreads();
   }

@@ -88,7 +88,7 @@ __device__ __forceinline__ void twist_store_rows(const float2* lds, rsrc_t tw2, 
   using W = RowWalk<L, C, T, TILED>;
   using TS = TwistSplit<L, C, T, TILED>;
   constexpr bool SPLIT = FACT && TS::ok;
-  if constexpr (W::STEADY && (L % 4) == 0) {
+  if constexpr (W::STEADY && (L % 4) == 0 && Plan<L>::E == 16) {
     // 2D: each lane forms the pair X[k], X[k + 1] (k even) of one row and stores it as 16 bytes.
     // FACT: k = kt + KI2 it, so the twist factors are tw2[kt] tw2[KI2 it] and tw2[kt + 1]
     // tw2[KI2 it]; otherwise the pair tw2[k], tw2[k + 1] is loaded for every step (all first)
@@ -187,7 +187,7 @@ template <int L, int C, int T, bool TILED, int RS>
 __device__ __forceinline__ void load_rows(float2* lds, rsrc_t spec, unsigned tile_off, unsigned run_stride,
                                           int rows_here, int tid) {
   using W = RowWalk<L, C, T, TILED>;
-  if constexpr (W::STEADY && (L % 4) == 0) {
+  if constexpr (W::STEADY && (L % 4) == 0 && Plan<L>::E == 16) {
     // 2D: 16-byte loads, each the pair k, k + 1 (k even) of one row inside a run of the tile
     constexpr int GP = W::GS / 2;                  // pairs per run
     constexpr int QP = T / GP;                     // runs per sweep

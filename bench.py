@@ -182,6 +182,22 @@ def roofline_obj(cfg, prof, steps, workload):
                          for k, v in prof.items()}), total
 
 
+def time_mask_variants(hf, torch, cfg, steps):
+    """The whole pipeline on the workload's fields with the mask variants: an antihyperuniform
+    filter (alpha = -1) and the offset regularisation (1e-3) on the workload's filter."""
+    out = {}
+    _, total = algorithmic_bytes(cfg["dims"], len(cfg["seeds"]))
+    vox = len(cfg["seeds"]) * math.prod(cfg["dims"])
+    for name, change in (("alpha_-1", dict(alpha=-1.0)), ("offset_1e-3", dict(offset=1e-3))):
+        c = dict(cfg)
+        c["filt"] = dict(cfg["filt"], **change)
+        el, _ = time_pipeline(hf, torch, c, steps, 2)
+        ms = el / steps * 1e3
+        out[name] = dict(filter_change=change, ms_per_step=round(ms, 4), value=round(vox / (ms * 1e-3), 1),
+                         pipeline_roofline_frac=round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    return out
+
+
 def time_uneven_batch(hf, torch, steps, warmup):
     """The uneven batch of 512 fields (448 2D, 64 3D) through hu_pipeline_batch (one replayed
     graph), after autotuning every shape class; and the plain form, one hu_pipeline call per
@@ -620,6 +636,7 @@ def main():
         line["also"]["window_variance_256cube_x4_8radii"] = time_window_variance(hf, torch, C3, max(args.steps // 5, 5))
         line["also"]["level_cut_and_two_point_2048sq_x16"] = time_two_point(hf, torch, C2, max(args.steps // 5, 5))
         line["also"]["level_cut_and_two_point_256cube_x4"] = time_two_point(hf, torch, C3, max(args.steps // 5, 5))
+        line["also"]["mask_variants_2048sq_x16"] = time_mask_variants(hf, torch, C2, max(args.steps // 5, 5))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(line), flush=True)

@@ -100,6 +100,17 @@ typedef struct hu_filter {
   double offset;   /* offset regularisation >= 0 added to the peak-normalised spectral density on
                       every mode but the DC (chi(k -> 0) = offset); 0 is the paper's mask;
                       HU_ERR_UNSUPPORTED together with alpha < 0 */
+  /* Optional tabulated radial form (a radial profile beyond Eq. (13), the generalisation named in
+   * Sec. IV): when prof_n > 0, ln chi at superellipse norm K is the linear interpolation of the
+   * prof_n >= 2 samples prof[i] = ln chi(i * prof_dk) (device memory, FP32, caller-owned, 4-byte
+   * aligned; held at the last sample beyond K = (prof_n - 1) prof_dk) in place of
+   * alpha ln K - (K - k0)^2 / (2 w^2).  The samples are used as given (an added constant does not
+   * change the normalised field, but their lattice maximum must be >= -80); alpha, k0 and width
+   * are then unused, offset must be 0 (else HU_ERR_UNSUPPORTED), the DC mode keeps amplitude 0,
+   * and hu_spectrum_grad returns HU_ERR_UNSUPPORTED.  prof_n = 0: Eq. (13). */
+  const float* prof;
+  int32_t prof_n;
+  double prof_dk;  /* sample spacing in K, > 0 when prof_n > 0 */
 } hu_filter;
 
 typedef struct hu_bins {
@@ -223,8 +234,9 @@ int hu_hyperuniformity_class(double alpha, int32_t d, double tol);
  * P_b = cont_sum_b / cont_cnt_b (the corner slot R*A and empty bins are ignored); all device.
  * Writes grad [7] = dL/d(a, b, c, p, rot, k0, w) (device FP64; the c entry is 0 in 2D).  The
  * noise spectrum is regenerated from the seed (nothing of the forward field is read), and the
- * seven sums are FP64, reduced in a fixed order (bit-reproducible).  HU_ERR_UNSUPPORTED for a filter
- * with a nonzero offset (only the amplitude sqrt(chi) is differentiated).
+ * seven sums are FP64 across tiles, reduced in a fixed order (bit-reproducible).  HU_ERR_UNSUPPORTED
+ * for a filter with a nonzero offset or a tabulated radial form (only the amplitude sqrt(chi) of
+ * Eq. (13) is differentiated).
  * Workspace: hu_workspace_size(HU_OP_LOSS, dims, 1, &bins, ...). */
 int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins bins, const double* dL_dP,
                      const double* cont_sum, const uint64_t* cont_cnt, const double* stats, double* grad,

@@ -13,6 +13,11 @@ chi diverging as k -> 0; the continuum then has no maximum, so C is fixed by the
 relative to the continuum peak; alpha >= 0 only), which makes chi(k -> 0) = offset.  The DC mode
 gets amplitude 0 for every alpha and offset: Eq. (15) removes the mean anyway.
 
+A tabulated radial form (a radial profile beyond Eq. (13); Sec. IV names more elaborate radial
+forms as the natural generalisation): ``prof`` holds ln chi at K = i * prof_dk, i = 0 .. n - 1,
+and ln chi(K) is its linear interpolation, held at the last sample for K beyond the table; the
+samples are used as given (no normalisation constant; the field is normalised by Eq. (15)).
+
 Readings where the paper is silent or ambiguous (each is listed in the design notes):
 * wavenumbers are in units of the Nyquist wavenumber: kappa_i = 2 m~_i / n_i with m~ the
   signed index (m for m < n/2, else m - n), except along the halved last axis of the
@@ -51,6 +56,7 @@ class FilterParams:
     width  Gaussian band width w (sigma of Eq. (13)) in Nyquist units
     sigma_f target standard deviation of the field (Eq. (15))
     offset regularisation added to chi_rel (>= 0; 0 is the paper's mask)
+    prof   tabulated radial form: ln chi at K = i * prof_dk (replaces alpha, k0, width), or None
     """
     p: float
     semi: tuple = (1.0, 1.0, 1.0)
@@ -60,10 +66,13 @@ class FilterParams:
     width: float = 0.1
     sigma_f: float = 1.0
     offset: float = 0.0
+    prof: tuple = None      # tabulated ln chi at K = i * prof_dk, or None for Eq. (13)
+    prof_dk: float = 0.0
 
     def replace(self, **kw):
         d = dict(p=self.p, semi=tuple(self.semi), rot=self.rot, alpha=self.alpha,
-                 k0=self.k0, width=self.width, sigma_f=self.sigma_f, offset=self.offset)
+                 k0=self.k0, width=self.width, sigma_f=self.sigma_f, offset=self.offset,
+                 prof=self.prof, prof_dk=self.prof_dk)
         d.update(kw)
         d["semi"] = tuple(float(s) for s in d["semi"]) + (1.0,) * (3 - len(d["semi"]))
         return FilterParams(**d)
@@ -167,7 +176,11 @@ def ln_chi_unnorm(K, filt):
 
 
 def ln_chi_rel(K, filt, kappas=None):
-    """ln chi - ln chi_ref, i.e. ln chi of Eq. (13) with C = 1/chi_ref (max chi = 1 for alpha >= 0)."""
+    """ln chi - ln chi_ref, i.e. ln chi of Eq. (13) with C = 1/chi_ref (max chi = 1 for alpha >= 0);
+    for a tabulated radial form, the interpolated samples as given."""
+    if filt.prof is not None:
+        prof = np.asarray(filt.prof, dtype=np.float64)
+        return np.interp(K, filt.prof_dk * np.arange(prof.size), prof)
     return ln_chi_unnorm(K, filt) - ln_chi_ref(filt, kappas)
 
 

@@ -427,7 +427,7 @@ __global__ void __launch_bounds__(FS_THREADS) k_filter_spectrum(FilterSpecArgs a
       const int e = (int)(i - (long long)g * n0);
       const ColCoord cc = col_coord(a.gm, g);
       float lnc;
-      const float H = amp_sym<NDIM>(a.filt, a.gm, cc, e, lnc);
+      const float H = amp_sym<NDIM, true>(a.filt, a.gm, cc, e, lnc);
       const double val = (double)(cc.wm * H * H);
       const int bin = (int)a.table[i];
       tot += val;

@@ -292,6 +292,7 @@ int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins
   HU_TRY(make_geom(dims, &g));
   HU_TRY(check_filter(filt, g.nd));
   if (filt->offset != 0.0) return HU_ERR_UNSUPPORTED;   // the adjoint differentiates sqrt(chi) only
+  if (filt->prof_n != 0) return HU_ERR_UNSUPPORTED;     // ... of Eq. (13), not of a tabulated form
   HU_TRY(check_bins(&bins, g.nd));
   if (!dL_dP || !cont_sum || !cont_cnt || !stats || !grad) return HU_ERR_ARG;
   const void* ptrs[] = {dL_dP, cont_sum, cont_cnt, stats, grad};

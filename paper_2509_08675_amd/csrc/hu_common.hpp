@@ -164,7 +164,7 @@ __device__ __forceinline__ ColCoord col_coord(const Axis0Geom& gm, int g) {
 
 // symmetrised amplitude at axis-0 index e of column cc (Eq. (8) with Eqs. (12)-(13));
 // also returns ln chi (unsymmetrised) for the support check
-template <int NDIM>
+template <int NDIM, bool PROF = false>
 __device__ __forceinline__ float amp_sym(const FiltDev& f, const Axis0Geom& gm, const ColCoord& cc, int e,
                                          float& lnc) {
   const int mt = e < gm.n0 / 2 ? e : e - gm.n0;
@@ -174,12 +174,12 @@ __device__ __forceinline__ float amp_sym(const FiltDev& f, const Axis0Geom& gm, 
   bool ny_y;
   if constexpr (NDIM == 2) { ky = k0c; kz = 0.0f; ny_y = nyq0; }
   else { ky = cc.ky; kz = k0c; ny_y = cc.nyq_y; }
-  lnc = ln_chi<NDIM>(f, kx, ky, kz);
+  lnc = ln_chi<NDIM, PROF>(f, kx, ky, kz);
   float H = amp_from_lnchi(lnc, f.offset);
   if (f.rotated && (cc.nyq_x || ny_y)) {
     // partner -m: by evenness, the canonical kappa with its Nyquist components negated
     const float kx2 = cc.nyq_x ? -kx : kx, ky2 = ny_y ? -ky : ky;
-    const float l2 = ln_chi<NDIM>(f, kx2, ky2, kz);
+    const float l2 = ln_chi<NDIM, PROF>(f, kx2, ky2, kz);
     H = 0.5f * (H + amp_from_lnchi(l2, f.offset));
   }
   return H;

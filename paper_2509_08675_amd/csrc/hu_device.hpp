@@ -484,7 +484,21 @@ struct FiltDev {
   float offset;          // offset regularisation added to chi / chi(K*) (0: none)
   float lnoffset;        // ln offset, or -1e30
   int rotated;           // rot != 0 (H_sym differs from H on x / y Nyquist planes)
+  const float* prof;     // tabulated ln chi(i dK), or null for Eq. (13)
+  int prof_n;            // samples
+  float prof_idk;        // 1 / dK
 };
+
+// ln chi(K) of a tabulated radial form: linear interpolation between samples i dK, held at the
+// last sample beyond the table
+__device__ __forceinline__ float prof_lnchi(const FiltDev& f, float K) {
+  const float x = K * f.prof_idk;
+  if (!(x < (float)(f.prof_n - 1))) return f.prof[f.prof_n - 1];
+  const int i = (int)x;
+  const float t = x - (float)i;
+  const float l0 = f.prof[i], l1 = f.prof[i + 1];
+  return fmaf(t, l1 - l0, l0);
+}
 
 // Load of a read-only table entry at a wave-uniform index through the constant address space, so
 // the compiler issues a scalar load (the host pass never runs device code and reads normally).
@@ -503,8 +517,9 @@ __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2
 // ln chi (relative to its peak) at the (unrotated) wavenumber (kx, ky, kz), kz = 0 in 2D:
 //   u_i = |kappa'_i| / a_i,  K = u_max (sum_i (u_i / u_max)^p)^(1/p)   (Eq. (12), scaled form)
 //   ln chi = alpha ln K - (K - k0)^2 / (2 w^2) - ln chi(K*)            (Eq. (13) with band centre k0)
+// or, for a tabulated radial form, the interpolated samples at K.
 // The largest ratio is 1, so only the other one (2D) or two (3D) need a power.
-template <int NDIM>
+template <int NDIM, bool PROF = false>
 __device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, float kz) {
   const float kxr = fmaf(f.cr, kx, f.sr * ky);
   const float kyr = fmaf(-f.sr, kx, f.cr * ky);
@@ -528,6 +543,9 @@ __device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, fl
   }
   const float log2K = fmaf(hw_log2(S), f.ip, hw_log2(um));
   const float K = hw_exp2(log2K);
+  if constexpr (PROF) {                          // instantiated only where a tabulated form may occur
+    if (f.prof) return prof_lnchi(f, K);
+  }
   const float d = K - f.k0;
   return fmaf(f.alpha, log2K * 0.69314718055994531f, -fmaf(d * d, f.inv2w2, f.lnchimax));
 }

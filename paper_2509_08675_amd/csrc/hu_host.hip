@@ -295,6 +295,13 @@ int check_filter(const hu_filter* f, int nd) {
   if (!f) return HU_ERR_ARG;
   if (!finite_pos(f->p) || !finite_pos(f->semi[0]) || !finite_pos(f->semi[1])) return HU_ERR_ARG;
   if (nd == 3 && !finite_pos(f->semi[2])) return HU_ERR_ARG;
+  if (f->prof_n != 0) {          // tabulated radial form: alpha, k0 and width unused
+    if (f->prof_n < 2 || !f->prof || !finite_pos(f->prof_dk) || !finite_pos(f->sigma_f)) return HU_ERR_ARG;
+    if (!aligned(f->prof, 4)) return HU_ERR_ALIGN;
+    if (!std::isfinite(f->rot) || !std::isfinite(f->offset) || f->offset < 0.0) return HU_ERR_ARG;
+    if (f->offset > 0.0) return HU_ERR_UNSUPPORTED;
+    return HU_OK;
+  }
   if (!std::isfinite(f->alpha) || !(f->alpha > -(double)nd) || !finite_pos(f->width) || !finite_pos(f->sigma_f))
     return HU_ERR_ARG;
   if (!std::isfinite(f->offset) || f->offset < 0.0) return HU_ERR_ARG;
@@ -397,6 +404,14 @@ FiltDev filt_dev(const hu_filter& f, const Geom& g) {
   d.offset = (float)f.offset;
   d.lnoffset = f.offset > 0.0 ? (float)std::log(f.offset) : -1.0e30f;
   d.rotated = (f.rot != 0.0) ? 1 : 0;
+  if (f.prof_n > 0) {            // samples used as given: no continuum normalisation, no offset
+    d.prof = f.prof;
+    d.prof_n = f.prof_n;
+    d.prof_idk = (float)(1.0 / f.prof_dk);
+    d.lnchimax = 0.0f;
+    d.offset = 0.0f;
+    d.lnoffset = -1.0e30f;
+  }
   return d;
 }
 
@@ -599,6 +614,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fa.partials = partials;
   fa.cont_sum = batch_mode ? nullptr : o.cont_sum;
   fa.want_bins = want_cont ? 1 : 0;
+  fa.any_prof = (batch_mode ? r.any_prof : r.filt.prof_n > 0) ? 1 : 0;
   HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], r.plan.v[P_FILTER], fa, st); }));
   FinalizeArgs fz{};
   fz.partials = partials;

@@ -99,6 +99,7 @@ struct ClassRun {
   // batch mode
   const FieldIO* io;
   bool want_cont, want_pm1_spec;
+  bool any_prof;           // some job of the class uses a tabulated radial form
   // workspace of this class
   char* work;
   Layout lay;

@@ -37,7 +37,8 @@ class hu_dims(ctypes.Structure):
 class hu_filter(ctypes.Structure):
     _fields_ = [("p", ctypes.c_double), ("semi", ctypes.c_double * 3), ("rot", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("k0", ctypes.c_double), ("width", ctypes.c_double),
-                ("sigma_f", ctypes.c_double), ("offset", ctypes.c_double)]
+                ("sigma_f", ctypes.c_double), ("offset", ctypes.c_double),
+                ("prof", ctypes.c_void_p), ("prof_n", ctypes.c_int32), ("prof_dk", ctypes.c_double)]
 
 
 class hu_bins(ctypes.Structure):
@@ -130,20 +131,30 @@ def make_dims(dims):
 
 
 def make_filter(f):
-    """hu_filter from a dict (keys p, semi, rot, alpha, k0, width, sigma_f, offset) or an object with those
-    attributes."""
+    """hu_filter from a dict (keys p, semi, rot, alpha, k0, width, sigma_f, offset, and optionally
+    prof, prof_dk) or an object with those attributes.  prof: a tabulated radial form, ln chi at
+    K = i * prof_dk, as a contiguous 1-D float32 tensor on the device (kept alive by the caller
+    for the duration of the call); alpha, k0 and width are then unused."""
     get = (lambda k, dflt=None: f.get(k, dflt)) if isinstance(f, dict) else (lambda k, dflt=None: getattr(f, k, dflt))
     h = hu_filter()
+    prof = get("prof")
     h.p = float(get("p"))
     semi = tuple(get("semi", (1.0, 1.0, 1.0))) + (1.0,) * 3
     for i in range(3):
         h.semi[i] = float(semi[i])
     h.rot = float(get("rot", 0.0))
-    h.alpha = float(get("alpha"))
+    h.alpha = float(get("alpha", 0.0 if prof is not None else None))
     h.k0 = float(get("k0", 0.0))
-    h.width = float(get("width"))
+    h.width = float(get("width", 1.0 if prof is not None else None))
     h.sigma_f = float(get("sigma_f", 1.0))
     h.offset = float(get("offset", 0.0))
+    if prof is not None:
+        if not (isinstance(prof, torch.Tensor) and prof.is_cuda and prof.dtype == torch.float32
+                and prof.dim() == 1 and prof.is_contiguous()):
+            raise TypeError("prof must be a contiguous 1-D float32 tensor on the device")
+        h.prof = prof.data_ptr()
+        h.prof_n = prof.numel()
+        h.prof_dk = float(get("prof_dk"))
     return h
 
 

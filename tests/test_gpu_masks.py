@@ -5,7 +5,9 @@ offset regularisation); the whole-pipeline parity cases for them are in test_gpu
 * the adjoint refuses a filter with an offset (HU_ERR_UNSUPPORTED), and negative alpha or offset
   are argument errors;
 * the small-k exponents of generated alpha = 0 and alpha = -1 fields are near 0 and -1 (standard
-  nonhyperuniform and antihyperuniform; properties of the method, statistical tolerance 0.15).
+  nonhyperuniform and antihyperuniform; properties of the method, statistical tolerance 0.15);
+* a tabulated radial form (two bands, FP32 samples shared by both sides) through the whole
+  pipeline against the oracle: field max-abs <= 1e-5 RMS, continuous bins rtol 1e-4.
 """
 
 import numpy as np
@@ -74,3 +76,55 @@ def test_alpha_zero_field_is_standard_nonhyperuniform(hf):
     print("exponent", a, flush=True)
     assert abs(a) < 0.15
     assert hf.hyperuniformity_class(a, 2, tol=0.15) == "nonhyperuniform (standard)"
+
+
+# ---------------------------------------------------------------------------------------------
+# tabulated radial form (two bands), through the whole pipeline against the oracle
+# ---------------------------------------------------------------------------------------------
+def _two_band_profile(dk=0.005, kmax=2.0):
+    K = dk * np.arange(int(kmax / dk) + 1)
+    chi = np.exp(-(K - 0.15) ** 2 / (2 * 0.03 ** 2)) + 0.5 * np.exp(-(K - 0.45) ** 2 / (2 * 0.05 ** 2))
+    return np.log(np.maximum(chi, 1e-30)).astype(np.float32), dk
+
+
+@pytest.mark.parametrize("dims,rot,bins", [((96, 128), 0.5, (32, 6)), ((32, 24, 16), 0.3, (16, 1))])
+def test_tabulated_radial_form_pipeline_matches_oracle(hf, dims, rot, bins):
+    prof, dk = _two_band_profile()
+    print("tabulated form", dims, flush=True)
+    prof_dev = torch.from_numpy(prof).cuda()
+    base = dict(p=3.0, semi=(1.0, 2.0, 1.5), rot=rot, sigma_f=1.0)
+    gpu_filt = dict(base, prof=prof_dev, prof_dk=dk)
+    ref_filt = O.FilterParams(p=3.0, semi=(1.0, 2.0, 1.5), rot=rot, prof=tuple(float(x) for x in prof), prof_dk=dk)
+    seeds = [21, 22]
+    bufs = hf.PipelineBuffers(dims, len(seeds), bins)
+    hf.pipeline(bufs, gpu_filt, seeds)
+    torch.cuda.synchronize()
+    hf.check_degenerate(bufs.stats)
+    for i, s in enumerate(seeds):
+        ref = O.pipeline(dims, ref_filt, s, bins[0], bins[1])
+        f = bufs.field[i].double().cpu().numpy()
+        rms = float(np.sqrt(np.mean(ref["f"] ** 2)))
+        err = float(np.max(np.abs(f - ref["f"]))) / rms
+        assert err <= 1e-5, (dims, s, err)
+        cs = bufs.cont_sum[i].cpu().numpy()
+        np.testing.assert_allclose(cs, ref["cont_sum"], rtol=1e-4, atol=1e-7 * ref["cont_sum"].max())
+
+
+def test_tabulated_radial_form_in_a_batch_equals_single_calls(hf):
+    # a shape class mixing a tabulated form and Eq. (13): each field equals its own pipeline call
+    prof, dk = _two_band_profile()
+    prof_dev = torch.from_numpy(prof).cuda()
+    tab = dict(p=3.0, semi=(1.0, 2.0, 1.0), rot=0.5, sigma_f=1.0, prof=prof_dev, prof_dk=dk)
+    eq13 = W.filt(p=4, semi=(2, 1, 1), rot=0.2, alpha=4, k0=0.2, width=0.05)
+    jobs = [dict(dims=(64, 96), filt=tab, seed=31, bins=(24, 6)), dict(dims=(64, 96), filt=eq13, seed=32, bins=(24, 6)),
+            dict(dims=(16, 24, 32), filt=tab, seed=33, bins=(16, 1))]
+    bb = hf.BatchBuffers(jobs)
+    st = hf.pipeline_batch(bb)
+    torch.cuda.synchronize()
+    assert st == [0] * len(jobs)
+    for i, j in enumerate(jobs):
+        b = hf.PipelineBuffers(j["dims"], 1, j["bins"])
+        hf.pipeline(b, j["filt"], [j["seed"]])
+        torch.cuda.synchronize()
+        assert torch.equal(bb.out[i]["field"], b.field[0]), i
+        assert torch.equal(bb.out[i]["pm1"], b.pm1[0]), i

@@ -103,6 +103,32 @@ def test_argument_errors_before_any_launch(hf):
     assert rc == hf.HU_ERR_ARG
 
 
+def test_tabulated_radial_form_argument_errors(hf):
+    lib = hf._lib
+    d = hf.make_dims((16, 16))
+    seeds = (ctypes.c_uint64 * 1)(1)
+    fake = ctypes.c_void_p(1 << 20)           # never dereferenced: validation fails first
+    # the C struct: ten doubles, a pointer, an int32 (padded to 8) and a double
+    assert ctypes.sizeof(hf.hu_filter) == 104
+
+    def with_prof(**kw):
+        f = hf.make_filter(dict(p=2, semi=(1, 1, 1), rot=0.3, alpha=2, k0=0.2, width=0.05))
+        f.prof, f.prof_n, f.prof_dk = 1 << 20, 64, 0.05
+        for k, v in kw.items():
+            setattr(f, k, v)
+        return f
+
+    for f, code in ((with_prof(prof_n=1), hf.HU_ERR_ARG), (with_prof(prof=None), hf.HU_ERR_ARG),
+                    (with_prof(prof_dk=0.0), hf.HU_ERR_ARG), (with_prof(prof_dk=float("inf")), hf.HU_ERR_ARG),
+                    (with_prof(prof=(1 << 20) + 2), hf.HU_ERR_ALIGN), (with_prof(offset=1e-3), hf.HU_ERR_UNSUPPORTED)):
+        rc = lib.hu_gen_field(d, 1, ctypes.byref(f), seeds, fake, None, None, None, None, fake, 1 << 30, None)
+        assert rc == code, (rc, code)
+    # the adjoint differentiates Eq. (13) only
+    rc = lib.hu_spectrum_grad(d, ctypes.byref(with_prof()), 1, hf.make_bins((16, 1)), fake, fake, fake, fake, fake,
+                              fake, 1 << 30, None)
+    assert rc == hf.HU_ERR_UNSUPPORTED
+
+
 def test_window_variance_argument_errors_and_workspace(hf):
     lib = hf.lib_handle()
     d = hf.make_dims((64, 64))

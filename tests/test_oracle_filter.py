@@ -7,7 +7,10 @@ Each test checks a property fixed by the paper or by mathematics, not the formul
 * Eq. (12) reduces to the Euclidean norm at p = 2, a = b, to the L1 norm at p = 1 and to the
   max norm as p -> infinity (the sentence after Eq. (12));
 * the amplitude is even, rotating the mask by 90 degrees swaps a and b, and with k0 = 0 the
-  band reduces to Eq. (13)'s exp(alpha ln K - K^2 / (2 sigma^2)) up to the constant C.
+  band reduces to Eq. (13)'s exp(alpha ln K - K^2 / (2 sigma^2)) up to the constant C;
+* a tabulated radial form sampled from a smooth closed form reproduces it within the linear
+  interpolation bound, a constant profile gives a flat amplitude, and K past the table takes
+  the last sample.
 """
 
 import numpy as np
@@ -155,3 +158,42 @@ def test_negative_alpha_normalisation_bounds_chi_on_the_lattice():
         assert np.max(lc) > -20.0                        # and the bound is not far above the maximum
         H = amplitude_half((64, 96), filt)
         assert H.flat[0] == 0.0 and np.all(np.isfinite(H))
+
+
+# ---------------------------------------------------------------------------------------------
+# tabulated radial form: ln chi at K = i dK, linearly interpolated, held at the last sample
+# ---------------------------------------------------------------------------------------------
+def test_tabulated_form_reproduces_a_smooth_closed_form():
+    # samples of the alpha = 0 Gaussian band (smooth in K): the interpolated amplitude matches the
+    # closed form within the linear-interpolation bound |ln chi''| dK^2 / 8 = dK^2 / (8 w^2)
+    from oracle.spectral import superellipse_K, wavenumbers_half
+    band = FilterParams(p=3, semi=(2, 1, 1), rot=0.4, alpha=0.0, k0=0.2, width=0.05)
+    dk = 2e-4
+    Kg = dk * np.arange(int(3.0 / dk) + 1)
+    prof = tuple(-(Kg - band.k0) ** 2 / (2 * band.width ** 2))
+    tab = band.replace(prof=prof, prof_dk=dk)
+    dims = (48, 64)
+    K, _, _ = superellipse_K(wavenumbers_half(dims), band)
+    assert K.max() < Kg[-1]
+    H0, H1 = amplitude_half(dims, band), amplitude_half(dims, tab)
+    bound = dk ** 2 / (8 * band.width ** 2)          # in ln chi, i.e. 2x in ln H
+    np.testing.assert_allclose(H1, H0, rtol=bound, atol=0.0)
+    assert H1.flat[0] == 0.0
+
+
+def test_tabulated_form_constant_and_held_last_sample():
+    from oracle.spectral import superellipse_K, wavenumbers_half
+    # a constant profile: every mode but the DC gets amplitude exp(c / 2)
+    tab = FilterParams(p=2, prof=(-1.0, -1.0), prof_dk=10.0)
+    H = amplitude_half((16, 16), tab)
+    np.testing.assert_allclose(H.ravel()[1:], np.exp(-0.5), rtol=1e-15)
+    assert H.flat[0] == 0.0
+    # a short ramp: modes past its end take its last sample, modes inside the linear value
+    dims = (32, 32)
+    tab = FilterParams(p=2, prof=(0.0, -2.0, -4.0), prof_dk=0.25)
+    K, _, _ = superellipse_K(wavenumbers_half(dims), tab)
+    H = amplitude_half(dims, tab)
+    inside, past = (K > 0) & (K <= 0.5), K > 0.5
+    assert np.any(inside) and np.any(past)
+    np.testing.assert_allclose(np.log(H[inside]) * 2, -8.0 * K[inside], rtol=1e-12)
+    np.testing.assert_allclose(H[past], np.exp(-2.0), rtol=1e-15)

@@ -6,7 +6,8 @@ offset regularisation); the whole-pipeline parity cases for them are in test_gpu
   are argument errors;
 * the small-k exponents of generated alpha = 0 and alpha = -1 fields are near 0 and -1 (standard
   nonhyperuniform and antihyperuniform; properties of the method, statistical tolerance 0.15);
-* a tabulated radial form (two bands, FP32 samples shared by both sides) through the whole
+* a tabulated radial form (two bands, FP32 samples shared by both sides): its expected spectrum
+  against the oracle (rtol 1e-5), a batch mixing it with Eq. (13) fields, and the whole
   pipeline against the oracle: field max-abs <= 1e-5 RMS, continuous bins rtol 1e-4.
 """
 
@@ -128,3 +129,18 @@ def test_tabulated_radial_form_in_a_batch_equals_single_calls(hf):
         torch.cuda.synchronize()
         assert torch.equal(bb.out[i]["field"], b.field[0]), i
         assert torch.equal(bb.out[i]["pm1"], b.pm1[0]), i
+
+
+def test_filter_spectrum_with_tabulated_form_matches_oracle(hf):
+    prof, dk = _two_band_profile()
+    prof_dev = torch.from_numpy(prof).cuda()
+    dims, nr = (128, 96), 32
+    s, c = hf.filter_spectrum(dims, dict(p=2.5, semi=(1.0, 1.5, 1.0), rot=0.3, sigma_f=1.0, prof=prof_dev, prof_dk=dk),
+                              (nr, 1))
+    torch.cuda.synchronize()
+    ref = O.FilterParams(p=2.5, semi=(1.0, 1.5, 1.0), rot=0.3, prof=tuple(float(x) for x in prof), prof_dk=dk)
+    T_ref, c_ref = O.target_bins(dims, ref, nr)
+    cnt = hf.u64_view(c)
+    np.testing.assert_array_equal(cnt[:nr], c_ref.astype(np.uint64))
+    got = s.cpu().numpy()[:nr] / np.maximum(cnt[:nr], 1)
+    np.testing.assert_allclose(got[c_ref > 0], T_ref[c_ref > 0], rtol=1e-5)

@@ -425,8 +425,12 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
   const rsrc_t spec = make_rsrc(a.spec + (long long)b * a.Nh, (unsigned)(a.Nh * 8));
   const rsrc_t tw2 = make_rsrc(a.tw2, (unsigned)(L * 8));
 
-  // ---- the tile's half rows X[0..L] into LDS, in address order
+  // ---- the tile's half rows X[0..L] into LDS, in address order.  The waves issue these loads at
+  //      raised priority, so a workgroup starting its tile gets its loads in flight ahead of the
+  //      transform work of the other resident workgroups (2D 197 -> 194 us, 3D 168 -> 160 us).
+  __builtin_amdgcn_s_setprio(2);
   load_rows<L, C, T, TILED, RS>(lds, spec, tile_off, run_stride, rows_here, tid);
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
   // ---- pre-twist: Z[k] = (X[k] + X*[L-k]) + i e^{+2 pi i k / 2L} (X[k] - X*[L-k])
   float2 v[E];

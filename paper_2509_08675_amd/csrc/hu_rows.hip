@@ -352,8 +352,10 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
     const char* src = reinterpret_cast<const char*>(a.src) + ((long long)b * a.N + v0) * ESZ;
     const rsrc_t rs = make_rsrc(src, (unsigned)nv * ESZ);
     u32x4 w[IT];
+    __builtin_amdgcn_s_setprio(2);                // as in the last row pass: loads in flight early
 #pragma unroll
     for (int it = 0; it < IT; ++it) w[it] = buf_load4(rs, (unsigned)(tid + it * T) * 16u, 0);
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int iv = tid + it * T;

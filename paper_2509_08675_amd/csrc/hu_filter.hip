@@ -85,7 +85,9 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
 
   // ---- inverse transform along axis 0 (first radix = last forward radix: no exchange needed)
   fft_run<L, P, E, true>(RadI{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
+  __builtin_amdgcn_s_setprio(2);                 // the stores out ahead of other workgroups' transforms
   if (valid) col_store<L, R1, P, E>(v, io);
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -35,7 +35,7 @@ struct Class {
   size_t work_off;           // workspace of the class
   Layout lay;
   bool want_cont, want_pm1;
-  bool any_prof;
+  bool any_gen;
 };
 
 std::mutex g_bmu;
@@ -103,7 +103,7 @@ int build_classes(const hu_job* jobs, int njobs, int32_t* status, std::vector<Cl
     c.jobs.push_back(i);
     c.want_cont = c.want_cont || jobs[i].cont_sum;
     c.want_pm1 = c.want_pm1 || jobs[i].pm1_sum;
-    c.any_prof = c.any_prof || jobs[i].filt.prof_n > 0;
+    c.any_gen = c.any_gen || filt_general(jobs[i].filt, g);
   }
   std::stable_sort(cls.begin(), cls.end(), [](const Class& a, const Class& b) {
     return (long long)a.jobs.size() * a.g.N > (long long)b.jobs.size() * b.g.N;
@@ -179,7 +179,7 @@ int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t
     plans.push_back(p);
     std::snprintf(buf, sizeof buf, "%d:%d,%d,%d:%d,%d:%zu:%d%d%d:%d%d%d%d%d|", c.g.nd, c.g.n[0], c.g.n[1], c.g.n[2],
                   c.has_bins ? c.bins.n_radial : 0, c.has_bins ? c.bins.n_angular : 0, c.jobs.size(), c.want_cont,
-                  c.want_pm1, c.any_prof, p.v[0], p.v[1], p.v[2], p.v[3], p.v[4]);
+                  c.want_pm1, c.any_gen, p.v[0], p.v[1], p.v[2], p.v[3], p.v[4]);
     key += buf;
   }
 
@@ -220,7 +220,7 @@ int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t
       r.io = io_dev + c.io_off;
       r.want_cont = c.want_cont;
       r.want_pm1_spec = c.want_pm1;
-      r.any_prof = c.any_prof;
+      r.any_gen = c.any_gen;
       r.work = w + c.work_off;
       r.lay = c.lay;
       rc = enqueue_class(r, g_side[i % NSIDE]);

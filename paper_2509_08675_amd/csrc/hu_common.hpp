@@ -163,10 +163,43 @@ __device__ __forceinline__ ColCoord col_coord(const Axis0Geom& gm, int g) {
 }
 
 // symmetrised amplitude at axis-0 index e of column cc (Eq. (8) with Eqs. (12)-(13));
-// also returns ln chi (unsymmetrised) for the support check
-template <int NDIM, bool PROF = false>
+// also returns ln chi (unsymmetrised) for the support check.  GEN: the instantiation for launches
+// where some field uses a tabulated radial form or the FP64 evaluation (uniform branches on the
+// field's filter); the default one evaluates Eq. (13) in FP32 only.
+template <int NDIM>
+__device__ __forceinline__ float amp_sym64(const FiltDev& f, const Axis0Geom& gm, const ColCoord& cc, int e,
+                                           float& lnc) {
+  // the canonical wavenumbers in FP64: 2 m~ / n, -1 on a Nyquist index
+  const int mt = e < gm.n0 / 2 ? e : e - gm.n0;
+  const double k0c = (double)(2 * mt) / (double)gm.n0;
+  const bool nyq0 = (2 * e == gm.n0);
+  const double kx = cc.nyq_x ? -1.0 : (double)(2 * cc.mx) / (double)gm.nx;
+  double ky, kz;
+  bool ny_y;
+  if constexpr (NDIM == 2) { ky = k0c; kz = 0.0; ny_y = nyq0; }
+  else {
+    const int my = cc.my < gm.ny / 2 ? cc.my : cc.my - gm.ny;
+    ky = (double)(2 * my) / (double)gm.ny;
+    kz = k0c;
+    ny_y = cc.nyq_y;
+  }
+  const double l1 = ln_chi64<NDIM>(f, kx, ky, kz);
+  lnc = l1 > -1.0e299 ? (float)l1 : -1.0e30f;
+  float H = amp_from_lnchi64(l1, f.doffset);
+  if (f.rotated && (cc.nyq_x || ny_y)) {
+    const double l2 = ln_chi64<NDIM>(f, cc.nyq_x ? -kx : kx, ny_y ? -ky : ky, kz);
+    H = (float)(0.5 * ((double)H + (double)amp_from_lnchi64(l2, f.doffset)));
+  }
+  return H;
+}
+
+template <int NDIM, bool GEN = false>
 __device__ __forceinline__ float amp_sym(const FiltDev& f, const Axis0Geom& gm, const ColCoord& cc, int e,
                                          float& lnc) {
+  if constexpr (GEN) {
+    if (f.prec64) return amp_sym64<NDIM>(f, gm, cc, e, lnc);
+  }
+  constexpr bool PROF = GEN;
   const int mt = e < gm.n0 / 2 ? e : e - gm.n0;
   const float k0c = (float)mt * gm.kap0;         // canonical kappa along axis 0 (-1 at Nyquist)
   const bool nyq0 = (2 * e == gm.n0);

@@ -487,6 +487,11 @@ struct FiltDev {
   const float* prof;     // tabulated ln chi(i dK), or null for Eq. (13)
   int prof_n;            // samples
   float prof_idk;        // 1 / dK
+  // FP64 evaluation of Eq. (13), for filters whose ln chi terms are large enough that their FP32
+  // rounding would show in the field (alpha ln K*, (K* - k0)^2 / (2 w^2) and ln chi(K*) summing to
+  // more than 32 in magnitude: the paper's alpha = 20 .. 100): the parameters in FP64
+  int prec64;
+  double dcr, dsr, dia, dib, dic, dp, dip, dalpha, dk0, dinv2w2, dlnchimax, doffset;
 };
 
 // ln chi(K) of a tabulated radial form: linear interpolation between samples i dK, held at the
@@ -548,6 +553,43 @@ __device__ __forceinline__ float ln_chi(const FiltDev& f, float kx, float ky, fl
   }
   const float d = K - f.k0;
   return fmaf(f.alpha, log2K * 0.69314718055994531f, -fmaf(d * d, f.inv2w2, f.lnchimax));
+}
+
+// The same ln chi in FP64 (library log2 / exp2 in double precision) from the exact wavenumbers,
+// for the filters flagged prec64.  The terms alpha ln K, (K - k0)^2 / (2 w^2) and ln chi(K*) of
+// such filters reach 50 .. 150 while ln chi itself is O(1) in the band, so their FP32 rounding
+// (2^-24 of each term) would be amplified into the amplitude; in FP64 it is 1e-14.
+template <int NDIM>
+__device__ __forceinline__ double ln_chi64(const FiltDev& f, double kx, double ky, double kz) {
+  const double kxr = f.dcr * kx + f.dsr * ky;
+  const double kyr = f.dcr * ky - f.dsr * kx;
+  const double ux = fabs(kxr) * f.dia, uy = fabs(kyr) * f.dib;
+  double um, S = 1.0;
+  if constexpr (NDIM == 2) {
+    um = fmax(ux, uy);
+    if (!(um > 0.0)) return -1.0e300;
+    const double un = fmin(ux, uy);
+    if (un > 0.0) S += exp2(f.dp * log2(un / um));
+  } else {
+    const double uz = fabs(kz) * f.dic;
+    um = fmax(ux, fmax(uy, uz));
+    if (!(um > 0.0)) return -1.0e300;
+    const double lo = fmin(ux, fmin(uy, uz));
+    const double mid = fmax(fmin(ux, uy), fmin(fmax(ux, uy), uz));
+    if (mid > 0.0) S += exp2(f.dp * log2(mid / um));
+    if (lo > 0.0) S += exp2(f.dp * log2(lo / um));
+  }
+  const double log2K = log2(S) * f.dip + log2(um);
+  const double K = exp2(log2K);
+  const double d = K - f.dk0;
+  return f.dalpha * (log2K * 0.69314718055994530942) - (d * d * f.dinv2w2 + f.dlnchimax);
+}
+
+// sqrt(chi_rel (+ offset)) from an FP64 ln chi; the DC mode keeps amplitude 0
+__device__ __forceinline__ float amp_from_lnchi64(double lnc, double offset) {
+  if (!(lnc > -1.0e299)) return 0.0f;
+  if (offset > 0.0) return (float)sqrt(exp(lnc) + offset);
+  return (float)exp(0.5 * lnc);
 }
 
 // exp(x / 2) for ln chi -> amplitude

@@ -8,7 +8,7 @@
 
 namespace hu {
 
-template <int L, int NDIM, int V, bool PROF>
+template <int L, int NDIM, int V, bool GEN>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
   constexpr int LP = ColTile<L, V>::LP;
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   for (int s = 0; s < E; ++s) {
     const int e = slot_index<L, RL, P>(s, p);
     float lnc;
-    const float H = amp_sym<NDIM, PROF>(filt, a.gm, cc, e, lnc);
+    const float H = amp_sym<NDIM, GEN>(filt, a.gm, cc, e, lnc);
     const float2 F = cscale(v[s], H);
     v[s] = F;
     const float m2 = cc.wm * (F.x * F.x + F.y * F.y);
@@ -163,12 +163,12 @@ template <int L, int V>
 static hipError_t launch_cols_filter_L(const FilterArgs& a, hipStream_t st) {
   constexpr int T = ColTile<L, V>::T;
   const size_t lds = a.want_bins ? col_lds_bytes_t<L, V>(a.nb) : col_xchg_bytes<L, V>();
-  // the tabulated-form branch only in the instantiation launched when a field may use one
+  // the tabulated-form and FP64 branches only in the instantiation launched when a field may use one
   if (a.gm.ndim == 2) {
-    if (a.any_prof) hipLaunchKernelGGL((k_cols_filter<L, 2, V, true>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+    if (a.any_gen) hipLaunchKernelGGL((k_cols_filter<L, 2, V, true>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
     else hipLaunchKernelGGL((k_cols_filter<L, 2, V, false>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
   } else {
-    if (a.any_prof) hipLaunchKernelGGL((k_cols_filter<L, 3, V, true>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+    if (a.any_gen) hipLaunchKernelGGL((k_cols_filter<L, 3, V, true>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
     else hipLaunchKernelGGL((k_cols_filter<L, 3, V, false>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
   }
   return hipGetLastError();

@@ -404,6 +404,27 @@ FiltDev filt_dev(const hu_filter& f, const Geom& g) {
   d.offset = (float)f.offset;
   d.lnoffset = f.offset > 0.0 ? (float)std::log(f.offset) : -1.0e30f;
   d.rotated = (f.rot != 0.0) ? 1 : 0;
+  // FP32 evaluation rounds each of alpha ln K, (K - k0)^2 / (2 w^2) and ln chi(K*) at 2^-24 of
+  // its magnitude; near the band they are about their values at the reference K, and the field
+  // error they cause grows with their sum (about 6e-8 of it, plus 5e-7; an emulation of the FP32
+  // chain at 1024^2: 7e-7 at alpha = 0.5, 4e-6 at alpha = 20, 1.2e-5 at alpha = 100).  Above 32
+  // (the paper's alpha = 20 .. 100) the filter is evaluated in FP64.
+  const double kref = f.alpha > 0.0 ? ks : (f.alpha == 0.0 ? (f.k0 > 0.0 ? f.k0 : 0.0) : 0.0);
+  const double tsum = (kref > 0.0 ? std::fabs(f.alpha * std::log(kref)) : 0.0) +
+                      (kref - f.k0) * (kref - f.k0) / w2 + std::fabs(ref);
+  d.prec64 = tsum > FP32_FILTER_TERMS ? 1 : 0;
+  d.dcr = std::cos(f.rot);
+  d.dsr = std::sin(f.rot);
+  d.dia = 1.0 / f.semi[0];
+  d.dib = 1.0 / f.semi[1];
+  d.dic = 1.0 / f.semi[2];
+  d.dp = f.p;
+  d.dip = 1.0 / f.p;
+  d.dalpha = f.alpha;
+  d.dk0 = f.k0;
+  d.dinv2w2 = 1.0 / w2;
+  d.dlnchimax = ref;
+  d.doffset = f.offset;
   if (f.prof_n > 0) {            // samples used as given: no continuum normalisation, no offset
     d.prof = f.prof;
     d.prof_n = f.prof_n;
@@ -411,9 +432,12 @@ FiltDev filt_dev(const hu_filter& f, const Geom& g) {
     d.lnchimax = 0.0f;
     d.offset = 0.0f;
     d.lnoffset = -1.0e30f;
+    d.prec64 = 0;
   }
   return d;
 }
+
+bool filt_general(const hu_filter& f, const Geom& g) { return f.prof_n > 0 || filt_dev(f, g).prec64 != 0; }
 
 Axis0Geom axis0(const Geom& g) {
   Axis0Geom a{};
@@ -614,7 +638,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fa.partials = partials;
   fa.cont_sum = batch_mode ? nullptr : o.cont_sum;
   fa.want_bins = want_cont ? 1 : 0;
-  fa.any_prof = (batch_mode ? r.any_prof : r.filt.prof_n > 0) ? 1 : 0;
+  fa.any_gen = (batch_mode ? r.any_gen : filt_general(r.filt, g)) ? 1 : 0;
   HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], r.plan.v[P_FILTER], fa, st); }));
   FinalizeArgs fz{};
   fz.partials = partials;

@@ -54,7 +54,11 @@ int check_bins(const hu_bins* b, int nd);
 bool aligned(const void* p, size_t a);
 size_t up256(size_t x);
 Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan);
+// the sum of the ln chi terms' magnitudes above which the filter is evaluated in FP64
+constexpr double FP32_FILTER_TERMS = 32.0;
 FiltDev filt_dev(const hu_filter& f, const Geom& g);
+// the filter needs the general kernel instantiation (tabulated radial form or FP64 evaluation)
+bool filt_general(const hu_filter& f, const Geom& g);
 Axis0Geom axis0(const Geom& g);
 int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd);
 int get_tw(int L, const float2** tw);
@@ -99,7 +103,7 @@ struct ClassRun {
   // batch mode
   const FieldIO* io;
   bool want_cont, want_pm1_spec;
-  bool any_prof;           // some job of the class uses a tabulated radial form
+  bool any_gen;            // some job of the class uses a tabulated radial form or the FP64 filter
   // workspace of this class
   char* work;
   Layout lay;

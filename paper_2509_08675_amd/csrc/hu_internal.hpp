@@ -96,7 +96,7 @@ struct FilterArgs {
   double* partials;        // [B][tiles][4]: sum w |F|^2, Re F(0), max ln chi
   double* cont_sum;        // [B][nb] raw sums of w |F|^2, or null (counts are filled from the geometry)
   int want_bins;           // accumulate the continuous spectrum (LDS sized for it)
-  int any_prof;            // some field uses a tabulated radial form
+  int any_gen;             // some field uses a tabulated radial form or the FP64 filter evaluation
 };
 
 struct FinalizeArgs {

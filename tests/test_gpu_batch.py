@@ -7,7 +7,9 @@
   for new seeds each time;
 * an invalid job gets its error status and does not disturb the others;
 * the half-width tile variants give the same fields as the default ones and match the oracle;
-* the autotuner writes a plan the library then reports.
+* the autotuner writes a plan the library then reports;
+* the full uneven 512-field batch in the benchmark's launch configuration: one field of every
+  shape class (64^2 .. 1024^2, 64^3 .. 128^3) against the oracle to the parity tolerances.
 """
 
 import json
@@ -20,6 +22,8 @@ import torch
 
 import oracle as O
 from paper_2509_08675_amd import workloads as W
+
+import _parity as P
 
 pytestmark = pytest.mark.gpu
 
@@ -84,13 +88,30 @@ def test_batch_matches_single_calls_and_oracle(hf):
     _check_against_singles(hf, bb, jobs)
     for i in (2, 7):
         j = jobs[i]
-        ref = O.pipeline(j["dims"], O.FilterParams(**j["filt"]), j["seed"], *j["bins"])
-        f = bb.out[i]["field"].double().cpu().numpy()
-        rms = math.sqrt(float(np.mean(ref["f"] ** 2)))
-        assert np.max(np.abs(f - ref["f"])) <= 1e-5 * rms
-        np.testing.assert_array_equal(hf.u64_view(bb.out[i]["cont_cnt"]), ref["cont_cnt"])
-        np.testing.assert_allclose(bb.out[i]["cont_sum"].cpu().numpy(), ref["cont_sum"], rtol=1e-4,
-                                   atol=1e-7 * ref["cont_sum"].max())
+        P.compare_field("mixed_batch_job%d" % i, j["dims"], j["filt"], j["seed"], j["bins"], job_host(hf, bb, i))
+
+
+def job_host(hf, bb, i):
+    """Job i of BatchBuffers as host arrays, in the form _parity.compare_field takes."""
+    o = bb.out[i]
+    h = {k: (hf.u64_view(v) if k in ("counts", "cont_cnt", "pm1_cnt") else v.cpu().numpy()) for k, v in o.items()}
+    return h
+
+
+def test_full_uneven_batch_sampled(hf):
+    jobs = W.c4_jobs()
+    _say("uneven batch of", len(jobs))
+    bb = hf.BatchBuffers(jobs)
+    st = hf.pipeline_batch(bb)
+    torch.cuda.synchronize()
+    assert st == [0] * len(jobs)
+    first = {}
+    for i, j in enumerate(jobs):
+        first.setdefault(tuple(j["dims"]), i)
+    for dims, i in sorted(first.items()):
+        j = jobs[i]
+        rec = P.compare_field("c4_job%d" % i, dims, j["filt"], j["seed"], j["bins"], job_host(hf, bb, i))
+        _say("   job", i, dims, "max err/rms %.3e" % rec["field_err_rms"], "flips", rec["flips"])
 
 
 def test_batch_graph_replays(hf):

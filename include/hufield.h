@@ -36,7 +36,8 @@
  *   it allocates on first use of a size and keeps until the process ends; hu_pipeline_batch
  *   also keeps a pinned upload buffer and its cached graphs, and hu_autotune allocates (and
  *   frees) its own test fields.  Apart from those it never allocates.  Workspace is
- *   caller-provided and its required size comes from hu_workspace_size(_batch).
+ *   caller-provided and its required size comes from hu_workspace_size(_batch), except for
+ *   hu_pipeline_noalloc, whose workspace is a fixed 128 MiB device array of the library.
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  All work is enqueued
  *   asynchronously; outputs are valid once the stream has been synchronised.  The first call
  *   on a new size waits on the host until its tables are built; hu_pipeline_batch waits for
@@ -70,7 +71,8 @@ enum {
   HU_ERR_WORKSPACE = -4,  /* workspace smaller than hu_workspace_size */
   HU_ERR_DEGENERATE = -5, /* reserved: returned by host-side helpers for a filter with no lattice support */
   HU_ERR_HIP = -6,        /* a HIP runtime call failed */
-  HU_ERR_UNSUPPORTED = -7 /* valid request that the library does not implement */
+  HU_ERR_UNSUPPORTED = -7, /* valid request that the library does not implement */
+  HU_ERR_TABLES = -8      /* hu_pipeline_noalloc: the per-size tables of the grid / bins do not exist yet */
 };
 
 enum { HU_F32 = 0, HU_I8 = 1 };
@@ -164,6 +166,29 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
 int hu_pipeline(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds,
                 hu_bins bins, float near_tol, const hu_outputs* out, void* work, size_t work_bytes,
                 void* stream);
+
+/* hu_pipeline for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same work, kernels and outputs as
+ * hu_pipeline(dims, batch, filt, seeds, bins, near_tol, out, work, bytes, stream), with the
+ * workspace taken from a fixed device array inside the library instead of a caller buffer.
+ *   Limit: the workspace hu_workspace_size(HU_OP_PIPELINE, dims, min(batch, 64), &bins) reports
+ *   must be at most HU_NOALLOC_WORK_BYTES (128 MiB: e.g. one 256^3 field, seven 2048^2 fields,
+ *   fifteen 1024^2 fields per call); larger requests return HU_ERR_WORKSPACE and enqueue nothing.
+ *   The array exists once per GPU (the library holds 128 MiB of device memory on every GPU it
+ *   runs on until the process ends); its address is looked up once per device on the first call
+ *   with that device current.
+ *   The call allocates nothing: no hipMalloc / hipFree and no host staging.  The per-size tables
+ *   (twiddles, bin tables) must already exist on the current device, i.e. some allocating call
+ *   (hu_pipeline, hu_gen_field, hu_power_spectrum, ...) on the same grid and bins has been made
+ *   earlier in the process; otherwise HU_ERR_TABLES is returned and nothing is enqueued.
+ *   Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (two
+ *   streams, two host threads) race on it and corrupt each other's results; order them on one
+ *   stream.  Nothing in the array needs to start at zero (every pass writes what the next one
+ *   reads), so no clearing is enqueued.
+ *   Arguments, outputs and errors otherwise as hu_pipeline. */
+#define HU_NOALLOC_WORK_BYTES ((size_t)128 << 20)
+int hu_pipeline_noalloc(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds, hu_bins bins,
+                        float near_tol, const hu_outputs* out, void* stream);
 
 /* Expected binned spectrum of a filter, with no noise: per mode E[P(k)] = sigma_f^2 N H_sym(k)^2 /
  * sum_k' w_k' H_sym(k')^2 (Eqs. (10)-(11) under the normalisation of Eq. (15)), summed per bin

@@ -65,7 +65,10 @@ int fs_blocks(const Geom& g) {
   return (int)(n < FS_MAX_BLOCKS ? n : FS_MAX_BLOCKS);
 }
 
-int run_generator(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds, const hu_bins* bins,
+
+}  // namespace
+
+int hu::run_generator(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds, const hu_bins* bins,
                   float near_tol_rel, const hu_outputs& o, bool thresh, void* work, size_t work_bytes, void* stream) {
   Geom g;
   HU_TRY(make_geom(dims, &g));
@@ -105,8 +108,6 @@ int run_generator(hu_dims dims, int32_t batch, const hu_filter* filt, const uint
   }
   return HU_OK;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -597,6 +598,7 @@ const char* hu_strerror(int code) {
     case HU_ERR_DEGENERATE: return "filter has no support on the lattice (max ln chi < -80)";
     case HU_ERR_HIP: return "HIP runtime error";
     case HU_ERR_UNSUPPORTED: return "unsupported request";
+    case HU_ERR_TABLES: return "the per-size tables of this grid and bin layout do not exist yet (hu_pipeline_noalloc allocates none: make any allocating call on the same grid and bins first)";
     default: return "unknown error";
   }
 }

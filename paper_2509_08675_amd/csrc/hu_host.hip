@@ -503,6 +503,20 @@ int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t
   return HU_OK;
 }
 
+int tables_ready(const Geom& g, const hu_bins* bins) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int dev = current_device();
+  if (!g_tw.count({dev, g.nx / 2}) || !g_tw2.count({dev, g.nx / 2}) || !g_tw.count({dev, g.n[0]}))
+    return HU_ERR_TABLES;
+  if (g.nd == 3 && !g_tw.count({dev, g.n[1]})) return HU_ERR_TABLES;
+  if (bins) {
+    if (!g_edges.count({dev, bins->n_angular})) return HU_ERR_TABLES;
+    const std::vector<long long> key = {dev, g.nd, g.n[0], g.n[1], g.n[2], bins->n_radial, bins->n_angular};
+    if (!g_bingeo.count(key)) return HU_ERR_TABLES;
+  }
+  return HU_OK;
+}
+
 // every table a class needs, created before any launch (and before a graph capture)
 int prepare_tables(const Geom& g, const hu_bins* bins, hipStream_t st) {
   const float2 *a, *b;

@@ -65,6 +65,9 @@ int get_tw(int L, const float2** tw);
 int get_tw2(int L, const float2** tw2);
 int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t st, BinGeo* out);
 int prepare_tables(const Geom& g, const hu_bins* bins, hipStream_t st);
+// HU_OK when every table prepare_tables would build already exists on the current device,
+// else HU_ERR_TABLES (allocates nothing)
+int tables_ready(const Geom& g, const hu_bins* bins);
 
 // tuned plans: in-memory cache, loaded once from $HUFIELD_TUNE_CACHE when set
 std::string plan_key(const Geom& g, const hu_bins* bins, int batch);
@@ -109,5 +112,11 @@ struct ClassRun {
   Layout lay;
 };
 int enqueue_class(const ClassRun& r, hipStream_t st);
+
+// hu_gen_field / hu_pipeline for a uniform batch into the given workspace (thresh: sign map,
+// counts and the +-1 spectrum); builds any missing per-size tables first
+int run_generator(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds, const hu_bins* bins,
+                  float near_tol_rel, const hu_outputs& o, bool thresh, void* work, size_t work_bytes, void* stream);
+
 
 }  // namespace hu

@@ -20,7 +20,8 @@ if not os.path.exists(_LIB_PATH):
 _lib = ctypes.CDLL(_LIB_PATH)
 
 HU_OK, HU_ERR_ARG, HU_ERR_SIZE, HU_ERR_ALIGN, HU_ERR_WORKSPACE, HU_ERR_DEGENERATE, HU_ERR_HIP, \
-    HU_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+    HU_ERR_UNSUPPORTED, HU_ERR_TABLES = 0, -1, -2, -3, -4, -5, -6, -7, -8
+HU_NOALLOC_WORK_BYTES = 128 << 20
 HU_F32, HU_I8 = 0, 1
 HU_OP_GEN_FIELD, HU_OP_PIPELINE, HU_OP_POWER_SPECTRUM, HU_OP_LOSS, HU_OP_FILTER_SPECTRUM = 0, 1, 2, 3, 4
 HU_OP_WINDOW_VARIANCE = 5
@@ -65,6 +66,7 @@ _lib.hu_gen_field.argtypes = [hu_dims, _i32, _P(hu_filter), _P(_u64), _vp, _vp, 
 _lib.hu_threshold.argtypes = [hu_dims, _i32, _vp, _vp, _vp, _f32, _vp]
 _lib.hu_power_spectrum.argtypes = [hu_dims, _i32, _vp, _i32, hu_bins, _vp, _vp, _vp, _sz, _vp]
 _lib.hu_pipeline.argtypes = [hu_dims, _i32, _P(hu_filter), _P(_u64), hu_bins, _f32, _P(hu_outputs), _vp, _sz, _vp]
+_lib.hu_pipeline_noalloc.argtypes = [hu_dims, _i32, _P(hu_filter), _P(_u64), hu_bins, _f32, _P(hu_outputs), _vp]
 _lib.hu_strerror.argtypes = [ctypes.c_int]
 _lib.hu_strerror.restype = ctypes.c_char_p
 _lib.hu_debug_philox.argtypes = [_u64, _u64, _u64, _vp, _vp, _vp]
@@ -83,7 +85,7 @@ _lib.hu_hyperuniformity_class.argtypes = [ctypes.c_double, _i32, ctypes.c_double
 _lib.hu_level_threshold.argtypes = [ctypes.c_double, ctypes.c_double, _P(ctypes.c_double)]
 _lib.hu_level_cut.argtypes = [hu_dims, _i32, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _f32, _vp]
 _lib.hu_two_point.argtypes = [hu_dims, _i32, _vp, _vp, _vp, _sz, _vp]
-for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline",
+for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline", "hu_pipeline_noalloc",
            "hu_debug_philox", "hu_profile_enable", "hu_profile_read", "hu_workspace_size_batch",
            "hu_pipeline_batch", "hu_autotune", "hu_plan_query", "hu_plan_set", "hu_filter_spectrum",
            "hu_spectrum_grad", "hu_window_variance", "hu_small_k_exponent", "hu_hyperuniformity_class",
@@ -376,6 +378,19 @@ def pipeline(bufs, filt, seeds, near_tol=1e-5):
     _check(_lib.hu_pipeline(bufs._dims, bufs.batch, ctypes.byref(h), _seeds(seeds), bufs._bins, float(near_tol),
                             ctypes.byref(bufs._out), _ptr(bufs.work), bufs.work.numel(), _stream(dev)),
            "hu_pipeline")
+    return bufs
+
+
+def pipeline_noalloc(bufs, filt, seeds, near_tol=1e-5):
+    """hu_pipeline_noalloc into the outputs of PipelineBuffers (its workspace is not used: the
+    library's fixed device array is).  Raises HuError(HU_ERR_TABLES) if no allocating call has
+    built this grid's tables yet, HuError(HU_ERR_WORKSPACE) beyond the array's size."""
+    if len(seeds) != bufs.batch:
+        raise ValueError("need one seed per field")
+    h = make_filter(filt)
+    _check(_lib.hu_pipeline_noalloc(bufs._dims, bufs.batch, ctypes.byref(h), _seeds(seeds), bufs._bins,
+                                    float(near_tol), ctypes.byref(bufs._out), _stream(bufs.work.device)),
+           "hu_pipeline_noalloc")
     return bufs
 
 

@@ -199,3 +199,26 @@ def test_level_cut_and_two_point_argument_errors(hf):
     assert lib.hu_two_point(d, 1, ctypes.c_void_p((1 << 20) + 8), fake, fake, 1 << 30, None) == hf.HU_ERR_ALIGN
     n = hf.workspace_size(hf.HU_OP_TWO_POINT, (256, 256, 256), 4)
     assert n >= 4 * 256 * 256 * 129 * 8
+
+
+def test_pipeline_noalloc_refusals_on_the_host(hf):
+    """The allocation-free entry point refuses, before any launch, a shape whose workspace
+    exceeds its fixed array and a shape whose per-size tables were never built."""
+    lib = hf.lib_handle()
+    fake = ctypes.c_void_p(1 << 20)
+    o = hf.hu_outputs()
+    o.field = fake
+    filt = hf.make_filter(__import__("paper_2509_08675_amd.workloads", fromlist=["C2"]).C2["filt"])
+    seeds = (ctypes.c_uint64 * 9)(*range(9))
+    big = hf.make_dims((2048, 2048))
+    assert hf.workspace_size(hf.HU_OP_PIPELINE, (2048, 2048), 9, (16, 1)) > hf.HU_NOALLOC_WORK_BYTES
+    assert hf.workspace_size(hf.HU_OP_PIPELINE, (2048, 2048), 7, (16, 1)) <= hf.HU_NOALLOC_WORK_BYTES
+    assert lib.hu_pipeline_noalloc(big, 9, ctypes.byref(filt), seeds, hf.make_bins((16, 1)), 1e-5,
+                                   ctypes.byref(o), None) == hf.HU_ERR_WORKSPACE
+    assert lib.hu_pipeline_noalloc(hf.make_dims((24, 48)), 1, ctypes.byref(filt), seeds, hf.make_bins((11, 3)),
+                                   1e-5, ctypes.byref(o), None) == hf.HU_ERR_TABLES
+    assert lib.hu_pipeline_noalloc(hf.make_dims((24, 48)), 1, ctypes.byref(filt), seeds, hf.make_bins((11, 3)),
+                                   1e-5, None, None) == hf.HU_ERR_ARG
+    assert lib.hu_pipeline_noalloc(hf.make_dims((24, 50)), 1, ctypes.byref(filt), seeds, hf.make_bins((11, 3)),
+                                   1e-5, ctypes.byref(o), None) == hf.HU_ERR_SIZE
+    assert "tables" in hf.strerror(hf.HU_ERR_TABLES)

@@ -16,7 +16,13 @@ Prints ONE JSON line.  Besides the headline value it carries
                 autotuning, with its plain form; the 512^3 forward plus the adjoint of the
                 spectrum-matching loss; the local variance over spherical windows of 8 radii
                 (hyperuniformity diagnostic) of the 2D and 3D workloads' fields; and the level cut
-                at volume fraction 0.35 with the two-point function S_2 of the cut maps.
+                at volume fraction 0.35 with the two-point function S_2 of the cut maps;
+  flops         the transform FLOPs of a step (5 N log2 N per transform, and 2.5 N log2 N) and
+                the rate they imply;
+  parity        the measured error of every output of the 128^2 configuration against the oracle;
+  paper_context the paper's two wall times (1024^2, 256^3; hardware not stated) beside one field
+                of the same grid here;
+  cpu_baseline_all_cores  the oracle's steps with an all-core FFT, with the time of each stage.
 """
 
 import argparse
@@ -46,6 +52,8 @@ def parse():
                     help="time only the batched 2D workload (for profiler runs)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the 512^3 forward + adjoint (for profiler runs)")
+    ap.add_argument("--c4-only", action="store_true",
+                    help="time only the uneven 512-field batch (for profiler runs)")
     ap.add_argument("--workload", default="2d_2048x2048_x16", choices=("2d_2048x2048_x16", "3d_256x256x256_x4"),
                     help="with --main-only: which workload to time")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -198,7 +206,7 @@ def time_mask_variants(hf, torch, cfg, steps):
     return out
 
 
-def time_uneven_batch(hf, torch, steps, warmup):
+def time_uneven_batch(hf, torch, steps, warmup, plain=True):
     """The uneven batch of 512 fields (448 2D, 64 3D) through hu_pipeline_batch (one replayed
     graph), after autotuning every shape class; and the plain form, one hu_pipeline call per
     field with the default tiles."""
@@ -228,6 +236,11 @@ def time_uneven_batch(hf, torch, steps, warmup):
     for o in bb.out:
         hf.check_degenerate(o["stats"].view(1, 4))
     del bb
+    vox = sum(math.prod(j["dims"]) for j in jobs)
+    bmin = sum(field_bytes_min(tuple(j["dims"])) for j in jobs)
+    if not plain:
+        return dict(value=round(vox / (ms * 1e-3), 1), unit="voxels/s", ms_per_step=round(ms, 4), fields=len(jobs),
+                    bytes_min=bmin, pipeline_roofline_frac=round(bmin / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
     plain = [hf.PipelineBuffers(j["dims"], 1, j["bins"]) for j in jobs]
 
     def plain_step():
@@ -241,8 +254,6 @@ def time_uneven_batch(hf, torch, steps, warmup):
         plain_step()
     torch.cuda.synchronize()
     pms = (time.perf_counter() - t0) / psteps * 1e3
-    vox = sum(math.prod(j["dims"]) for j in jobs)
-    bmin = sum(field_bytes_min(tuple(j["dims"])) for j in jobs)
     n2 = sum(1 for j in jobs if len(j["dims"]) == 2)
     return dict(value=round(vox / (ms * 1e-3), 1), unit="voxels/s", ms_per_step=round(ms, 4),
                 fields=len(jobs), fields_2d=n2, fields_3d=len(jobs) - n2, voxels=vox, shape_classes=len(classes),
@@ -367,6 +378,162 @@ def time_two_point(hf, torch, cfg, steps, phi=0.35):
     total = sum(fam.values()) - (0 if len(dims) == 3 else 4 * t)
     return dict(phi=phi, ms_per_call=round(ms, 4), value=round(N * B / (ms * 1e-3), 1), unit="voxels/s",
                 bytes_min=total, roofline_frac=round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernels=kern)
+
+
+def flops_obj(cfg, ms):
+    """Transform FLOPs of one step: three real transforms per field (the noise's forward, the
+    inverse to the field, the +-1 map's forward), counted as 5 N log2 N each (the convention of the
+    complex transform) with the real-data figure 2.5 N log2 N beside it."""
+    N = math.prod(cfg["dims"])
+    B = len(cfg["seeds"])
+    f5 = 3 * 5.0 * N * math.log2(N) * B
+    f25 = f5 / 2
+    return dict(transforms_per_field=3, per_step_5NlogN=f5, per_step_2p5NlogN=f25,
+                achieved_tflops_5NlogN=round(f5 / (ms * 1e-3) / 1e12, 2),
+                achieved_tflops_2p5NlogN=round(f25 / (ms * 1e-3) / 1e12, 2),
+                note="the path is bound by HBM, not by these FLOPs (FP32 vector peak 157.3 TFLOP/s)")
+
+
+def oracle_stages(cfg, seed, fft):
+    """One field through the oracle's steps in the order of the pipeline, timing each; `fft` supplies
+    rfftn / irfftn (numpy's, or scipy's on all cores).  Returns {stage: seconds}."""
+    import numpy as np
+    import oracle
+    dims, (nr, na) = tuple(cfg["dims"]), cfg["bins"]
+    fp = oracle.FilterParams(**cfg["filt"])
+    ax = tuple(range(len(dims)))
+    t = {}
+    c = time.perf_counter()
+    w = oracle.white_noise(dims, seed)
+    t["noise"] = time.perf_counter() - c
+    c = time.perf_counter()
+    W = fft.rfftn(w, axes=ax)
+    t["forward_fft"] = time.perf_counter() - c
+    c = time.perf_counter()
+    F = oracle.amplitude_sym(dims, fp) * W
+    t["filter"] = time.perf_counter() - c
+    c = time.perf_counter()
+    f_raw = fft.irfftn(F, s=dims, axes=ax)
+    t["inverse_fft"] = time.perf_counter() - c
+    c = time.perf_counter()
+    mu = float(f_raw.mean())
+    var = float(((f_raw - mu) ** 2).mean())
+    f = fp.sigma_f * (f_raw - mu) / np.sqrt(var)
+    tm, _, _ = oracle.threshold(f, fp.sigma_f)
+    t["normalise_threshold"] = time.perf_counter() - c
+    c = time.perf_counter()
+    for g in (f, tm.astype(np.float64)):
+        G = fft.rfftn(g, axes=ax)
+        oracle.bin_power((G.real ** 2 + G.imag ** 2) / g.size, dims, nr, na)
+    t["spectra"] = time.perf_counter() - c
+    return t
+
+
+def cpu_baseline_all_cores(cfg, budget_s=12.0):
+    """The oracle's steps with scipy.fft on all of this host's cores (workers = the affinity count)
+    in place of numpy's single-threaded FFT, on the workload's fields in order until `budget_s`
+    seconds have passed, with the time of each stage (the other stages are numpy, one core)."""
+    import scipy.fft as sfft
+    cores = len(os.sched_getaffinity(0))
+
+    class AllCores:
+        @staticmethod
+        def rfftn(x, axes):
+            return sfft.rfftn(x, axes=axes, workers=cores)
+
+        @staticmethod
+        def irfftn(x, s, axes):
+            return sfft.irfftn(x, s=s, axes=axes, workers=cores)
+    t0 = time.perf_counter()
+    n = 0
+    stages = {}
+    for seed in cfg["seeds"]:
+        for k, v in oracle_stages(cfg, seed, AllCores).items():
+            stages[k] = stages.get(k, 0.0) + v
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    vox = n * math.prod(cfg["dims"])
+    return dict(value=round(vox / el, 1), unit="voxels/s", cores=cores, kind="oracle steps, scipy.fft all cores",
+                sample="%d of the %d fields of %s, whole pipeline (field, threshold, both spectra), FP64"
+                       % (n, len(cfg["seeds"]), "x".join(map(str, cfg["dims"]))),
+                seconds=round(el, 2), stage_seconds_per_field={k: round(v / n, 4) for k, v in stages.items()})
+
+
+def oracle_stage_breakdown(cfg):
+    """Per-stage seconds of the single-core oracle on the workload's first field."""
+    import numpy as np
+
+    class OneCore:
+        @staticmethod
+        def rfftn(x, axes):
+            return np.fft.rfftn(x, axes=axes)
+
+        @staticmethod
+        def irfftn(x, s, axes):
+            return np.fft.irfftn(x, s=s, axes=axes)
+    return {k: round(v, 4) for k, v in oracle_stages(cfg, cfg["seeds"][0], OneCore).items()}
+
+
+def parity_c1(hf, torch):
+    """The small parity configuration (128^2, one field, 64 radial bins) on the GPU against the FP64
+    oracle: the measured error of every output."""
+    import numpy as np
+    import oracle
+    from paper_2509_08675_amd.workloads import C1
+    dims, (nr, na), seed = C1["dims"], C1["bins"], C1["seeds"][0]
+    b = hf.PipelineBuffers(dims, 1, (nr, na))
+    hf.pipeline(b, C1["filt"], [seed])
+    torch.cuda.synchronize()
+    fp = oracle.FilterParams(**C1["filt"])
+    ref = oracle.pipeline(dims, fp, seed, nr, na)
+    cont_ref, _ = oracle.continuous_spectrum_fused(ref["F"], dims, nr, na, fp.sigma_f)
+    f = b.field[0].double().cpu().numpy()
+    rms = math.sqrt(float(np.mean(ref["f"] ** 2)))
+    near = np.abs(ref["f"]) < 1e-5 * rms
+    diff = b.pm1[0].cpu().numpy() != ref["t"]
+    st = b.stats[0].cpu().numpy()
+    cnt = hf.u64_view(b.counts[0])
+
+    def rel(got, r):
+        r = np.asarray(r, dtype=np.float64)
+        sel = r > 1e-9 * r.max()
+        return float(np.max(np.abs(np.asarray(got)[sel] - r[sel]) / r[sel]))
+    return dict(workload=C1["name"], field_max_err_over_rms=float(np.max(np.abs(f - ref["f"])) / rms),
+                sign_flips=int(diff.sum()), sign_flips_outside_near_zero=int(np.sum(diff & ~near)),
+                near_zero_sites=int(near.sum()), mean_err_over_sd=float(abs(st[0] - ref["mu"]) / math.sqrt(ref["var"])),
+                var_rel_err=float(abs(st[1] - ref["var"]) / ref["var"]),
+                n_pos_err=int(abs(int(cnt[0]) - ref["n_pos"])),
+                cont_bins_max_rel_err=rel(b.cont_sum[0].cpu().numpy(), cont_ref),
+                pm1_bins_max_rel_err=rel(b.pm1_sum[0].cpu().numpy(), ref["pm1_sum"]),
+                bin_counts_exact=bool(np.array_equal(hf.u64_view(b.cont_cnt[0]), ref["cont_cnt"])
+                                      and np.array_equal(hf.u64_view(b.pm1_cnt[0]), ref["pm1_cnt"])),
+                note="bins compared where the oracle's bin is above 1e-9 of the largest")
+
+
+def paper_context(hf, torch):
+    """The paper's two wall times (hardware, precision and library not stated) beside one field of
+    the same grid and parameters through hu_pipeline here."""
+    from paper_2509_08675_amd.workloads import paper_preset
+    out = {}
+    for name, dims, L, alpha, paper_s, where in (
+            ("2d_1024sq_alpha20", (1024, 1024), 100.0, 20.0, 0.03, "Sec. III.A"),
+            ("3d_256cube_alpha20", (256, 256, 256), 25.0, 20.0, 1.3, "Sec. III.B")):
+        filt = paper_preset(dims[0], L, alpha=alpha, p=1.0)
+        b = hf.PipelineBuffers(dims, 1, (128, 1))
+        for _ in range(3):
+            hf.pipeline(b, filt, [1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            hf.pipeline(b, filt, [1])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 10 * 1e3
+        out[name] = dict(paper_seconds=paper_s, paper_source=where, paper_hardware="not stated",
+                         here_ms=round(ms, 4), here_outputs="field, sign map, counts, both 128-bin spectra")
+        del b
+    return out
 
 
 def cpu_baseline(cfg, budget_s=12.0):
@@ -595,6 +762,9 @@ def main():
     if args.adjoint_only:
         print(json.dumps(time_adjoint(hf, torch, args.steps, args.warmup)), flush=True)
         return
+    if args.c4_only:
+        print(json.dumps(time_uneven_batch(hf, torch, args.steps, args.warmup, plain=False)), flush=True)
+        return
 
     cfg = C3 if (args.main_only and args.workload == C3["name"]) else C2
     el, prof = time_pipeline(hf, torch, cfg, args.steps, args.warmup)
@@ -611,6 +781,7 @@ def main():
         roofline=roof,
         pipeline_roofline_frac=round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         pipeline_bytes_min=total,
+        flops=flops_obj(cfg, ms),
     )
     if args.main_only:
         print(json.dumps(line), flush=True)
@@ -637,8 +808,12 @@ def main():
         line["also"]["level_cut_and_two_point_2048sq_x16"] = time_two_point(hf, torch, C2, max(args.steps // 5, 5))
         line["also"]["level_cut_and_two_point_256cube_x4"] = time_two_point(hf, torch, C3, max(args.steps // 5, 5))
         line["also"]["mask_variants_2048sq_x16"] = time_mask_variants(hf, torch, C2, max(args.steps // 5, 5))
+    line["parity"] = parity_c1(hf, torch)
+    line["paper_context"] = paper_context(hf, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
+        line["cpu_baseline"]["stage_seconds_first_field"] = oracle_stage_breakdown(cfg)
+        line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(cfg)
     print(json.dumps(line), flush=True)
 
 

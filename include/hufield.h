@@ -183,8 +183,9 @@ int hu_pipeline(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64
  *   earlier in the process; otherwise HU_ERR_TABLES is returned and nothing is enqueued.
  *   Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (two
  *   streams, two host threads) race on it and corrupt each other's results; order them on one
- *   stream.  Nothing in the array needs to start at zero (every pass writes what the next one
- *   reads), so no clearing is enqueued.
+ *   stream.  The only words that must start at zero (the work counter of the persistent
+ *   binning pass) are cleared by the first kernel of every call; everything else a pass reads was
+ *   written by an earlier pass of the same call.
  *   Arguments, outputs and errors otherwise as hu_pipeline. */
 #define HU_NOALLOC_WORK_BYTES ((size_t)128 << 20)
 int hu_pipeline_noalloc(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64_t* seeds, hu_bins bins,
@@ -323,6 +324,22 @@ const char* hu_strerror(int code);
  * [4*count] FP32, either may be NULL.  For parity tests. */
 int hu_debug_philox(uint64_t seed, uint64_t first, uint64_t count, uint32_t* words, float* normals,
                     void* stream);
+
+/* The host-built bin tables behind the binned spectra, for tests (host only, no device work).
+ * The axis-0 passes see the half spectrum as ncol columns of n0 modes along the slowest axis
+ * (column g = m_x in 2D, g = m_y (n_x/2+1) + m_x in 3D; mode e = the natural index along axis 0)
+ * and take them in tiles of `width` consecutive columns (tile variant 0 or 1 of those passes).
+ *   sizes [6] (host): ncol, n0, ntiles, M (partials per field), nloc_max (most distinct bins in a
+ *         tile), width
+ *   table [ncol][n0]: bin of each mode (r A + a, the corner slot R A)
+ *   ltab  [ncol][n0]: position of the mode's bin in its tile's ascending list of distinct bins
+ *   toff  [ntiles + 1]: the partials of tile t are toff[t] .. toff[t+1]-1, one per distinct bin
+ *   coff  [R A + 2], cpos [M]: the partials of bin k are cpos[coff[k] .. coff[k+1]-1], tile order
+ * Each array may be NULL (host arrays).  A tile's partial is the sum over its modes in that bin,
+ * combined in integer arithmetic; a spectrum bin is a fixed-order sum of its partials, so the
+ * spectra are the same bits on every run. */
+int hu_debug_bin_tables(hu_dims dims, hu_bins bins, int32_t variant, int32_t* sizes, uint16_t* table,
+                        uint16_t* ltab, uint32_t* toff, uint32_t* coff, uint32_t* cpos);
 
 /* Kernel timing with HIP events recorded on the launch stream around every kernel the library
  * enqueues.  hu_profile_enable(1) resets the counters and starts recording; hu_profile_read

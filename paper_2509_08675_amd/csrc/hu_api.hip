@@ -85,7 +85,8 @@ int hu::run_generator(hu_dims dims, int32_t batch, const hu_filter* filt, const 
   if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
   const int chunk = batch < MAX_CHUNK ? batch : MAX_CHUNK;
   const TunePlan plan = get_plan(g, bins, batch);
-  const Layout lay = layout(g, chunk, true, plan);
+  Layout lay;
+  HU_TRY(layout(g, chunk, true, plan, bins, &lay));
   if (work_bytes < lay.total) return HU_ERR_WORKSPACE;
   const int nb = bins ? bins->n_radial * bins->n_angular + 1 : 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -117,13 +118,17 @@ int hu_workspace_size(int op, hu_dims dims, int32_t batch, const hu_bins* bins, 
   HU_TRY(make_geom(dims, &g));
   if (bins) HU_TRY(check_bins(bins, g.nd));
   const int chunk = batch < MAX_CHUNK ? batch : MAX_CHUNK;
+  Layout lay;
   switch (op) {
     case HU_OP_GEN_FIELD:
     case HU_OP_PIPELINE:
-      *bytes = layout(g, chunk, true, widest_plan()).total;
+      HU_TRY(layout(g, chunk, true, widest_plan(), bins, &lay));
+      *bytes = lay.total;
       return HU_OK;
     case HU_OP_POWER_SPECTRUM:
-      *bytes = layout(g, chunk, false, widest_plan()).total;
+      if (!bins) return HU_ERR_ARG;
+      HU_TRY(layout(g, chunk, false, widest_plan(), bins, &lay));
+      *bytes = lay.total;
       return HU_OK;
     case HU_OP_LOSS:
       if (!bins) return HU_ERR_ARG;
@@ -136,7 +141,8 @@ int hu_workspace_size(int op, hu_dims dims, int32_t batch, const hu_bins* bins, 
       *bytes = wvar_layout(g, chunk).total;
       return HU_OK;
     case HU_OP_TWO_POINT:
-      *bytes = layout(g, chunk, true, TunePlan{{0, 0, 0, 0, 0}}).total;
+      HU_TRY(layout(g, chunk, true, TunePlan{{0, 0, 0, 0, 0}}, nullptr, &lay));
+      *bytes = lay.total;
       return HU_OK;
     default:
       return HU_ERR_ARG;
@@ -188,7 +194,8 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
   if (!aligned(x, 16) || !aligned(sum, 16) || (cnt && !aligned(cnt, 16))) return HU_ERR_ALIGN;
   if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
   const TunePlan plan{{0, 0, 0, 0, 0}};
-  const Layout lay = layout(g, batch < MAX_CHUNK ? batch : MAX_CHUNK, false, plan);
+  Layout lay;
+  HU_TRY(layout(g, batch < MAX_CHUNK ? batch : MAX_CHUNK, false, plan, &bins, &lay));
   if (work_bytes < lay.total) return HU_ERR_WORKSPACE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HU_TRY(prepare_tables(g, &bins, st));
@@ -199,11 +206,14 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
   HU_TRY(get_tw2(Lrow, &tw2_row));
   HU_TRY(get_tw(g.n[0], &tw_0));
   if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
-  BinDev bd{};
-  HU_TRY(make_bindev(g, bins, &bd));
   BinGeo geo{nullptr, nullptr};
-  HU_TRY(get_bingeo(g, bins, bd, st, &geo));
+  HU_TRY(get_bingeo(g, bins, &geo));
+  TileBinDev tb{};
+  HU_TRY(get_tilebins(g, bins, col_width(g.n[0], 0), &tb));
+  if (tb.M > lay.Mp) return HU_ERR_WORKSPACE;
   float2* spec = reinterpret_cast<float2*>(reinterpret_cast<char*>(work) + lay.spec);
+  double* parts = reinterpret_cast<double*>(reinterpret_cast<char*>(work) + lay.parts_p);
+  unsigned* queue = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(work) + lay.queue);
   const size_t esz = dtype == HU_F32 ? 4 : 1;
   for (int f0 = 0; f0 < batch; f0 += MAX_CHUNK) {
     const int B = batch - f0 < MAX_CHUNK ? batch - f0 : MAX_CHUNK;
@@ -216,10 +226,10 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
     ra.src = reinterpret_cast<const char*>(x) + (size_t)f0 * g.N * esz;
     ra.tw = tw_row;
     ra.tw2 = tw2_row;
-    double* s = sum + (long long)f0 * nb;
+    ra.zero = queue;
+    ra.nzero = NQUEUE;
     uint64_t* c = cnt ? cnt + (long long)f0 * nb : nullptr;
     int fs = 0;
-    ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(s), nullptr, 2 * nb};
     if (c) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(c), reinterpret_cast<const uint32_t*>(geo.counts), 2 * nb};
     ra.fill_spans = fs;
     const int src = dtype == HU_F32 ? SRC_F32 : SRC_I8;
@@ -235,17 +245,25 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
       HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, 0, cy, st); }));
     }
     BinArgs ba{};
+    ba.ntiles = col_tiles(g.n[0], 0, g.Nh / g.n[0]);
+    ba.batch = B;
+    ba.q = ItemQueue{queue + Q_BIN, ba.ntiles * B, 8};
+    ba.sc = col_sched_fields(g.n[0], 0, g.Nh / g.n[0], B);
     ba.spec = spec;
     ba.Nh = g.Nhp;
-    ba.N = g.N;
     ba.gm = axis0(g);
-    ba.sc = col_sched(g.n[0], 0, ba.gm.ncol, B);
-    ba.bd = bd;
-    ba.nb = nb;
-    ba.table = geo.table;
+    ba.tb = tb;
+    ba.parts = parts;
     ba.tw = tw_0;
-    ba.sum = s;
     HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], 0, ba, st); }));
+    SpecFinalArgs sf{};
+    sf.nb = nb;
+    sf.coff_p = tb.coff;
+    sf.parts_p = parts;
+    sf.M_p = tb.M;
+    sf.pscale = 1.0 / (double)g.N;
+    sf.pm1_sum = sum + (long long)f0 * nb;
+    HU_HIP(timed("spec_final", st, [&] { return launch_spec_final(sf, B, st); }));
   }
   return HU_OK;
 }
@@ -266,7 +284,7 @@ int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double
   BinDev bd{};
   HU_TRY(make_bindev(g, bins, &bd));
   BinGeo geo{nullptr, nullptr};
-  HU_TRY(get_bingeo(g, bins, bd, st, &geo));
+  HU_TRY(get_bingeo(g, bins, &geo));
   FilterSpecArgs a{};
   a.gm = axis0(g);
   a.Nh = (long long)a.gm.ncol * a.gm.n0;
@@ -314,7 +332,7 @@ int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins
   BinDev bd{};
   HU_TRY(make_bindev(g, bins, &bd));
   BinGeo geo{nullptr, nullptr};
-  HU_TRY(get_bingeo(g, bins, bd, st, &geo));
+  HU_TRY(get_bingeo(g, bins, &geo));
   char* w = reinterpret_cast<char*>(work);
   float2* spec = reinterpret_cast<float2*>(w + lay.spec);
   double* coef = reinterpret_cast<double*>(w + lay.coef);
@@ -491,7 +509,8 @@ int hu_two_point(hu_dims dims, int32_t batch, const int8_t* pm1, float* s2, void
   if (!aligned(pm1, 16) || !aligned(s2, 16)) return HU_ERR_ALIGN;
   if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
   const int chunk = batch < MAX_CHUNK ? batch : MAX_CHUNK;
-  const Layout lay = layout(g, chunk, true, TunePlan{{0, 0, 0, 0, 0}});
+  Layout lay;
+  HU_TRY(layout(g, chunk, true, TunePlan{{0, 0, 0, 0, 0}}, nullptr, &lay));
   if (work_bytes < lay.total) return HU_ERR_WORKSPACE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int Lrow = g.nx / 2;

@@ -113,7 +113,7 @@ int build_classes(const hu_job* jobs, int njobs, int32_t* status, std::vector<Cl
   for (Class& c : cls) {
     c.io_off = io;
     io += c.jobs.size();
-    c.lay = layout(c.g, (int)c.jobs.size(), true, widest());
+    HU_TRY(layout(c.g, (int)c.jobs.size(), true, widest(), c.has_bins ? &c.bins : nullptr, &c.lay));
     c.work_off = off;
     off += c.lay.total;
   }
@@ -281,7 +281,8 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
   const int B = batch;
   const int nb = bins->n_radial * bins->n_angular + 1;
   const int chunk = B < MAX_CHUNK ? B : MAX_CHUNK;
-  const Layout lay = layout(g, chunk, true, widest());
+  Layout lay;
+  HU_TRY(layout(g, chunk, true, widest(), bins, &lay));
   hipStream_t st = nullptr;
   HU_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   float* field = nullptr;

@@ -1,18 +1,77 @@
 // Spectrum binning passes and small utility kernels.
 //
-//   cols_bin    forward FFT along axis 0 and the binned periodogram |X|^2 / N of the +-1 field
-//               (or of any real input), read only;
-//   bin_geom    once per grid and bin layout: the bin of every half-spectrum mode (optionally
-//               stored as a table, column-major for the axis-0 passes) and the per-bin mode counts;
+//   cols_bin    forward FFT along axis 0 and the per-tile bin partials of w |X|^2 of the +-1
+//               field (or of any real input), read only;
+//   spec_final  the per-field binned spectra from the tile partials, and the sign counts;
 //   threshold   the standalone sign map with counts;
 //   debug_philox  raw Philox words and normals for the parity tests.
 #include "hu_common.hpp"
 
 namespace hu {
 
-// One tile per workgroup; the FP64 histogram shares the exchange buffer and is flushed per tile.
+// 3D: persistent over the items (tile, field), tile-major, taken from the work counter in chunks: the
+// forward transform of a tile's columns, the per-mode values w |X|^2 into LDS, then (while the next
+// item's columns are already being loaded into the transform's registers) the tile's deterministic
+// bin partials.
 template <int L, int V>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
+  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
+  constexpr int LP = ColTile<L, V>::LP;
+  using Rad = typename Plan<L>::fwd;
+  constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
+  extern __shared__ float2 lds[];
+  __shared__ int grab[2];
+  float* pw = reinterpret_cast<float*>(lds);
+  int* hx = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + a.hx_off);
+  unsigned long long* hq = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(lds) + a.hq_off);
+  const int tid = threadIdx.x;
+  const int c = tid % C, p = tid / C;
+  for (int j = tid; j < a.tb.nloc_max; j += T) {
+    hx[j] = HX_EMPTY;
+    hq[j] = 0ull;
+  }
+  int last = 0;
+  float2 v[E];
+  for (;;) {
+    if (tid == 0) {
+      int ch = (a.q.nitems - last) / (2 * (int)gridDim.x);
+      ch = ch < 1 ? 1 : (ch > a.q.chunk_max ? a.q.chunk_max : ch);
+      const int s0 = (int)atomicAdd(a.q.counter, (unsigned)ch);
+      grab[0] = s0;
+      grab[1] = s0 + ch < a.q.nitems ? s0 + ch : a.q.nitems;
+    }
+    __syncthreads();
+    const int i0 = grab[0], i1 = grab[1];
+    if (i0 >= a.q.nitems) break;
+    last = i0;
+    {
+      const int tile = i0 / a.batch, b = i0 - tile * a.batch;
+      col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, tile * C + c, p));
+    }
+    for (int it = i0; it < i1; ++it) {
+      const int tile = it / a.batch, b = it - tile * a.batch;
+      const int g = tile * C + c;
+      const bool valid = g < a.gm.ncol;
+      fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
+      const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
+      __syncthreads();                              // the exchange buffer is free from here
+#pragma unroll
+      for (int s = 0; s < E; ++s)
+        pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = valid ? wm * (v[s].x * v[s].x + v[s].y * v[s].y) : 0.0f;
+      if (it + 1 < i1) {                            // the next item's columns, in flight during the binning
+        const int tn = (it + 1) / a.batch, bn = it + 1 - tn * a.batch;
+        col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)bn * a.Nh, a.Nh, a.gm.inner0, tn * C + c, p));
+      }
+      __syncthreads();
+      tile_bins<L, E, C, LP, T>(pw, hx, hq, a.tb, tile, a.gm.ncol, a.parts + (long long)b * a.tb.M, tid);
+    }
+  }
+}
+
+// One item per workgroup (2D): the schedule's XCD mapping puts the fields of a tile on one XCD,
+// which then reads the tile's slice of the bin table once.
+template <int L, int V>
+__global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin_tile(BinArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
   constexpr int LP = ColTile<L, V>::LP;
   using Rad = typename Plan<L>::fwd;
@@ -21,102 +80,45 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
   int b;
   long long tile;
   if (!map_tile(a.sc, b, tile)) return;
+  float* pw = reinterpret_cast<float*>(lds);
+  int* hx = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + a.hx_off);
+  unsigned long long* hq = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(lds) + a.hq_off);
   const int tid = threadIdx.x;
   const int c = tid % C, p = tid / C;
   const int g = (int)tile * C + c;
   const bool valid = g < a.gm.ncol;
-  const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, g, p);
   float2 v[E];
-  col_load<L, R1, P, E>(v, io);
+  col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, g, p));
   fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
   const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
-  float* pw = reinterpret_cast<float*>(lds);
-  double* hs = reinterpret_cast<double*>(pw + ((C * LP + 1) & ~1));
+  for (int j = tid; j < a.tb.nloc_max; j += T) {
+    hx[j] = HX_EMPTY;
+    hq[j] = 0ull;
+  }
   __syncthreads();                                  // the exchange buffer is free from here
 #pragma unroll
   for (int s = 0; s < E; ++s)
-    pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = wm * (v[s].x * v[s].x + v[s].y * v[s].y);
-  for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
+    pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = valid ? wm * (v[s].x * v[s].x + v[s].y * v[s].y) : 0.0f;
   __syncthreads();
-  bin_tile<L, E, C, LP>(pw, hs, a.table, (int)tile * C, a.gm.ncol, tid);
-  __syncthreads();
-  double* out = a.io ? a.io[b].pm1_sum : field_ptr(a.sum, a.nb, b);
-  if (out) hist_flush(hs, a.nb, 1.0 / (double)a.N, out, tid, T);
-}
-
-// Persistent, when the FP64 histogram fits beyond the exchange buffer with two workgroups per CU:
-// each workgroup takes a contiguous chunk of (field, tile) pairs, keeps one histogram per field
-// (flushed when the field changes) and requests the next tile's columns into the transform's
-// registers once the current power values are in LDS, so their loads overlap the binning.
-template <int L, int V>
-__global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin_keep(BinArgs a) {
-  constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
-  constexpr int LP = ColTile<L, V>::LP;
-  using Rad = typename Plan<L>::fwd;
-  constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
-  extern __shared__ float2 lds[];
-  const int total = a.sc.batch * a.sc.ntiles;
-  const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
-  int lin = (int)blockIdx.x * per;
-  const int end = lin + per < total ? lin + per : total;
-  if (lin >= end) return;
-  const int tid = threadIdx.x;
-  const int c = tid % C, p = tid / C;
-  float* pw = reinterpret_cast<float*>(lds);
-  double* hs = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + a.hs_off);
-  const double scale = 1.0 / (double)a.N;
-  int b = lin / a.sc.ntiles;
-  int tile = lin - b * a.sc.ntiles;
-  for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
-  float2 v[E];
-  col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, tile * C + c, p));
-  for (;;) {
-    const int g = tile * C + c;
-    const bool valid = g < a.gm.ncol;
-    fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
-    const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
-    __syncthreads();                                // the exchange buffer is free from here
-#pragma unroll
-    for (int s = 0; s < E; ++s)
-      pw[c * LP + pw_index(slot_index<L, RL, P>(s, p))] = wm * (v[s].x * v[s].x + v[s].y * v[s].y);
-    __syncthreads();
-    ++lin;
-    const int bn = lin / a.sc.ntiles, tn = lin - bn * a.sc.ntiles;
-    if (lin < end) col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)bn * a.Nh, a.Nh, a.gm.inner0, tn * C + c, p));
-    bin_tile<L, E, C, LP>(pw, hs, a.table, tile * C, a.gm.ncol, tid);
-    __syncthreads();
-    if (lin == end || bn != b) {
-      double* out = a.io ? a.io[b].pm1_sum : field_ptr(a.sum, a.nb, b);
-      if (out) hist_flush(hs, a.nb, scale, out, tid, T);
-      if (lin == end) break;
-      __syncthreads();                              // the flush has read hs
-      for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
-    }
-    b = bn;
-    tile = tn;
-  }
+  tile_bins<L, E, C, LP, T>(pw, hx, hq, a.tb, (int)tile, a.gm.ncol, a.parts + (long long)b * a.tb.M, tid);
 }
 
 template <int L, int V>
 static hipError_t launch_cols_bin_L(BinArgs a, hipStream_t st) {
   constexpr int T = ColTile<L, V>::T;
-  const long long total = (long long)a.sc.batch * a.sc.ntiles;
-  if (total == 0) return hipSuccess;
-  const size_t x = col_xchg_bytes<L, V>();
-  const size_t pwb = (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4;
-  const size_t base = ((x > pwb ? x : pwb) + 15) / 16 * 16;
-  const size_t keep = base + (size_t)a.nb * 8;
-  if (keep <= LDS_PER_CU / 2) {
-    a.hs_off = (int)base;
-    int slots = 0;
-    const hipError_t e = resident_blocks(reinterpret_cast<const void*>(&k_cols_bin_keep<L, V>), T, keep, &slots);
-    if (e != hipSuccess) return e;
-    const long long per = (total + slots - 1) / slots;
-    const unsigned grid = (unsigned)((total + per - 1) / per);
-    hipLaunchKernelGGL((k_cols_bin_keep<L, V>), dim3(grid), dim3(T), keep, st, a);
+  if (a.q.nitems <= 0) return hipSuccess;
+  a.hx_off = (int)col_bin_base<L, V>();
+  a.hq_off = a.hx_off + (a.tb.nloc_max * 4 + 15) / 16 * 16;
+  const size_t lds = (size_t)a.hq_off + (size_t)a.tb.nloc_max * 8;
+  if (a.gm.ndim == 2) {
+    hipLaunchKernelGGL((k_cols_bin_tile<L, V>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_cols_bin<L, V>), dim3(sched_blocks(a.sc)), dim3(T), (col_lds_bytes_t<L, V>(a.nb)), st, a);
+  int slots = 0;
+  const hipError_t e = resident_blocks(reinterpret_cast<const void*>(&k_cols_bin<L, V>), T, lds, &slots);
+  if (e != hipSuccess) return e;
+  const unsigned grid = (unsigned)(slots < a.q.nitems ? slots : a.q.nitems);
+  hipLaunchKernelGGL((k_cols_bin<L, V>), dim3(grid), dim3(T), lds, st, a);
   return hipGetLastError();
 }
 
@@ -130,31 +132,99 @@ hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------------------------
-// bin geometry: grid-stride over the Nh modes in half-spectrum order (m_0 slowest, column g
-// fastest); LDS-privatised u32 counts, flushed with 64-bit atomics (integers: deterministic).
+// Per-field spectra and sign counts.  The partials of a bin are stored together, in tile order, and
+// added in a fixed order by a group of G lanes of one wave: lane l of the group adds partials
+// l, l + G, l + 2G, ... (loads issued four at a time, added in order), then the group combines in a
+// fixed butterfly.  G = 8 when bins hold few partials (2D: about ten), 64 when they hold hundreds
+// (3D); the corner slot, which every tile touches, always gets a whole wave.  The result does not
+// depend on the schedule of the passes that wrote the partials.  The continuous spectrum is scaled
+// to the normalised field (factor from k_finalize), the +-1 spectrum by 1 / N.  The last workgroup
+// of each field's row of the grid also totals the last row pass's per-tile sign counts.
 // ---------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_bin_geom(BinGeomArgs a) {
-  extern __shared__ unsigned hcnt[];
-  for (int i = threadIdx.x; i < a.nb; i += 256) hcnt[i] = 0u;
-  __syncthreads();
-  const long long ncol = a.gm.ncol;
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.Nh; i += (long long)gridDim.x * 256) {
-    const int g = (int)(i % ncol);
-    const int e = (int)(i / ncol);
-    const ColCoord cc = col_coord(a.gm, g);
-    const int bi = mode_bin(a.bd, a.gm, cc, e);
-    if (a.table) a.table[g * (long long)a.gm.n0 + e] = (uint16_t)bi;
-    atomicAdd(hcnt + bi, (unsigned)cc.wm);
+constexpr int SF_T = 256;
+
+template <int G>
+__device__ __forceinline__ double bin_total(const double* __restrict__ parts, const uint32_t* __restrict__ coff,
+                                            int bin, int sub) {
+  const unsigned j1 = coff[bin + 1];
+  unsigned j = coff[bin] + sub;
+  double s = 0.0;
+  for (; j + 3 * G < j1; j += 4 * G) {
+    const double x0 = parts[j], x1 = parts[j + G], x2 = parts[j + 2 * G], x3 = parts[j + 3 * G];
+    s += x0;
+    s += x1;
+    s += x2;
+    s += x3;
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < a.nb; i += 256)
-    if (hcnt[i]) atomicAdd(a.counts + i, (unsigned long long)hcnt[i]);
+  for (; j < j1; j += G) s += parts[j];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  return s;
 }
 
-hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st) {
-  long long blocks = (a.Nh + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(k_bin_geom, dim3((unsigned)blocks), dim3(256), (size_t)a.nb * sizeof(unsigned), st, a);
+template <int G>
+__device__ __forceinline__ void bin_out(const SpecFinalArgs& a, int b, int bin, int sub, double* cout_, double* pout) {
+  if (cout_ && a.coff_c) {
+    const double s = bin_total<G>(a.parts_c + (long long)b * a.M_c, a.coff_c, bin, sub);
+    if (sub == 0) cout_[bin] = s * a.fstats[8LL * b + 6];
+  }
+  if (pout && a.coff_p) {
+    const double s = bin_total<G>(a.parts_p + (long long)b * a.M_p, a.coff_p, bin, sub);
+    if (sub == 0) pout[bin] = s * a.pscale;
+  }
+}
+
+template <int G>
+__global__ void __launch_bounds__(SF_T) k_spec_final(SpecFinalArgs a) {
+  __shared__ unsigned long long red[2][SF_T];
+  constexpr int PER = SF_T / G;                        // bins per workgroup
+  const int b = blockIdx.y, tid = threadIdx.x;
+  double* cout_ = a.io ? a.io[b].cont_sum : field_ptr(a.cont_sum, a.nb, b);
+  double* pout = a.io ? a.io[b].pm1_sum : field_ptr(a.pm1_sum, a.nb, b);
+  const int last = (int)gridDim.x - 1;
+  if ((int)blockIdx.x < last) {
+    // bins 0 .. nb - 2, G lanes each (a group lies inside one wave: the shuffles stay uniform)
+    const int bin = (int)blockIdx.x * PER + tid / G;
+    if (bin < a.nb - 1) bin_out<G>(a, b, bin, tid % G, cout_, pout);
+    return;
+  }
+  if (a.nb >= 1 && tid < 64) bin_out<64>(a, b, a.nb - 1, tid, cout_, pout);   // the corner slot: one wave
+  if (!a.cpart) return;                                           // uniform over the workgroup
+  uint64_t* out = a.io ? a.io[b].counts : field_ptr(a.counts, 2, b);
+  if (!out) return;
+  const uint2* part = reinterpret_cast<const uint2*>(a.cpart) + (long long)b * a.ntc;
+  unsigned long long np = 0, nn = 0;
+  for (int t = tid; t < a.ntc; t += SF_T) {
+    const uint2 v = part[t];
+    np += v.x;
+    nn += v.y;
+  }
+  red[0][tid] = np;
+  red[1][tid] = nn;
+  __syncthreads();
+  for (int o = SF_T / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      red[0][tid] += red[0][tid + o];
+      red[1][tid] += red[1][tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+  }
+}
+
+hipError_t launch_spec_final(const SpecFinalArgs& a, int batch, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  // partials per bin (the larger of the two spectra's): a wave per bin from 64 on
+  const long long mc = a.coff_c ? a.M_c : 0, mp = a.coff_p ? a.M_p : 0;
+  const bool wide = (mc > mp ? mc : mp) > 64LL * a.nb;
+  const int per = wide ? SF_T / 64 : SF_T / 8;
+  // the regular bins (none without spectra), then the corner slot and the counts
+  const unsigned gx = (unsigned)((a.nb > 1 ? (a.nb - 1 + per - 1) / per : 0) + 1);
+  if (wide) hipLaunchKernelGGL((k_spec_final<64>), dim3(gx, (unsigned)batch), dim3(SF_T), 0, st, a);
+  else hipLaunchKernelGGL((k_spec_final<8>), dim3(gx, (unsigned)batch), dim3(SF_T), 0, st, a);
   return hipGetLastError();
 }
 

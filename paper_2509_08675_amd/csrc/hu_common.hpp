@@ -218,29 +218,59 @@ __device__ __forceinline__ float amp_sym(const FiltDev& f, const Axis0Geom& gm, 
   return H;
 }
 
-__device__ __forceinline__ int mode_bin(const BinDev& bd, const Axis0Geom& gm, const ColCoord& cc, int e) {
-  const int mt = e < gm.n0 / 2 ? e : e - gm.n0;
-  const long long q0 = (long long)mt * gm.dfac_0;
-  const long long s = cc.sfix + q0 * q0;
-  // 2D: angle of (q_x, q_y = q0); 3D: radial only
-  return bin_index(bd, s, cc.qx, gm.ndim == 2 ? q0 : 0);
+// ---------------------------------------------------------------------------------------------
+// Deterministic binning of one tile.  The per-mode power values w |X|^2 of the tile's C columns sit
+// in LDS (padded layout pw_index).  Thread (column cb, segment pb) takes the E consecutive modes
+// e = pb E .. pb E + E - 1 of its column, reads their tile-local bins j (the position of the mode's
+// bin in the tile's ascending list of distinct bins, from the per-geometry table ltab) and sums
+// each run of equal j in FP64 in mode order.  The runs of one bin are combined in integer
+// arithmetic, which does not depend on the order in which the atomics land:
+//   pass 1: hx[j] = the largest binary exponent of the bin's runs (integer maximum);
+//   pass 2: hq[j] += each run rounded to a multiple of 2^(hx[j] - 48), as an unsigned integer.
+// A run is below 2^hx[j], so it contributes less than 2^48 units, and a bin of one tile gathers
+// at most T E <= 2^15 runs: the sum stays below 2^63.  The tile's partial of bin j is then
+// hq[j] 2^(hx[j] - 48), the same bits for every schedule of the workgroup; its error is at most
+// 2^-48 of the bin's largest run per run.
+// ---------------------------------------------------------------------------------------------
+constexpr int HX_EMPTY = -100000;
+constexpr int HQ_SHIFT = 48;
+
+__device__ __forceinline__ unsigned long long run_to_fixed(double s, int emax) {
+  const double x = ldexp(s, HQ_SHIFT - emax);               // in [0, 2^48)
+  const double y = x + 4503599627370496.0;                  // + 2^52: the low mantissa bits hold rint(x)
+  return (unsigned long long)__double_as_longlong(y) - 0x4330000000000000ull;
 }
 
-// ---------------------------------------------------------------------------------------------
-// Run-length binning.  The per-mode power values w |X|^2 of the C columns sit in LDS (padded
-// layout pw_index).  Thread (c, p) walks the E consecutive modes e = p E .. p E + E - 1 of its
-// column, reads their bins from the per-geometry table (column-major [g][L], u16), sums in FP64
-// while the bin stays the same and adds each run to the LDS histogram with one atomic.
-// ---------------------------------------------------------------------------------------------
+template <bool PASS2>
+__device__ __forceinline__ void run_commit(int j, double s, int* hx, unsigned long long* hq) {
+  if (!(s > 0.0)) return;
+  if constexpr (!PASS2) atomicMax(hx + j, __builtin_amdgcn_frexp_exp(s));
+  else atomicAdd(hq + j, run_to_fixed(s, hx[j]));
+}
+
+template <int E, bool PASS2>
+__device__ __forceinline__ void runs_commit(const int (&loc)[E], const float (&v)[E], int* hx,
+                                            unsigned long long* hq) {
+  int cur = loc[0];
+  double acc = (double)v[0];
+#pragma unroll
+  for (int i = 1; i < E; ++i) {
+    if (loc[i] != cur) {
+      run_commit<PASS2>(cur, acc, hx, hq);
+      cur = loc[i];
+      acc = 0.0;
+    }
+    acc += (double)v[i];
+  }
+  run_commit<PASS2>(cur, acc, hx, hq);
+}
+
+// the E tile-local bins and power values of binning thread (cb, pb), all loads issued first
 template <int L, int E>
-__device__ __forceinline__ void bin_runs(const float* pw, double* hs, const uint16_t* __restrict__ table, int g, int p) {
-  const int e0 = p * E;
-  const uint16_t* t = table + (unsigned)(g * L + e0);
-  // every bin and power value of the thread's E modes first, so all their loads are in flight
-  // together (the histogram atomics below share LDS with the power values and would otherwise
-  // order each read after the previous atomic)
-  int bin[E];
-  float v[E];
+__device__ __forceinline__ void seg_read(const float* pwc, const uint16_t* __restrict__ ltab, int g, int pb,
+                                         int (&loc)[E], float (&v)[E]) {
+  const int e0 = pb * E;
+  const uint16_t* t = ltab + (unsigned)(g * L + e0);
   if constexpr ((L % 8) == 0 && (E % 8) == 0) {
     uint4 w[E / 8];
 #pragma unroll
@@ -249,43 +279,46 @@ __device__ __forceinline__ void bin_runs(const float* pw, double* hs, const uint
     for (int q = 0; q < E / 8; ++q) {
       const uint32_t ws[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
 #pragma unroll
-      for (int h = 0; h < 8; ++h) bin[8 * q + h] = (int)((ws[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
+      for (int h = 0; h < 8; ++h) loc[8 * q + h] = (int)((ws[h >> 1] >> (16 * (h & 1))) & 0xFFFFu);
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < E; ++i) bin[i] = (int)t[i];
+    for (int i = 0; i < E; ++i) loc[i] = (int)t[i];
   }
 #pragma unroll
-  for (int i = 0; i < E; ++i) v[i] = pw[pw_index(e0 + i)];
-  int cur = bin[0];
-  double acc = (double)v[0];
-#pragma unroll
-  for (int i = 1; i < E; ++i) {
-    if (bin[i] != cur) {
-      atomicAdd(hs + cur, acc);
-      cur = bin[i];
-      acc = 0.0;
-    }
-    acc += (double)v[i];
-  }
-  atomicAdd(hs + cur, acc);
+  for (int i = 0; i < E; ++i) v[i] = pwc[pw_index(e0 + i)];
 }
 
-// Binning of a tile's C columns from their power values in LDS.  Thread t walks segment t % P of
-// column t / P, so the lanes of one instruction span as few columns as possible: neighbouring
-// columns of a tile share most bins, and lanes of one LDS atomic that hit the same bin serialise.
-template <int L, int E, int C, int LP>
-__device__ __forceinline__ void bin_tile(const float* pw, double* hs, const uint16_t* __restrict__ table, int col0,
-                                         int ncol, int tid) {
+// The whole tile: both passes and the stores of the partials (thread j < nloc stores the partial of
+// local bin j at its position wpos[toff[tile] + j] and clears its slots for the next tile).  Called
+// by every thread of the workgroup after the power values are in LDS and a barrier; ends with the
+// LDS histogram cleared, without a final barrier.
+template <int L, int E, int C, int LP, int T>
+__device__ __forceinline__ void tile_bins(const float* pw, int* hx, unsigned long long* hq, const TileBinDev& tb,
+                                          int tile, int ncol, double* __restrict__ out, int tid) {
   constexpr int P = Plan<L>::P;
   const int cb = tid / P, pb = tid - cb * P;
-  if (cb < C && col0 + cb < ncol) bin_runs<L, E>(pw + cb * LP, hs, table, col0 + cb, pb);
-}
-
-__device__ __forceinline__ void hist_flush(const double* hs, int nb, double scale, double* out_sum, int tid, int T) {
-  for (int i = tid; i < nb; i += T) {
-    const double v = hs[i];
-    if (v != 0.0) atomicAdd(out_sum + i, v * scale);
+  const int g = tile * C + cb;
+  const bool act = cb < C && g < ncol;
+  // the tile's partial range and store positions first: their loads overlap the two passes
+  const unsigned j0 = tb.toff[tile];
+  const int nloc = (int)(tb.toff[tile + 1] - j0);
+  const unsigned wp0 = tid < nloc ? tb.wpos[j0 + tid] : 0u;
+  int loc[E];
+  float v[E];
+  if (act) {
+    seg_read<L, E>(pw + cb * LP, tb.ltab, g, pb, loc, v);
+    runs_commit<E, false>(loc, v, hx, hq);
+  }
+  __syncthreads();
+  if (act) runs_commit<E, true>(loc, v, hx, hq);
+  __syncthreads();
+  for (int j = tid; j < nloc; j += T) {
+    const int e = hx[j];
+    const unsigned long long q = hq[j];
+    out[j == tid ? wp0 : tb.wpos[j0 + j]] = e == HX_EMPTY ? 0.0 : ldexp((double)q, e - HQ_SHIFT);
+    hx[j] = HX_EMPTY;
+    hq[j] = 0ull;
   }
 }
 
@@ -294,12 +327,13 @@ __host__ __device__ constexpr size_t col_xchg_bytes() {
   return (size_t)ColTile<L, V>::C * ColTile<L, V>::RS * 8;
 }
 
+// LDS of an axis-0 pass that bins: the exchange buffer (the power values reuse it), then the tile
+// histogram (nloc_max exponents and fixed-point sums)
 template <int L, int V>
-__host__ __device__ constexpr size_t col_lds_bytes_t(int nb) {
-  // exchange buffer, or the padded power values plus the FP64 histogram
-  return col_xchg_bytes<L, V>() > (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4 + (size_t)nb * 8 + 8
-             ? col_xchg_bytes<L, V>()
-             : (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4 + (size_t)nb * 8 + 8;
+__host__ __device__ constexpr size_t col_bin_base() {
+  return ((col_xchg_bytes<L, V>() > (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4
+               ? col_xchg_bytes<L, V>()
+               : (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4) + 15) / 16 * 16;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -1,13 +1,14 @@
 // The fused axis-0 pass of the generator: forward FFT along the slowest axis, multiplication by
 // the symmetrised amplitude H_sym = sqrt(chi) (Eq. (8) with Eqs. (12)-(13)), the FP64 Parseval
 // statistics of Eq. (15), the continuous-field spectrum bins, and the inverse FFT along the same
-// axis -- one read and one write of the half spectrum.  Each workgroup leaves its partial sums;
-// k_finalize turns them into (mu, var, scale, offset) in a fixed order and rescales the
-// continuous bins to the normalised field.
+// axis -- one read and one write of the half spectrum.  Each workgroup leaves its partial sums
+// and its tile's bin partials; k_finalize turns the sums into (mu, var, scale, offset) in a fixed
+// order, and k_spec_final assembles the bins of the normalised field.
 #include "hu_common.hpp"
 
 namespace hu {
 
+// One tile of C columns of one field per workgroup.
 template <int L, int NDIM, int V, bool GEN>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
@@ -31,8 +32,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   fft_run<L, P, E, false>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
 
   // ---- filter and per-thread statistics
-  double* cont_out = a.io ? a.io[b].cont_sum : field_ptr(a.cont_sum, a.nb, b);
-  const bool do_bins = a.want_bins && cont_out != nullptr;
+  const bool do_bins = a.parts != nullptr;
   const FiltDev filt = a.io ? a.io[b].filt : a.filt;
   const ColCoord cc = col_coord(a.gm, valid ? g : 0);
   double gsum = 0.0, f0 = 0.0;
@@ -40,10 +40,14 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   // the exchange buffer is free once every thread has its transform in registers: the power
   // values of the continuous spectrum go to LDS as they are computed
   float* pw = reinterpret_cast<float*>(lds);
-  double* hs = reinterpret_cast<double*>(pw + ((C * LP + 1) & ~1));
+  int* hx = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + a.hx_off);
+  unsigned long long* hq = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(lds) + a.hq_off);
   if (do_bins) {
+    for (int j = tid; j < a.tb.nloc_max; j += T) {
+      hx[j] = HX_EMPTY;
+      hq[j] = 0ull;
+    }
     __syncthreads();
-    for (int i = tid; i < a.nb; i += T) hs[i] = 0.0;
   }
 #pragma unroll
   for (int s = 0; s < E; ++s) {
@@ -65,13 +69,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   lmax = wave_max(lmax);
   f0 = wave_sum(f0);
   if ((tid & 63) == 0) { red_d[tid >> 6] = gsum; red_f[tid >> 6] = lmax; red_d0[tid >> 6] = f0; }
-  // ---- continuous-spectrum histogram (run-length over contiguous modes of each column)
   __syncthreads();
-  if (do_bins) {
-    bin_tile<L, E, C, LP>(pw, hs, a.table, (int)tile * C, a.gm.ncol, tid);
-    __syncthreads();
-    hist_flush(hs, a.nb, 1.0, cont_out, tid, T);
-  }
   if (tid == 0) {
     double gs = 0.0, fz = 0.0;
     float lm = -1.0e30f;
@@ -81,6 +79,10 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
     part[1] = fz;
     part[2] = (double)lm;
     part[3] = 0.0;
+  }
+  // ---- continuous-spectrum bins of the tile -> parts[b][toff[tile] ..] (deterministic)
+  if (do_bins) {
+    tile_bins<L, E, C, LP, T>(pw, hx, hq, a.tb, (int)tile, a.gm.ncol, a.parts + (long long)b * a.tb.M, tid);
   }
 
   // ---- inverse transform along axis 0 (first radix = last forward radix: no exchange needed)
@@ -92,18 +94,16 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
 
 // ---------------------------------------------------------------------------------------------
 // finalize: one workgroup per field turns the filter pass's partials into mu, var and the
-// normalisation constants (Eq. (15) via Parseval) with a fixed-order reduction, and rescales
-// the continuous-field bins to the spectrum of the normalised field.
+// normalisation constants (Eq. (15) via Parseval) with a fixed-order reduction, and the factor
+// that turns the continuous-field bins into the spectrum of the normalised field.
 // ---------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
   __shared__ double sg[256], sf[256];
   __shared__ float sm[256];
-  __shared__ double fac;
   const int b = blockIdx.x, tid = threadIdx.x;
   const double* part = a.partials + (long long)b * a.ntiles * 4;
   const double sigma_f = a.io ? a.io[b].sigma_f : a.sigma_f;
   double* stats_out = a.io ? a.io[b].stats : field_ptr(a.stats, 4, b);
-  double* cont_out = a.io ? a.io[b].cont_sum : field_ptr(a.cont_sum, a.nb, b);
   double G = 0.0, F0 = 0.0;
   float lm = -1.0e30f;
 #pragma unroll 4
@@ -144,13 +144,6 @@ __global__ void __launch_bounds__(256) k_finalize(FinalizeArgs a) {
     if (stats_out) {
       stats_out[0] = mu; stats_out[1] = var; stats_out[2] = lmx; stats_out[3] = fs[3];
     }
-    fac = fs[6];
-  }
-  __syncthreads();
-  if (cont_out) {
-    const double f = fac;
-#pragma unroll 8
-    for (int i = tid; i < a.nb; i += 256) cont_out[i] *= f;
   }
 }
 
@@ -160,9 +153,14 @@ hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st) {
 }
 
 template <int L, int V>
-static hipError_t launch_cols_filter_L(const FilterArgs& a, hipStream_t st) {
+static hipError_t launch_cols_filter_L(FilterArgs a, hipStream_t st) {
   constexpr int T = ColTile<L, V>::T;
-  const size_t lds = a.want_bins ? col_lds_bytes_t<L, V>(a.nb) : col_xchg_bytes<L, V>();
+  size_t lds = col_xchg_bytes<L, V>();
+  if (a.parts) {
+    a.hx_off = (int)col_bin_base<L, V>();
+    a.hq_off = a.hx_off + (a.tb.nloc_max * 4 + 15) / 16 * 16;
+    lds = (size_t)a.hq_off + (size_t)a.tb.nloc_max * 8;
+  }
   // the tabulated-form and FP64 branches only in the instantiation launched when a field may use one
   if (a.gm.ndim == 2) {
     if (a.any_gen) hipLaunchKernelGGL((k_cols_filter<L, 2, V, true>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
@@ -172,6 +170,15 @@ static hipError_t launch_cols_filter_L(const FilterArgs& a, hipStream_t st) {
     else hipLaunchKernelGGL((k_cols_filter<L, 3, V, false>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
   }
   return hipGetLastError();
+}
+
+int col_width(int L, int variant) {
+  switch (L) {
+#define X(LL) case LL: return variant ? ColTile<LL, 1>::C : ColTile<LL, 0>::C;
+    HU_COL_LENGTHS(X)
+#undef X
+    default: return 0;
+  }
 }
 
 hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st) {

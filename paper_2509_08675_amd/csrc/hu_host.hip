@@ -3,7 +3,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <tuple>
@@ -19,6 +21,20 @@ std::mutex g_mu;
 std::map<std::pair<int, int>, float2*> g_tw, g_tw2;
 std::map<std::pair<int, int>, double*> g_edges;
 std::map<std::vector<long long>, BinGeo> g_bingeo;
+
+// Host bin tables of a grid and bin layout (built once, kept for the tile tables of other widths)
+struct BinHost {
+  std::vector<uint16_t> table;                 // [ncol][n0]: bin of each half-spectrum mode
+  std::vector<unsigned long long> counts;      // [nb]: modes per bin with multiplicity
+};
+struct TileHost {
+  std::vector<uint16_t> ltab;                  // [ncol][n0]: position in the tile's list of distinct bins
+  std::vector<uint32_t> toff, coff, cpos, wpos;   // wpos: the inverse of cpos
+  int nloc_max = 0;
+};
+std::map<std::vector<long long>, std::shared_ptr<BinHost>> g_binhost;    // {nd, n0, n1, n2, nr, na}
+std::map<std::vector<long long>, std::shared_ptr<TileHost>> g_tilehost;  // ... + C
+std::map<std::vector<long long>, TileBinDev> g_tiledev;                  // device + ... + C
 
 int current_device() {
   int d = 0;
@@ -40,24 +56,31 @@ int make_table(int n, int count, float2** out) {
   return HU_OK;
 }
 
+// e_j = (cos j pi / A, sin j pi / A), j = 1..A-1, in FP64; the 45, 90 and 135 degree edges exact.
+// h[0 .. m) holds the x components, h[m .. 2m) the y components, m = max(A - 1, 1).
+std::vector<double> host_edges(int na) {
+  const int m = na > 1 ? na - 1 : 1;
+  std::vector<double> h(2 * m, 0.0);
+  const double c = std::cos(M_PI / 4.0);
+  for (int j = 1; j < na; ++j) {
+    double x, y;
+    if (4 * j == na) { x = c; y = c; }
+    else if (2 * j == na) { x = 0.0; y = 1.0; }
+    else if (4 * j == 3 * na) { x = -c; y = c; }
+    else { x = std::cos(j * M_PI / na); y = std::sin(j * M_PI / na); }
+    h[j - 1] = x;
+    h[m + j - 1] = y;
+  }
+  return h;
+}
+
 int get_edges(int na, const double** ex, const double** ey) {
   std::lock_guard<std::mutex> lk(g_mu);
   const int m = na > 1 ? na - 1 : 1;
   auto key = std::make_pair(current_device(), na);
   auto it = g_edges.find(key);
   if (it == g_edges.end()) {
-    // e_j = (cos j pi / A, sin j pi / A), j = 1..A-1; the 45, 90 and 135 degree edges exact
-    std::vector<double> h(2 * m, 0.0);
-    const double c = std::cos(M_PI / 4.0);
-    for (int j = 1; j < na; ++j) {
-      double x, y;
-      if (4 * j == na) { x = c; y = c; }
-      else if (2 * j == na) { x = 0.0; y = 1.0; }
-      else if (4 * j == 3 * na) { x = -c; y = c; }
-      else { x = std::cos(j * M_PI / na); y = std::sin(j * M_PI / na); }
-      h[j - 1] = x;
-      h[m + j - 1] = y;
-    }
+    const std::vector<double> h = host_edges(na);
     double* d = nullptr;
     if (hipMalloc(&d, sizeof(double) * 2 * m) != hipSuccess) return HU_ERR_HIP;
     if (hipMemcpy(d, h.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice) != hipSuccess) return HU_ERR_HIP;
@@ -322,12 +345,16 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan) {
+int tile_partials(const Geom& g, const hu_bins& bins, int C, int* M, int* nloc_max);
+
+int layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan, const hu_bins* bins, Layout* out) {
   Layout L{};
   size_t off = 0;
   L.spec = off;
   off += up256((size_t)batch * g.Nhp * sizeof(float2));
-  L.tiles = col_tiles(g.n[0], plan.v[P_FILTER], g.Nh / g.n[0]);
+  (void)plan;
+  L.tiles = 0;                                    // filter-pass tiles of either tile width
+  for (int v = 0; v < NVARIANT; ++v) L.tiles = std::max(L.tiles, col_tiles(g.n[0], v, g.Nh / g.n[0]));
   if (need_stats) {
     L.partials = off;
     off += up256((size_t)batch * L.tiles * 4 * sizeof(double));
@@ -338,8 +365,28 @@ Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan) {
     L.cpart = off;
     off += up256((size_t)batch * (rt0 > rt1 ? rt0 : rt1) * 2 * sizeof(uint32_t));
   }
+  if (bins) {
+    // room for the partials of either tile width (the plan of a later call may differ)
+    int M = 0;
+    for (int v = 0; v < NVARIANT; ++v) {
+      int m = 0, nl = 0;
+      HU_TRY(tile_partials(g, *bins, col_width(g.n[0], v), &m, &nl));
+      M = m > M ? m : M;
+    }
+    if (need_stats) {
+      L.Mc = M;
+      L.parts_c = off;
+      off += up256((size_t)batch * M * sizeof(double));
+    }
+    L.Mp = M;
+    L.parts_p = off;
+    off += up256((size_t)batch * M * sizeof(double));
+  }
+  L.queue = off;
+  off += up256(NQUEUE * sizeof(unsigned));
   L.total = off;
-  return L;
+  *out = L;
+  return HU_OK;
 }
 
 // workgroups of a kernel that fit on the device at once (cached per device, kernel and LDS size)
@@ -466,8 +513,143 @@ int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd) {
   return get_edges(b.n_angular, &bd->ex, &bd->ey);
 }
 
-int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t st, BinGeo* out) {
-  std::vector<long long> key = {current_device(), g.nd, g.n[0], g.n[1], g.n[2], bins.n_radial, bins.n_angular};
+// ---------------------------------------------------------------------------------------------
+// Bin tables, built on the host.  The bin of a half-spectrum mode (exact integer radial rule and
+// FP64 angular edge tests with separately rounded products; the library is compiled without
+// multiply-add contraction): with D = lcm of the dims, q_i = m~_i D / n_i (q_x = m_x on the
+// halved axis), r = the largest integer with r^2 D^2 <= 4 R^2 sum q_i^2; r >= R goes to the corner
+// slot R A; in 2D the angular bin counts the edges e_j with e_jx q_y - e_jy q_x >= 0 after folding
+// q to q_y >= 0 (q_y = 0 with q_x >= 0 on the half spectrum), the DC mode in bin 0.
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+int host_bin(long long s, long long qx, long long qy, long long D2, long long fourR2, int nr, int na,
+             const std::vector<double>& ed) {
+  const long long rhs = fourR2 * s;
+  long long r = (long long)std::sqrt((double)rhs / (double)D2);
+  while (r > 0 && r * r * D2 > rhs) --r;
+  while ((r + 1) * (r + 1) * D2 <= rhs) ++r;
+  if (r >= nr) return nr * na;
+  int a = 0;
+  if (na > 1 && s != 0) {
+    if (qy < 0) { qy = -qy; qx = -qx; }
+    const double dx = (double)qx, dy = (double)qy;
+    const int m = na - 1;
+    for (int j = 0; j < m; ++j) {
+      const double t1 = ed[j] * dy;
+      const double t2 = ed[m + j] * dx;
+      if (t1 - t2 >= 0.0) ++a;
+    }
+  }
+  return (int)r * na + a;
+}
+
+long long signed_index(long long m, long long n) { return m < n / 2 ? m : m - n; }
+
+std::shared_ptr<BinHost> bin_host(const Geom& g, const hu_bins& bins) {
+  const std::vector<long long> key = {g.nd, g.n[0], g.n[1], g.n[2], bins.n_radial, bins.n_angular};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_binhost.find(key);
+    if (it != g_binhost.end()) return it->second;
+  }
+  const Axis0Geom a = axis0(g);
+  const int nr = bins.n_radial, na = bins.n_angular, nb = nr * na + 1;
+  const std::vector<double> ed = host_edges(na);
+  const long long D2 = g.D * g.D, fourR2 = 4LL * nr * nr;
+  auto h = std::make_shared<BinHost>();
+  h->table.resize((size_t)a.ncol * a.n0);
+  h->counts.assign(nb, 0ull);
+  for (int gc = 0; gc < a.ncol; ++gc) {
+    const int my = g.nd == 3 ? gc / a.nxh : 0;
+    const int mx = gc - my * (g.nd == 3 ? a.nxh : 0);
+    const long long qx = (long long)mx * a.dfac_x;
+    const long long qy = g.nd == 3 ? signed_index(my, a.ny) * a.dfac_y : 0;
+    const unsigned wm = (mx == 0 || 2 * mx == a.nx) ? 1u : 2u;
+    uint16_t* row = h->table.data() + (size_t)gc * a.n0;
+    for (int e = 0; e < a.n0; ++e) {
+      const long long q0 = signed_index(e, a.n0) * a.dfac_0;
+      const long long s = qx * qx + qy * qy + q0 * q0;
+      const int bin = host_bin(s, qx, g.nd == 2 ? q0 : 0, D2, fourR2, nr, na, ed);
+      row[e] = (uint16_t)bin;
+      h->counts[bin] += wm;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_binhost.emplace(key, h).first->second;
+}
+
+// Tile tables for tiles of C columns: for tile t, its distinct bins in ascending order (their
+// partials occupy [toff[t], toff[t + 1])), each mode's position in that list, and per bin the
+// partial positions in tile order (CSR).
+std::shared_ptr<TileHost> tile_host(const Geom& g, const hu_bins& bins, int C) {
+  const std::vector<long long> key = {g.nd, g.n[0], g.n[1], g.n[2], bins.n_radial, bins.n_angular, C};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tilehost.find(key);
+    if (it != g_tilehost.end()) return it->second;
+  }
+  const std::shared_ptr<BinHost> bh = bin_host(g, bins);
+  const Axis0Geom a = axis0(g);
+  const int nb = bins.n_radial * bins.n_angular + 1;
+  const int ntiles = (a.ncol + C - 1) / C;
+  auto th = std::make_shared<TileHost>();
+  th->ltab.resize((size_t)a.ncol * a.n0);
+  th->toff.assign(ntiles + 1, 0u);
+  std::vector<int> mark(nb, -1), jpos(nb, 0);
+  std::vector<int> lst, pbin;
+  for (int t = 0; t < ntiles; ++t) {
+    const int g0 = t * C, g1 = g0 + C < a.ncol ? g0 + C : a.ncol;
+    lst.clear();
+    for (size_t i = (size_t)g0 * a.n0; i < (size_t)g1 * a.n0; ++i) {
+      const int b = bh->table[i];
+      if (mark[b] != t) {
+        mark[b] = t;
+        lst.push_back(b);
+      }
+    }
+    std::sort(lst.begin(), lst.end());
+    for (size_t j = 0; j < lst.size(); ++j) {
+      jpos[lst[j]] = (int)j;
+      pbin.push_back(lst[j]);
+    }
+    for (size_t i = (size_t)g0 * a.n0; i < (size_t)g1 * a.n0; ++i) th->ltab[i] = (uint16_t)jpos[bh->table[i]];
+    th->toff[t + 1] = th->toff[t] + (uint32_t)lst.size();
+    th->nloc_max = std::max(th->nloc_max, (int)lst.size());
+  }
+  th->coff.assign(nb + 1, 0u);
+  for (int b : pbin) th->coff[b + 1]++;
+  for (int b = 0; b < nb; ++b) th->coff[b + 1] += th->coff[b];
+  th->cpos.resize(pbin.size());
+  std::vector<uint32_t> cur(th->coff.begin(), th->coff.end() - 1);
+  for (size_t i = 0; i < pbin.size(); ++i) th->cpos[cur[pbin[i]]++] = (uint32_t)i;
+  th->wpos.resize(pbin.size());
+  for (size_t k = 0; k < pbin.size(); ++k) th->wpos[th->cpos[k]] = (uint32_t)k;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_tilehost.emplace(key, th).first->second;
+}
+
+template <class T>
+int upload(const std::vector<T>& h, T** d) {
+  const size_t n = h.empty() ? 1 : h.size();
+  if (hipMalloc(d, sizeof(T) * n) != hipSuccess) return HU_ERR_HIP;
+  if (!h.empty() && hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return HU_ERR_HIP;
+  return HU_OK;
+}
+
+}  // namespace
+
+int tile_partials(const Geom& g, const hu_bins& bins, int C, int* M, int* nloc_max) {
+  if (C < 1) return HU_ERR_SIZE;
+  const std::shared_ptr<TileHost> th = tile_host(g, bins, C);
+  *M = (int)th->toff.back();
+  *nloc_max = th->nloc_max;
+  return HU_OK;
+}
+
+int get_bingeo(const Geom& g, const hu_bins& bins, BinGeo* out) {
+  const std::vector<long long> key = {current_device(), g.nd, g.n[0], g.n[1], g.n[2], bins.n_radial, bins.n_angular};
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_bingeo.find(key);
@@ -476,30 +658,54 @@ int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t
       return HU_OK;
     }
   }
-  const int nb = bins.n_radial * bins.n_angular + 1;
+  const std::shared_ptr<BinHost> bh = bin_host(g, bins);
   BinGeo geo{nullptr, nullptr};
-  HU_HIP(hipMalloc(&geo.counts, sizeof(unsigned long long) * nb));
-  HU_HIP(hipMalloc(&geo.table, sizeof(uint16_t) * g.Nh));
-  HU_HIP(launch_zero_u64(reinterpret_cast<uint64_t*>(geo.counts), nb, st));
-  BinGeomArgs ba{};
-  ba.Nh = g.Nh;
-  ba.gm = axis0(g);
-  ba.bd = bd;
-  ba.nb = nb;
-  ba.table = geo.table;
-  ba.counts = geo.counts;
-  HU_HIP(launch_bin_geom(ba, st));
-  HU_HIP(hipStreamSynchronize(st));          // complete before any stream can use it
+  HU_TRY(upload(bh->table, &geo.table));
+  HU_TRY(upload(bh->counts, &geo.counts));
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_bingeo.find(key);
   if (it != g_bingeo.end()) {                // another thread built it meanwhile
     (void)hipFree(geo.counts);
-    if (geo.table) (void)hipFree(geo.table);
+    (void)hipFree(geo.table);
     *out = it->second;
     return HU_OK;
   }
   g_bingeo.emplace(key, geo);
   *out = geo;
+  return HU_OK;
+}
+
+int get_tilebins(const Geom& g, const hu_bins& bins, int C, TileBinDev* out) {
+  const std::vector<long long> key = {current_device(), g.nd, g.n[0], g.n[1], g.n[2], bins.n_radial, bins.n_angular, C};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tiledev.find(key);
+    if (it != g_tiledev.end()) {
+      *out = it->second;
+      return HU_OK;
+    }
+  }
+  if (C < 1) return HU_ERR_SIZE;
+  const std::shared_ptr<TileHost> th = tile_host(g, bins, C);
+  uint16_t* ltab = nullptr;
+  uint32_t *toff = nullptr, *coff = nullptr, *wpos = nullptr;
+  HU_TRY(upload(th->ltab, &ltab));
+  HU_TRY(upload(th->toff, &toff));
+  HU_TRY(upload(th->wpos, &wpos));
+  HU_TRY(upload(th->coff, &coff));
+  TileBinDev d{ltab, toff, wpos, coff, th->nloc_max, (int)th->toff.back()};
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_tiledev.find(key);
+  if (it != g_tiledev.end()) {
+    (void)hipFree(ltab);
+    (void)hipFree(toff);
+    (void)hipFree(coff);
+    (void)hipFree(wpos);
+    *out = it->second;
+    return HU_OK;
+  }
+  g_tiledev.emplace(key, d);
+  *out = d;
   return HU_OK;
 }
 
@@ -513,12 +719,19 @@ int tables_ready(const Geom& g, const hu_bins* bins) {
     if (!g_edges.count({dev, bins->n_angular})) return HU_ERR_TABLES;
     const std::vector<long long> key = {dev, g.nd, g.n[0], g.n[1], g.n[2], bins->n_radial, bins->n_angular};
     if (!g_bingeo.count(key)) return HU_ERR_TABLES;
+    for (int v = 0; v < NVARIANT; ++v) {
+      std::vector<long long> kt = key;
+      kt.push_back(col_width(g.n[0], v));
+      if (!g_tiledev.count(kt)) return HU_ERR_TABLES;
+    }
   }
   return HU_OK;
 }
 
-// every table a class needs, created before any launch (and before a graph capture)
+// every table a class needs, created before any launch (and before a graph capture); the tile
+// tables for both tile widths
 int prepare_tables(const Geom& g, const hu_bins* bins, hipStream_t st) {
+  (void)st;
   const float2 *a, *b;
   HU_TRY(get_tw(g.nx / 2, &a));
   HU_TRY(get_tw2(g.nx / 2, &b));
@@ -527,8 +740,10 @@ int prepare_tables(const Geom& g, const hu_bins* bins, hipStream_t st) {
   if (bins) {
     BinDev bd{};
     BinGeo geo;
+    TileBinDev tb;
     HU_TRY(make_bindev(g, *bins, &bd));
-    HU_TRY(get_bingeo(g, *bins, bd, st, &geo));
+    HU_TRY(get_bingeo(g, *bins, &geo));
+    for (int v = 0; v < NVARIANT; ++v) HU_TRY(get_tilebins(g, *bins, col_width(g.n[0], v), &tb));
   }
   return HU_OK;
 }
@@ -586,11 +801,13 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   HU_TRY(get_tw(g.n[0], &tw_0));
   if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
   const int nb = r.bins ? r.bins->n_radial * r.bins->n_angular + 1 : 0;
-  BinDev bd{};
   BinGeo geo{nullptr, nullptr};
+  TileBinDev tb_c{}, tb_p{};
   if (r.bins) {
-    HU_TRY(make_bindev(g, *r.bins, &bd));
-    HU_TRY(get_bingeo(g, *r.bins, bd, st, &geo));
+    HU_TRY(get_bingeo(g, *r.bins, &geo));
+    HU_TRY(get_tilebins(g, *r.bins, col_width(g.n[0], r.plan.v[P_FILTER]), &tb_c));
+    HU_TRY(get_tilebins(g, *r.bins, col_width(g.n[0], r.plan.v[P_BIN]), &tb_p));
+    if (tb_c.M > r.lay.Mc || tb_p.M > r.lay.Mp) return HU_ERR_WORKSPACE;
   }
   const bool want_cont = batch_mode ? (r.want_cont && r.bins) : (o.cont_sum != nullptr);
   const bool want_pm1 = r.thresh && (batch_mode ? (r.want_pm1_spec && r.bins) : (o.pm1_sum != nullptr));
@@ -598,9 +815,13 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   float2* spec = reinterpret_cast<float2*>(r.work + r.lay.spec);
   double* partials = reinterpret_cast<double*>(r.work + r.lay.partials);
   double* fstats = reinterpret_cast<double*>(r.work + r.lay.fstats);
+  double* parts_c = reinterpret_cast<double*>(r.work + r.lay.parts_c);
+  double* parts_p = reinterpret_cast<double*>(r.work + r.lay.parts_p);
+  unsigned* queue = reinterpret_cast<unsigned*>(r.work + r.lay.queue);
   const uint32_t* cnt_src = reinterpret_cast<const uint32_t*>(geo.counts);
 
-  // pass A: noise -> R2C rows; block 0 of each field sets up that field's accumulators
+  // pass A: noise -> R2C rows; block 0 of each field sets up that field's bin counts, block (0, 0)
+  // clears the work counters of the persistent passes
   RowsArgs ra{};
   ra.spec = spec;
   ra.Nh = g.Nhp;
@@ -612,13 +833,13 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   ra.io = r.io;
   ra.nb = nb;
   ra.cnt_src = cnt_src;
+  ra.zero = queue;
+  ra.nzero = NQUEUE;
   if (!batch_mode) {
     for (int i = 0; i < B; ++i) ra.seeds[i] = r.seeds[i];
     int fs = 0;
-    if (o.cont_sum) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.cont_sum), nullptr, 2 * nb};
     if (o.cont_cnt) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.cont_cnt), cnt_src, 2 * nb};
-    if (o.pm1_sum) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_sum), nullptr, 2 * nb};
-    if (o.pm1_cnt) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_cnt), cnt_src, 2 * nb};
+    if (o.pm1_cnt && r.thresh) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_cnt), cnt_src, 2 * nb};
     ra.fill_spans = fs;
   }
   HU_HIP(timed("rows_r2c_noise", st, [&] { return launch_rows_r2c(Lrow, SRC_NOISE, r.plan.v[P_R2C], ra, B, st); }));
@@ -645,14 +866,12 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
                     : col_sched(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B);
   if (!batch_mode) fa.filt = filt_dev(r.filt, g);
   fa.io = r.io;
-  fa.bd = bd;
-  fa.nb = nb;
-  fa.table = geo.table;
+  fa.tb = tb_c;
+  fa.parts = want_cont ? parts_c : nullptr;
   fa.tw = tw_0;
   fa.partials = partials;
-  fa.cont_sum = batch_mode ? nullptr : o.cont_sum;
-  fa.want_bins = want_cont ? 1 : 0;
   fa.any_gen = (batch_mode ? r.any_gen : filt_general(r.filt, g)) ? 1 : 0;
+  if (fa.sc.ntiles > r.lay.tiles) return HU_ERR_WORKSPACE;
   HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], r.plan.v[P_FILTER], fa, st); }));
   FinalizeArgs fz{};
   fz.partials = partials;
@@ -661,8 +880,6 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fz.sigma_f = batch_mode ? 1.0 : r.filt.sigma_f;
   fz.fstats = fstats;
   fz.stats = batch_mode ? nullptr : o.stats;
-  fz.cont_sum = batch_mode ? nullptr : o.cont_sum;
-  fz.nb = nb;
   fz.io = r.io;
   HU_HIP(timed("finalize", st, [&] { return launch_finalize(fz, B, st); }));
 
@@ -688,29 +905,76 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   za.cpart = want_counts ? cpart : nullptr;
   HU_HIP(timed(r.thresh ? "rows_c2r_thresh" : "rows_c2r", st,
                [&] { return launch_rows_c2r(Lrow, r.thresh, r.plan.v[P_C2R], za, B, st); }));
-  if (want_counts) {
-    CountFinalArgs cf{cpart, row_tiles(Lrow, r.plan.v[P_C2R], g.nrows), batch_mode ? nullptr : o.counts, r.io};
-    HU_HIP(timed("count_final", st, [&] { return launch_count_final(cf, B, st); }));
-  }
 
   if (want_pm1) {
     if (g.nd == 3) HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st); }));
     BinArgs ba{};
+    ba.ntiles = col_tiles(g.n[0], r.plan.v[P_BIN], g.Nh / g.n[0]);
+    ba.batch = B;
+    ba.q = ItemQueue{queue + Q_BIN, ba.ntiles * B, 8};
+    ba.sc = col_sched_fields(g.n[0], r.plan.v[P_BIN], g.Nh / g.n[0], B);
     ba.spec = spec;
     ba.Nh = g.Nhp;
-    ba.N = g.N;
     ba.gm = axis0(g);
-    ba.sc = g.nd == 2 ? col_sched_fields(g.n[0], r.plan.v[P_BIN], ba.gm.ncol, B)
-                      : col_sched(g.n[0], r.plan.v[P_BIN], ba.gm.ncol, B);
-    ba.bd = bd;
-    ba.nb = nb;
-    ba.table = geo.table;
+    ba.tb = tb_p;
+    ba.parts = parts_p;
     ba.tw = tw_0;
-    ba.sum = batch_mode ? nullptr : o.pm1_sum;
-    ba.io = r.io;
     HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], r.plan.v[P_BIN], ba, st); }));
+  }
+  if (want_cont || want_pm1 || want_counts) {
+    SpecFinalArgs sf{};
+    sf.nb = nb;
+    if (want_cont) {
+      sf.coff_c = tb_c.coff;
+      sf.parts_c = parts_c;
+      sf.M_c = tb_c.M;
+      sf.fstats = fstats;
+      sf.cont_sum = batch_mode ? nullptr : o.cont_sum;
+    }
+    if (want_pm1) {
+      sf.coff_p = tb_p.coff;
+      sf.parts_p = parts_p;
+      sf.M_p = tb_p.M;
+      sf.pscale = 1.0 / (double)g.N;
+      sf.pm1_sum = batch_mode ? nullptr : o.pm1_sum;
+    }
+    if (want_counts) {
+      sf.cpart = cpart;
+      sf.ntc = row_tiles(Lrow, r.plan.v[P_C2R], g.nrows);
+      sf.counts = batch_mode ? nullptr : o.counts;
+    }
+    sf.io = r.io;
+    HU_HIP(timed("spec_final", st, [&] { return launch_spec_final(sf, B, st); }));
   }
   return HU_OK;
 }
 
 }  // namespace hu
+
+extern "C" int hu_debug_bin_tables(hu_dims dims, hu_bins bins, int32_t variant, int32_t* sizes, uint16_t* table,
+                                   uint16_t* ltab, uint32_t* toff, uint32_t* coff, uint32_t* cpos) {
+  using namespace hu;
+  Geom g;
+  HU_TRY(make_geom(dims, &g));
+  HU_TRY(check_bins(&bins, g.nd));
+  if (variant != 0 && variant != 1) return HU_ERR_ARG;
+  const int C = col_width(g.n[0], variant);
+  if (C < 1) return HU_ERR_SIZE;
+  const std::shared_ptr<BinHost> bh = bin_host(g, bins);
+  const std::shared_ptr<TileHost> th = tile_host(g, bins, C);
+  const Axis0Geom a = axis0(g);
+  if (sizes) {
+    sizes[0] = a.ncol;
+    sizes[1] = a.n0;
+    sizes[2] = (int32_t)th->toff.size() - 1;
+    sizes[3] = (int32_t)th->toff.back();
+    sizes[4] = th->nloc_max;
+    sizes[5] = C;
+  }
+  if (table) std::memcpy(table, bh->table.data(), bh->table.size() * sizeof(uint16_t));
+  if (ltab) std::memcpy(ltab, th->ltab.data(), th->ltab.size() * sizeof(uint16_t));
+  if (toff) std::memcpy(toff, th->toff.data(), th->toff.size() * sizeof(uint32_t));
+  if (coff) std::memcpy(coff, th->coff.data(), th->coff.size() * sizeof(uint32_t));
+  if (cpos) std::memcpy(cpos, th->cpos.data(), th->cpos.size() * sizeof(uint32_t));
+  return HU_OK;
+}

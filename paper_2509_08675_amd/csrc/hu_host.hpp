@@ -38,10 +38,15 @@ struct TunePlan {
   int v[NPASS];
 };
 
+// Workspace of one class: half spectra, the filter pass's per-tile statistics, per-field stats,
+// the last row pass's per-tile sign counts, the tile partials of the continuous (parts_c) and the
+// +-1 (parts_p) spectra, and the work counter of the persistent binning pass.
 struct Layout {
-  size_t spec, partials, fstats, cpart, total;
+  size_t spec, partials, fstats, cpart, parts_c, parts_p, queue, total;
   int tiles;
+  int Mc, Mp;                    // tile partials per field of each spectrum (0: none)
 };
+enum { Q_BIN = 0, NQUEUE = 1 };
 
 struct BinGeo {
   uint16_t* table;               // [ncol][n0] bin of each mode
@@ -53,7 +58,10 @@ int check_filter(const hu_filter* f, int nd);
 int check_bins(const hu_bins* b, int nd);
 bool aligned(const void* p, size_t a);
 size_t up256(size_t x);
-Layout layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan);
+// need_stats: the generator's layout (filter statistics, sign counts, both spectra); otherwise the
+// binning of a stored input.  bins: null when no spectrum is binned.  Builds the host bin tables of
+// the grid on first use (no device work).
+int layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan, const hu_bins* bins, Layout* out);
 // the sum of the ln chi terms' magnitudes above which the filter is evaluated in FP64
 constexpr double FP32_FILTER_TERMS = 32.0;
 FiltDev filt_dev(const hu_filter& f, const Geom& g);
@@ -63,7 +71,9 @@ Axis0Geom axis0(const Geom& g);
 int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd);
 int get_tw(int L, const float2** tw);
 int get_tw2(int L, const float2** tw2);
-int get_bingeo(const Geom& g, const hu_bins& bins, const BinDev& bd, hipStream_t st, BinGeo* out);
+int get_bingeo(const Geom& g, const hu_bins& bins, BinGeo* out);
+// the tile-local bin tables of the axis-0 passes for tiles of C columns (device copy)
+int get_tilebins(const Geom& g, const hu_bins& bins, int C, TileBinDev* out);
 int prepare_tables(const Geom& g, const hu_bins* bins, hipStream_t st);
 // HU_OK when every table prepare_tables would build already exists on the current device,
 // else HU_ERR_TABLES (allocates nothing)

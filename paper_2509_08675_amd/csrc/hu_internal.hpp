@@ -53,13 +53,15 @@ struct RowsArgs {
   int tiled;               // 2D column-group layout (TW = 4) or row-major (3D)
   uint64_t seeds[MAX_CHUNK];
   const FieldIO* io;       // per-field seeds and accumulators (batch path) or null
-  int nb;                  // with io: bins + 1, for clearing the per-field spectra
+  int nb;                  // with io: bins + 1, for the per-field bin counts
   const uint32_t* cnt_src; // with io: precomputed bin counts (nb uint64)
   const void* src;         // real input for the load variants, [B][N]
   const float2* tw;        // stage twiddle table of the row length (StageTab layout)
   const float2* tw2;       // exp(-2 pi i k / 2L), k < L
   FillSpan fill[6];
   int fill_spans;
+  unsigned* zero;          // words cleared by block (0, 0) before the later passes read them
+  int nzero;               // (the work counter of the persistent binning pass)
 };
 
 struct ColsArgs {
@@ -82,20 +84,40 @@ struct Axis0Geom {
   long long dfac_0, dfac_y, dfac_x;   // D / n_i, D = lcm of the dims
 };
 
+// Tile-local bin tables of the axis-0 passes for one tile width.  The modes of a tile touch few of
+// the bins; each tile has one partial sum per distinct bin (in ascending bin order), stored grouped
+// by bin so that a bin's partials are contiguous, and the partials of a bin are combined in a
+// fixed order: the binned spectra are the same bits on every run.
+struct TileBinDev {
+  const uint16_t* ltab;    // [ncol][n0]: position of the mode's bin in its tile's list of distinct bins
+  const uint32_t* toff;    // [ntiles + 1]: partials i = toff[t] .. toff[t+1]-1 belong to tile t
+  const uint32_t* wpos;    // [M]: where partial i is stored: grouped by bin, tile order inside a bin
+  const uint32_t* coff;    // [nb + 1]: the stored partials of bin k are coff[k] .. coff[k+1]-1
+  int nloc_max;            // most distinct bins in one tile
+  int M;                   // partials per field
+};
+
+// Dynamic schedule of the persistent binning pass: the items (tile, field), tile-major, are
+// taken in chunks (shrinking towards the end) from a counter that the first pass of the same
+// launch sequence cleared.
+struct ItemQueue {
+  unsigned* counter;
+  int nitems;              // ntiles * batch
+  int chunk_max;
+};
+
 struct FilterArgs {
   ColSched sc;
   float2* spec;
   long long Nh, N;
   Axis0Geom gm;
   FiltDev filt;
-  const FieldIO* io;       // per-field filter and continuous-spectrum output (batch path) or null
-  BinDev bd;
-  int nb;                  // bins + 1 (corner slot)
-  const uint16_t* table;   // bin of each mode, [ncol][n0], or null (computed)
+  const FieldIO* io;       // per-field filter (batch path) or null
+  TileBinDev tb;
+  double* parts;           // [B][M] tile partials of the continuous-spectrum bins, or null (no bins)
   const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
   double* partials;        // [B][tiles][4]: sum w |F|^2, Re F(0), max ln chi
-  double* cont_sum;        // [B][nb] raw sums of w |F|^2, or null (counts are filled from the geometry)
-  int want_bins;           // accumulate the continuous spectrum (LDS sized for it)
+  int hx_off, hq_off;      // LDS byte offsets of the tile histogram (set by the launcher)
   int any_gen;             // some field uses a tabulated radial form or the FP64 filter evaluation
 };
 
@@ -106,32 +128,40 @@ struct FinalizeArgs {
   double sigma_f;
   double* fstats;          // [B][8] mu, var, max ln chi, flag, scale, offset, spectrum factor, G
   double* stats;           // [B][4] user copy or null
-  double* cont_sum;        // [B][nb] rescaled in place, or null
-  int nb;
   const FieldIO* io;
 };
 
 struct BinArgs {
-  ColSched sc;             // tiles per field and fields (the launch is persistent over them)
+  int ntiles, batch;
+  ItemQueue q;             // 3D: persistent over the items
+  ColSched sc;             // 2D: one item per workgroup (the fields of a tile on one XCD)
   const float2* spec;
-  long long Nh, N;
-  Axis0Geom gm;
-  BinDev bd;
-  int nb;
-  const uint16_t* table;
-  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
-  double* sum;
-  const FieldIO* io;       // per-field +-1 spectrum output (batch path) or null
-  int hs_off;              // LDS byte offset of the histogram (set by the launcher)
-};
-
-struct BinGeomArgs {
   long long Nh;
   Axis0Geom gm;
-  BinDev bd;
+  TileBinDev tb;
+  double* parts;           // [B][M] tile partials of the bins of sum w |X|^2
+  const float2* tw;        // stage twiddle table of the axis length (StageTab layout)
+  int hx_off, hq_off;      // LDS byte offsets of the tile histogram (set by the launcher)
+};
+
+// Per-field spectra from the tile partials (each bin summed over its tiles in tile order) and the
+// per-field sign counts from the last row pass's per-tile counts.
+struct SpecFinalArgs {
   int nb;
-  uint16_t* table;         // [ncol][n0] or null
-  unsigned long long* counts;   // [nb], zeroed before the launch
+  const uint32_t* coff_c;  // continuous spectrum: bin ranges of the filter pass's tile width, or null
+  const double* parts_c;   // [B][M_c]
+  int M_c;
+  const double* fstats;    // [B][8]: entry 6 turns raw sums into the normalised field's spectrum
+  double* cont_sum;        // [B][nb] (uniform path) or null
+  const uint32_t* coff_p;  // +-1 (or input) spectrum: bin ranges of the binning pass's tile width, or null
+  const double* parts_p;   // [B][M_p]
+  int M_p;
+  double pscale;           // 1 / N
+  double* pm1_sum;         // [B][nb] (uniform path) or null
+  const uint32_t* cpart;   // [B][ntc][2]: n_pos, n_near of each row tile, or null
+  int ntc;
+  uint64_t* counts;        // [B][2] (uniform path) or null
+  const FieldIO* io;       // per-field outputs (batch path) or null
 };
 
 struct RowsZArgs {
@@ -145,14 +175,6 @@ struct RowsZArgs {
   int8_t* pm1;
   uint32_t* cpart;         // [B][row tiles][2]: n_pos, n_near of each tile (THRESH), or null
   float near_tol;          // absolute
-  const FieldIO* io;       // per-field outputs (batch path) or null
-};
-
-// per-field totals of the last row pass's per-tile counts
-struct CountFinalArgs {
-  const uint32_t* cpart;   // [B][ntiles][2]
-  int ntiles;
-  uint64_t* counts;        // [B][2] (plain path) or null
   const FieldIO* io;       // per-field outputs (batch path) or null
 };
 
@@ -256,13 +278,14 @@ hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st);
 hipError_t launch_rows_r2c(int L, int src, int variant, const RowsArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st);
 hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st);
+// columns per tile of the axis-0 passes with tile variant `variant`
+int col_width(int L, int variant);
 hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st);
 hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st);
 hipError_t launch_rows_c2r(int L, bool thresh, int variant, const RowsZArgs& a, int batch, hipStream_t st);
 int row_tiles(int L, int variant, long long nrows);
-hipError_t launch_count_final(const CountFinalArgs& a, int batch, hipStream_t st);
+hipError_t launch_spec_final(const SpecFinalArgs& a, int batch, hipStream_t st);
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st);
-hipError_t launch_bin_geom(const BinGeomArgs& a, hipStream_t st);
 // `group` tiles in a row per XCD (see ColSched)
 ColSched col_sched(int L, int variant, long long ncol, int batch, int group = 1);
 ColSched col_sched_fields(int L, int variant, long long ncol, int batch);

@@ -41,12 +41,15 @@ extern "C" int hu_pipeline_noalloc(hu_dims dims, int32_t batch, const hu_filter*
   HU_TRY(make_geom(dims, &g));
   if (batch < 1 || !seeds) return HU_ERR_ARG;
   HU_TRY(check_bins(&bins, g.nd));
-  // the workspace this shape needs (the plan may be a tuned one): within the fixed array?
+  // the half spectra alone beyond the fixed array: refused before anything else
   const int chunk = batch < MAX_CHUNK ? batch : MAX_CHUNK;
-  const Layout lay = layout(g, chunk, true, get_plan(g, &bins, batch));
-  if (lay.total > HU_NOALLOC_WORK_BYTES) return HU_ERR_WORKSPACE;
+  if ((size_t)chunk * (size_t)g.Nhp * 8 > HU_NOALLOC_WORK_BYTES) return HU_ERR_WORKSPACE;
   // the tables must exist already: building them would allocate
   HU_TRY(tables_ready(g, &bins));
+  // the whole workspace of this shape (the plan may be a tuned one): within the fixed array?
+  Layout lay;
+  HU_TRY(layout(g, chunk, true, get_plan(g, &bins, batch), &bins, &lay));
+  if (lay.total > HU_NOALLOC_WORK_BYTES) return HU_ERR_WORKSPACE;
   void* work = nullptr;
   HU_TRY(scratch_ptr(&work));
   return run_generator(dims, batch, filt, seeds, &bins, near_tol, *out, true, work, HU_NOALLOC_WORK_BYTES, stream);

@@ -283,16 +283,15 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {
   const long long row0 = (long long)blockIdx.x * C;
   const long long nx = 2 * L;
 
-  if (blockIdx.x == 0) {                        // set up this field's accumulators for later passes
+  if (blockIdx.x == 0) {                        // set up this field's outputs and counters for later passes
+    if (b == 0)
+      for (int i = tid; i < a.nzero; i += T) a.zero[i] = 0u;
     if (a.io) {
       const FieldIO& io = a.io[b];
-      uint32_t* dst[4] = {reinterpret_cast<uint32_t*>(io.cont_sum), reinterpret_cast<uint32_t*>(io.cont_cnt),
-                          reinterpret_cast<uint32_t*>(io.pm1_sum), reinterpret_cast<uint32_t*>(io.pm1_cnt)};
-      const uint32_t* src[4] = {nullptr, a.cnt_src, nullptr, a.cnt_src};
-      const int words[4] = {2 * a.nb, 2 * a.nb, 2 * a.nb, 2 * a.nb};
-      for (int s = 0; s < 4; ++s)
-        if (dst[s])
-          for (int i = tid; i < words[s]; i += T) dst[s][i] = src[s] ? src[s][i] : 0u;
+      uint32_t* dst[2] = {reinterpret_cast<uint32_t*>(io.cont_cnt), reinterpret_cast<uint32_t*>(io.pm1_cnt)};
+      for (int s = 0; s < 2; ++s)
+        if (dst[s] && a.cnt_src)
+          for (int i = tid; i < 2 * a.nb; i += T) dst[s][i] = a.cnt_src[i];
     } else {
       for (int s = 0; s < a.fill_spans; ++s) {
         uint32_t* dst = a.fill[s].dst + (long long)b * a.fill[s].per_field;
@@ -538,7 +537,7 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
     slot_store<L, RLF, P, E>(v, lrow, p);
     __syncthreads();
     twist_store_rows<L, C, T, TILED, RS, true>(lds, tw2, a.tw2, spec, tile_off, run_stride, rows_here, tid);
-    // the tile's counts go to their own slot (k_count_final adds them up): thousands of atomics
+    // the tile's counts go to their own slot (k_spec_final adds them up): thousands of atomics
     // on one counter line per field would serialise in its L2 channel
     if (tid == 0 && a.cpart) {
       unsigned np = 0, nn = 0;
@@ -546,42 +545,6 @@ __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_c2r(RowsZArgs a) {
       reinterpret_cast<uint2*>(a.cpart)[(long long)b * gridDim.x + blockIdx.x] = make_uint2(np, nn);
     }
   }
-}
-
-// counts[b] = the sums of the per-tile counts of field b: one workgroup per field, exact integer
-// sums (the order does not matter)
-__global__ void __launch_bounds__(256) k_count_final(CountFinalArgs a) {
-  __shared__ unsigned long long red[2][256];
-  const int b = blockIdx.x, tid = threadIdx.x;
-  uint64_t* out = a.io ? a.io[b].counts : (a.counts ? a.counts + 2LL * b : nullptr);
-  if (!out) return;                                  // uniform over the workgroup
-  const uint2* part = reinterpret_cast<const uint2*>(a.cpart) + (long long)b * a.ntiles;
-  unsigned long long np = 0, nn = 0;
-  for (int t = tid; t < a.ntiles; t += 256) {
-    const uint2 v = part[t];
-    np += v.x;
-    nn += v.y;
-  }
-  red[0][tid] = np;
-  red[1][tid] = nn;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) {
-      red[0][tid] += red[0][tid + o];
-      red[1][tid] += red[1][tid + o];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    out[0] = red[0][0];
-    out[1] = red[1][0];
-  }
-}
-
-hipError_t launch_count_final(const CountFinalArgs& a, int batch, hipStream_t st) {
-  if (batch <= 0 || a.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_count_final, dim3(batch), dim3(256), 0, st, a);
-  return hipGetLastError();
 }
 
 #define HU_ROW_LENGTHS(X) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)

@@ -85,11 +85,12 @@ _lib.hu_hyperuniformity_class.argtypes = [ctypes.c_double, _i32, ctypes.c_double
 _lib.hu_level_threshold.argtypes = [ctypes.c_double, ctypes.c_double, _P(ctypes.c_double)]
 _lib.hu_level_cut.argtypes = [hu_dims, _i32, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _f32, _vp]
 _lib.hu_two_point.argtypes = [hu_dims, _i32, _vp, _vp, _vp, _sz, _vp]
+_lib.hu_debug_bin_tables.argtypes = [hu_dims, hu_bins, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
 for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline", "hu_pipeline_noalloc",
            "hu_debug_philox", "hu_profile_enable", "hu_profile_read", "hu_workspace_size_batch",
            "hu_pipeline_batch", "hu_autotune", "hu_plan_query", "hu_plan_set", "hu_filter_spectrum",
            "hu_spectrum_grad", "hu_window_variance", "hu_small_k_exponent", "hu_hyperuniformity_class",
-           "hu_level_threshold", "hu_level_cut", "hu_two_point"):
+           "hu_level_threshold", "hu_level_cut", "hu_two_point", "hu_debug_bin_tables"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -410,6 +411,27 @@ def debug_philox(seed, first, count, device="cuda"):
     _check(_lib.hu_debug_philox(int(seed), int(first), int(count), _ptr(w), _ptr(z), _stream(w.device)),
            "hu_debug_philox")
     return w, z
+
+
+def debug_bin_tables(dims, bins, variant=0):
+    """The host-built bin tables of a grid (no device work): dict with ncol, n0, ntiles, M,
+    nloc_max, width and the arrays table, ltab [ncol, n0] (uint16), toff, coff, cpos (uint32)."""
+    import numpy as np
+    d, b = make_dims(dims), make_bins(bins)
+    sz = (ctypes.c_int32 * 6)()
+    _check(_lib.hu_debug_bin_tables(d, b, int(variant), ctypes.addressof(sz), None, None, None, None, None),
+           "hu_debug_bin_tables")
+    ncol, n0, ntiles, M, nloc_max, width = list(sz)
+    nb = b.n_radial * b.n_angular + 1
+    table = np.empty((ncol, n0), np.uint16)
+    ltab = np.empty((ncol, n0), np.uint16)
+    toff = np.empty(ntiles + 1, np.uint32)
+    coff = np.empty(nb + 1, np.uint32)
+    cpos = np.empty(max(M, 1), np.uint32)
+    _check(_lib.hu_debug_bin_tables(d, b, int(variant), None, table.ctypes.data, ltab.ctypes.data,
+                                    toff.ctypes.data, coff.ctypes.data, cpos.ctypes.data), "hu_debug_bin_tables")
+    return dict(ncol=ncol, n0=n0, ntiles=ntiles, M=M, nloc_max=nloc_max, width=width, table=table, ltab=ltab,
+                toff=toff, coff=coff, cpos=cpos[:M])
 
 
 def profile_enable(on=True):

@@ -72,10 +72,9 @@ def _check_against_singles(hf, bb, jobs):
         np.testing.assert_allclose(o["stats"].cpu().numpy(), s.stats[0].cpu().numpy(), rtol=1e-12)
         if j["bins"] is not None:
             assert torch.equal(o["cont_cnt"], s.cont_cnt[0]) and torch.equal(o["pm1_cnt"], s.pm1_cnt[0])
-            np.testing.assert_allclose(o["cont_sum"].cpu().numpy(), s.cont_sum[0].cpu().numpy(), rtol=1e-9,
-                                       atol=1e-12 * s.cont_sum[0].abs().max().item())
-            np.testing.assert_allclose(o["pm1_sum"].cpu().numpy(), s.pm1_sum[0].cpu().numpy(), rtol=1e-9,
-                                       atol=1e-12 * s.pm1_sum[0].abs().max().item())
+            # the bins are combined in a fixed order: the same bits whatever the schedule
+            assert torch.equal(o["cont_sum"], s.cont_sum[0]), (i, j["dims"])
+            assert torch.equal(o["pm1_sum"], s.pm1_sum[0]), (i, j["dims"])
 
 
 def test_batch_matches_single_calls_and_oracle(hf):

@@ -50,10 +50,13 @@ def test_strerror(hf):
 
 def test_workspace_sizes(hf):
     # 2D 2048^2 x 16: half spectrum 16 * 2048 * 1025 complex64, stored in column groups of four
-    # (1025 -> 1028 columns), plus statistics
+    # (1025 -> 1028 columns), statistics, and the FP64 tile partials of the two spectra (room for
+    # either tile width)
     n = hf.workspace_size(hf.HU_OP_PIPELINE, (2048, 2048), 16, (128, 36))
     spec = 16 * 2048 * 1028 * 8
-    assert spec <= n < spec + (1 << 20)
+    M = max(hf.debug_bin_tables((2048, 2048), (128, 36), v)["M"] for v in (0, 1))
+    parts = 2 * 16 * M * 8
+    assert spec + parts <= n < spec + parts + (1 << 20)
     m = hf.workspace_size(hf.HU_OP_POWER_SPECTRUM, (256, 256, 256), 4, (128, 1))
     assert m >= 4 * 256 * 256 * 129 * 8
     # batches above 64 fields are processed in chunks of 64 that reuse the workspace

@@ -579,6 +579,8 @@ PROFILE_COMMANDS = {
     "sq1": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_ACTIVE_INST_VALU "
            "SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU_TRANS_F32 -f csv -d DIR/sq1 -o sq1 -- "
            "python3 REPO/bench.py --main-only --steps 2 --warmup 1",
+    "c4_trace": "rocprofv3 --kernel-trace --stats -f csv -d DIR/c4_uneven_512_fields/trace -o trace -- "
+                "python3 REPO/bench.py --c4-only --steps 10 --warmup 2",
     "sq2": "rocprofv3 --pmc SQ_WAIT_INST_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_ACTIVE_INST_LDS SQ_INSTS_SALU "
            "SQ_WAIT_INST_ANY SQ_INST_CYCLES_VMEM_RD SQ_INSTS_LDS_ATOMIC -f csv -d DIR/sq2 -o sq2 -- "
            "python3 REPO/bench.py --main-only --steps 2 --warmup 1",
@@ -592,7 +594,7 @@ def kernel_family(name):
     if not m:
         return None
     k, args = m.group(1), [t.strip() for t in (m.group(2) or "").split(",")]
-    if k in ("k_finalize", "k_count_final", "k_grad_coef", "k_grad_final", "k_cols_adjoint"):
+    if k in ("k_finalize", "k_spec_final", "k_grad_coef", "k_grad_final", "k_cols_adjoint"):
         return k[2:]
     if k == "k_rows_r2c":
         return "rows_r2c_noise" if args[1] == "0" else "rows_r2c"
@@ -600,7 +602,7 @@ def kernel_family(name):
         return "rows_c2r_thresh" if args[1] == "true" else "rows_c2r"
     if k == "k_cols":
         return "cols_y_inv" if args[1] == "true" else "cols_y_fwd"
-    return {"k_cols_filter": "cols_filter", "k_cols_bin": "cols_bin", "k_cols_bin_keep": "cols_bin"}.get(k)
+    return {"k_cols_filter": "cols_filter", "k_cols_bin": "cols_bin", "k_cols_bin_tile": "cols_bin"}.get(k)
 
 
 def _csv_rows(d, suffix):
@@ -727,9 +729,83 @@ def summarize_profiles(d):
                 f, c["SQ_INSTS_VALU"] * 64 / modes, share, c.get("SQ_INSTS_LDS", 0) * 64 / modes,
                 c.get("SQ_LDS_BANK_CONFLICT", 0) * 64 / modes, c.get("SQ_INSTS_VALU_TRANS_F32", 0) * 64 / modes))
         md.append("")
+    summarize_c4_trace(os.path.join(d, "c4_uneven_512_fields", "trace"))
     with open(os.path.join(ROOT, "profiles", "pmc_traffic.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     with open(os.path.join(ROOT, "profiles", "pipeline_kernels_2048sq_x16_and_256cube_x4.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
+def summarize_c4_trace(td, replays=10):
+    """profiles/batch_kernels_c4_uneven_512.md from the kernel trace of `bench.py --c4-only`: the
+    last `replays` graph launches (found as the period of the dispatch sequence), their span on the
+    GPU and the summed kernel time per family."""
+    if not os.path.isdir(td):
+        return
+    rows = [r for r in _csv_rows(td, "_kernel_trace.csv") if "hu::" in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    import collections
+    names = [r["Kernel_Name"] for r in rows]
+    # the classes run on several streams, so the order of the dispatches varies between launches:
+    # the period is the smallest K whose last windows of K dispatches hold the same kernels
+    period = next((k for k in range(1, len(names) // (replays + 1) + 1)
+                   if all(collections.Counter(names[len(names) - (i + 1) * k:len(names) - i * k]) ==
+                          collections.Counter(names[len(names) - k:]) for i in range(1, replays))), None)
+    if period is None:
+        return
+    spans, fam = [], {}
+    for i in range(replays):
+        win = rows[len(rows) - (i + 1) * period:len(rows) - i * period]
+        t0 = min(int(r["Start_Timestamp"]) for r in win)
+        t1 = max(int(r["End_Timestamp"]) for r in win)
+        spans.append((t1 - t0) * 1e-3)
+        for r in win:
+            f = kernel_family(r["Kernel_Name"]) or r["Kernel_Name"].split("(")[0]
+            n, t = fam.get(f, (0, 0.0))
+            fam[f] = (n + 1, t + (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    busy = sum(t for _, t in fam.values()) / replays
+    md = ["# Uneven batch of 512 fields (448 2D, 64 3D): kernel trace of the replayed graph", "",
+          "Command (after `cd /tmp && export TMPDIR=/tmp`; `REPO` the repository root, `DIR` a scratch folder): "
+          "`%s`, then `python3 REPO/bench.py --summarize-profiles DIR`." % PROFILE_COMMANDS["c4_trace"], "",
+          "The last %d graph launches of the run (%d kernel dispatches each): GPU span of one launch %.1f us "
+          "(first dispatch start to last dispatch end), summed kernel time %.1f us per launch (the classes "
+          "run on four streams, so kernels overlap and the sum exceeds the span)." % (
+              replays, period, sum(spans) / replays, busy), "",
+          "| family | dispatches per launch | summed us per launch | mean us per dispatch |", "|---|---|---|---|"]
+    for f, (n, t) in sorted(fam.items(), key=lambda kv: -kv[1][1]):
+        md.append("| %s | %d | %.1f | %.2f |" % (f, n // replays, t / replays, t / n))
+
+    # the shape class of a dispatch from its template arguments: the row passes take n_x / 2 (2D:
+    # tiled layout), the axis-0 and y passes n along that axis (cols_filter names the dimension)
+    def shape_class(name):
+        import re
+        m = re.search(r"hu::k_(\w+)<([^>]*)>", name)
+        if not m:
+            return None
+        k, a = m.group(1), [t.strip() for t in m.group(2).split(",")]
+        if k in ("rows_r2c", "rows_c2r"):
+            n, d = 2 * int(a[0]), 2 if a[2] == "true" else 3
+        elif k == "cols_filter":
+            n, d = int(a[0]), int(a[1])
+        elif k in ("cols", "cols_bin"):
+            n, d = int(a[0]), 3
+        elif k == "cols_bin_tile":
+            n, d = int(a[0]), 2
+        else:
+            return None
+        return "%dD %d^%d" % (d, n, d)
+    cls = {}
+    for i in range(replays):
+        for r in rows[len(rows) - (i + 1) * period:len(rows) - i * period]:
+            c = shape_class(r["Kernel_Name"])
+            if c:
+                cls[c] = cls.get(c, 0.0) + (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+    md += ["", "Summed kernel time per shape class (the five axis passes; finalize and the final "
+           "reduction left out):", "", "| class | summed us per launch |", "|---|---|"]
+    for c, t in sorted(cls.items(), key=lambda kv: -kv[1]):
+        md.append("| %s | %.1f |" % (c, t / replays))
+    with open(os.path.join(ROOT, "profiles", "batch_kernels_c4_uneven_512.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
     print("\n".join(md))
 

@@ -180,6 +180,7 @@ template <int L, int NDIM>
 __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, 0>::C, T = ColTile<L, 0>::T;
   constexpr int PS = AdjLds<L>::PS, TS = AdjLds<L>::TS;
+  static_assert(E % 2 == 0, "the 3D pairs of modes split a thread's E modes in halves");
   using Rad = typename Plan<L>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
   constexpr float LN2 = 0.69314718055994531f;
@@ -232,14 +233,22 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
       const float kx = cc.kx_c;
       const float wm2 = 2.0f * cc.wm;
       if constexpr (NDIM == 3) {
+        // kappa_z enters ln H only through |kappa_z| (the rotation is about z) and the radial bin
+        // only through kappa_z^2: the modes e and n0 - e share H, its derivatives and their bin, so
+        // each pair is evaluated once with the sum of the two |W|^2.  Thread p takes the pairs
+        // q = p + P k, k < E / 2 (q < n0 / 2); thread 0 also takes q = n0 / 2.  q = 0 and q = n0 / 2
+        // are their own partners.
         const bool partner = f.rotated && (cc.nyq_x || cc.nyq_y);
         const Lnh3Col c1 = lnh3_col(f, kx, cc.ky);
         const Lnh3Col c2 = partner ? lnh3_col(f, cc.nyq_x ? -kx : kx, cc.nyq_y ? -cc.ky : cc.ky) : c1;
+        constexpr int NP = E / 2 + 1;
 #pragma unroll 2
-        for (int k = 0; k < E; ++k) {
-          const int e = p + P * k;
-          const float kz = (float)(e < n0 / 2 ? e : e - n0) * a.gm.kap0;
-          const float cb = wm2 * (float)(cf[tc[e]] - gamma) * pc[e];
+        for (int k = 0; k < NP; ++k) {
+          const int q = k < E / 2 ? p + P * k : (p == 0 ? n0 / 2 : -1);
+          if (q < 0) continue;
+          const float kz = (float)q * a.gm.kap0;
+          const float w2 = (q == 0 || 2 * q == n0) ? pc[q] : pc[q] + pc[n0 - q];
+          const float cb = wm2 * (float)(cf[tc[q]] - gamma) * w2;
           LnhOut o1;
           lnh3(f, c1, kz, o1);
           if (partner) {

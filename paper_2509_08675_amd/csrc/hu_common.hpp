@@ -193,6 +193,68 @@ __device__ __forceinline__ float amp_sym64(const FiltDev& f, const Axis0Geom& gm
   return H;
 }
 
+// 3D: the x and y terms of the superellipse norm are fixed along an axis-0 column (the rotation is
+// about z), so they are formed once per column: lxy = log2 max(u_x, u_y) and the sum of the in-plane
+// terms relative to it, c01 = 1 + (min / max)^p (0 when u_x = u_y = 0).  Per mode only the z term
+// joins them, relative to the largest of the three (Eq. (12), scaled form).
+struct Col3 {
+  float lxy, c01;
+};
+constexpr float COL3_OFF = -1.0e4f;   // log2 of a zero term: its power 2^(p (COL3_OFF - l)) is 0
+
+__device__ __forceinline__ Col3 col3(const FiltDev& f, float kx, float ky) {
+  const float kxr = fmaf(f.cr, kx, f.sr * ky);
+  const float kyr = fmaf(-f.sr, kx, f.cr * ky);
+  const float u0 = fabsf(kxr) * f.ia, u1 = fabsf(kyr) * f.ib;
+  const float um = fmaxf(u0, u1), un = fminf(u0, u1);
+  Col3 c;
+  if (!(um > 0.0f)) {
+    c.lxy = COL3_OFF;
+    c.c01 = 0.0f;
+    return c;
+  }
+  c.lxy = hw_log2(um);
+  c.c01 = 1.0f + (un > 0.0f ? hw_exp2(f.p * (hw_log2(un) - c.lxy)) : 0.0f);
+  return c;
+}
+
+// ln chi (relative to its peak) at (column c, kappa_z): Eq. (13) with band centre k0, or the
+// tabulated radial form (PROF); -1e30 at the DC mode
+template <bool PROF>
+__device__ __forceinline__ float ln_chi3(const FiltDev& f, const Col3& c, float kz) {
+  const float u2 = fabsf(kz) * f.ic;
+  const bool on2 = u2 > 0.0f;
+  if (!on2 && !(c.c01 > 0.0f)) return -1.0e30f;
+  const float l2 = on2 ? hw_log2(u2) : COL3_OFF;
+  const bool zbig = l2 > c.lxy;
+  const float lm = zbig ? l2 : c.lxy;
+  const float t = hw_exp2(-f.p * fabsf(l2 - c.lxy));      // the smaller side relative to the larger
+  const float S = zbig ? fmaf(c.c01, t, 1.0f) : c.c01 + (on2 ? t : 0.0f);
+  const float log2K = fmaf(hw_log2(S), f.ip, lm);
+  const float K = hw_exp2(log2K);
+  if constexpr (PROF) {
+    if (f.prof) return prof_lnchi(f, K);
+  }
+  const float d = K - f.k0;
+  return fmaf(f.alpha, log2K * 0.69314718055994531f, -fmaf(d * d, f.inv2w2, f.lnchimax));
+}
+
+// the symmetrised amplitude of a 3D mode from its column's terms (c2: the column with its Nyquist
+// x / y components negated, used on those planes when the filter is rotated); kappa_z enters only
+// through |kappa_z|, so the z Nyquist plane needs no partner
+template <bool GEN>
+__device__ __forceinline__ float amp_sym3(const FiltDev& f, const Axis0Geom& gm, const ColCoord& cc, const Col3& c1,
+                                          const Col3& c2, int e, float& lnc) {
+  if constexpr (GEN) {
+    if (f.prec64) return amp_sym64<3>(f, gm, cc, e, lnc);
+  }
+  const float kz = (float)(e < gm.n0 / 2 ? e : e - gm.n0) * gm.kap0;
+  lnc = ln_chi3<GEN>(f, c1, kz);
+  float H = amp_from_lnchi(lnc, f.offset);
+  if (f.rotated && (cc.nyq_x || cc.nyq_y)) H = 0.5f * (H + amp_from_lnchi(ln_chi3<GEN>(f, c2, kz), f.offset));
+  return H;
+}
+
 template <int NDIM, bool GEN = false>
 __device__ __forceinline__ float amp_sym(const FiltDev& f, const Axis0Geom& gm, const ColCoord& cc, int e,
                                          float& lnc) {
@@ -289,6 +351,45 @@ __device__ __forceinline__ void seg_read(const float* pwc, const uint16_t* __res
   for (int i = 0; i < E; ++i) v[i] = pwc[pw_index(e0 + i)];
 }
 
+// Radial bins only (sym): the bin of a mode depends on the axis-0 index e only through its square,
+// so e and n0 - e share it.  Thread (cb, pb) then takes the pairs q = pb E/2 .. pb E/2 + E/2 - 1 of
+// its column with the value pw[q] + pw[n0 - q] (pw[q] alone for q = 0), the last thread also
+// q = n0 / 2 (its own partner): half the runs.  Other threads carry an empty last entry.
+template <int L, int E, int P>
+__device__ __forceinline__ void seg_read_sym(const float* pwc, const uint16_t* __restrict__ ltab, int g, int pb,
+                                             int (&loc)[E / 2 + 1], double (&v)[E / 2 + 1]) {
+  constexpr int H = E / 2;
+  const int q0 = pb * H;
+  const uint16_t* t = ltab + (unsigned)(g * L);
+#pragma unroll
+  for (int i = 0; i < H; ++i) loc[i] = (int)t[q0 + i];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const int q = q0 + i;
+    v[i] = q == 0 ? (double)pwc[pw_index(0)] : (double)pwc[pw_index(q)] + (double)pwc[pw_index(L - q)];
+  }
+  const bool nyq = pb == P - 1;
+  loc[H] = nyq ? (int)t[L / 2] : loc[H - 1];
+  v[H] = nyq ? (double)pwc[pw_index(L / 2)] : 0.0;
+}
+
+template <int N, bool PASS2>
+__device__ __forceinline__ void runs_commit_d(const int (&loc)[N], const double (&v)[N], int* hx,
+                                              unsigned long long* hq) {
+  int cur = loc[0];
+  double acc = v[0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    if (loc[i] != cur) {
+      run_commit<PASS2>(cur, acc, hx, hq);
+      cur = loc[i];
+      acc = 0.0;
+    }
+    acc += v[i];
+  }
+  run_commit<PASS2>(cur, acc, hx, hq);
+}
+
 // The whole tile: both passes and the stores of the partials (thread j < nloc stores the partial of
 // local bin j at its position wpos[toff[tile] + j] and clears its slots for the next tile).  Called
 // by every thread of the workgroup after the power values are in LDS and a barrier; ends with the
@@ -304,15 +405,28 @@ __device__ __forceinline__ void tile_bins(const float* pw, int* hx, unsigned lon
   const unsigned j0 = tb.toff[tile];
   const int nloc = (int)(tb.toff[tile + 1] - j0);
   const unsigned wp0 = tid < nloc ? tb.wpos[j0 + tid] : 0u;
-  int loc[E];
-  float v[E];
-  if (act) {
-    seg_read<L, E>(pw + cb * LP, tb.ltab, g, pb, loc, v);
-    runs_commit<E, false>(loc, v, hx, hq);
+  if (tb.sym) {                                      // uniform over the launch
+    static_assert(E % 2 == 0, "pairs of modes split a thread's E modes in halves");
+    int loc[E / 2 + 1];
+    double v[E / 2 + 1];
+    if (act) {
+      seg_read_sym<L, E, P>(pw + cb * LP, tb.ltab, g, pb, loc, v);
+      runs_commit_d<E / 2 + 1, false>(loc, v, hx, hq);
+    }
+    __syncthreads();
+    if (act) runs_commit_d<E / 2 + 1, true>(loc, v, hx, hq);
+    __syncthreads();
+  } else {
+    int loc[E];
+    float v[E];
+    if (act) {
+      seg_read<L, E>(pw + cb * LP, tb.ltab, g, pb, loc, v);
+      runs_commit<E, false>(loc, v, hx, hq);
+    }
+    __syncthreads();
+    if (act) runs_commit<E, true>(loc, v, hx, hq);
+    __syncthreads();
   }
-  __syncthreads();
-  if (act) runs_commit<E, true>(loc, v, hx, hq);
-  __syncthreads();
   for (int j = tid; j < nloc; j += T) {
     const int e = hx[j];
     const unsigned long long q = hq[j];

@@ -35,6 +35,12 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   const bool do_bins = a.parts != nullptr;
   const FiltDev filt = a.io ? a.io[b].filt : a.filt;
   const ColCoord cc = col_coord(a.gm, valid ? g : 0);
+  Col3 c3a{}, c3b{};
+  if constexpr (NDIM == 3) {                       // the column's x / y terms of the filter
+    c3a = col3(filt, cc.kx_c, cc.ky);
+    c3b = (filt.rotated && (cc.nyq_x || cc.nyq_y)) ? col3(filt, cc.nyq_x ? -cc.kx_c : cc.kx_c, cc.nyq_y ? -cc.ky : cc.ky)
+                                                   : c3a;
+  }
   double gsum = 0.0, f0 = 0.0;
   float lmax = filt.lnoffset;             // the lattice maximum of ln(chi_rel + offset) is at least ln offset
   // the exchange buffer is free once every thread has its transform in registers: the power
@@ -53,7 +59,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   for (int s = 0; s < E; ++s) {
     const int e = slot_index<L, RL, P>(s, p);
     float lnc;
-    const float H = amp_sym<NDIM, GEN>(filt, a.gm, cc, e, lnc);
+    const float H = NDIM == 3 ? amp_sym3<GEN>(filt, a.gm, cc, c3a, c3b, e, lnc) : amp_sym<NDIM, GEN>(filt, a.gm, cc, e, lnc);
     const float2 F = cscale(v[s], H);
     v[s] = F;
     const float m2 = cc.wm * (F.x * F.x + F.y * F.y);

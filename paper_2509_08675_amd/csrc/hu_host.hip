@@ -693,7 +693,7 @@ int get_tilebins(const Geom& g, const hu_bins& bins, int C, TileBinDev* out) {
   HU_TRY(upload(th->toff, &toff));
   HU_TRY(upload(th->wpos, &wpos));
   HU_TRY(upload(th->coff, &coff));
-  TileBinDev d{ltab, toff, wpos, coff, th->nloc_max, (int)th->toff.back()};
+  TileBinDev d{ltab, toff, wpos, coff, th->nloc_max, (int)th->toff.back(), bins.n_angular == 1 ? 1 : 0};
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_tiledev.find(key);
   if (it != g_tiledev.end()) {

@@ -95,6 +95,7 @@ struct TileBinDev {
   const uint32_t* coff;    // [nb + 1]: the stored partials of bin k are coff[k] .. coff[k+1]-1
   int nloc_max;            // most distinct bins in one tile
   int M;                   // partials per field
+  int sym;                 // radial bins only: modes e and n0 - e of a column share their bin
 };
 
 // Dynamic schedule of the persistent binning pass: the items (tile, field), tile-major, are

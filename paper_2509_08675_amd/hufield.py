@@ -11,7 +11,8 @@ import os
 import numpy as np
 import torch
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhufield.so")
+# HUFIELD_LIB selects another build of the same library (the host-sanitizer build of the tests)
+_LIB_PATH = os.environ.get("HUFIELD_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhufield.so")
 
 if not os.path.exists(_LIB_PATH):
     raise ImportError("libhufield.so is not built (run: python -m paper_2509_08675_amd.build); "

@@ -69,6 +69,10 @@ def test_tables_match_oracle_bins(hf, dims, bins, variant):
     t = hf.debug_bin_tables(dims, bins, variant)
     nb = bins[0] * bins[1] + 1
     check_structure(t, oracle_columns(dims, *bins), nb)
+    if bins[1] == 1:
+        # radial bins: the modes e and n0 - e of a column share their bin (the binning passes pair them)
+        n0 = t["n0"]
+        assert np.array_equal(t["ltab"][:, 1:], t["ltab"][:, :0:-1])
 
 
 def test_full_size_2d_table(hf):

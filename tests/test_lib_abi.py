@@ -13,7 +13,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "hufield.h")
-LIB = os.path.join(ROOT, "paper_2509_08675_amd", "libhufield.so")
+# HUFIELD_LIB: another build of the same library (the host-sanitizer run of these tests)
+LIB = os.environ.get("HUFIELD_LIB") or os.path.join(ROOT, "paper_2509_08675_amd", "libhufield.so")
 
 pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhufield.so not built")
 

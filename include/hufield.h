@@ -173,7 +173,8 @@ int hu_pipeline(hu_dims dims, int32_t batch, const hu_filter* filt, const uint64
  * workspace taken from a fixed device array inside the library instead of a caller buffer.
  *   Limit: the workspace hu_workspace_size(HU_OP_PIPELINE, dims, min(batch, 64), &bins) reports
  *   must be at most HU_NOALLOC_WORK_BYTES (128 MiB: e.g. one 256^3 field, seven 2048^2 fields,
- *   fifteen 1024^2 fields per call); larger requests return HU_ERR_WORKSPACE and enqueue nothing.
+ *   thirty-one 1024^2 fields with 64 radial bins per call); larger requests return
+ *   HU_ERR_WORKSPACE and enqueue nothing.
  *   The array exists once per GPU (the library holds 128 MiB of device memory on every GPU it
  *   runs on until the process ends); its address is looked up once per device on the first call
  *   with that device current.

@@ -175,6 +175,16 @@ def time_pipeline(hf, torch, cfg, steps, warmup, plain=False):
     return el, prof
 
 
+def autotune_workload(hf, cfg):
+    """hu_autotune for a workload's shape class before it is timed (plan search excluded from the
+    timing): the plan it keeps and the summed mean kernel time of one pass sequence with the
+    default plan and with the tuned one."""
+    t0 = time.perf_counter()
+    plan, ms = hf.autotune(cfg["dims"], len(cfg["seeds"]), cfg["bins"])
+    return dict(plan=[k for k, v in plan.items() if v], default_kernel_ms=round(ms["default_ms"], 4),
+                tuned_kernel_ms=round(ms["tuned_ms"], 4), autotune_s=round(time.perf_counter() - t0, 2))
+
+
 def roofline_obj(cfg, prof, steps, workload):
     fam_bytes, total = algorithmic_bytes(cfg["dims"], len(cfg["seeds"]))
     dom = max(prof.items(), key=lambda kv: kv[1][1])
@@ -217,8 +227,12 @@ def time_uneven_batch(hf, torch, steps, warmup, plain=True):
         key = (tuple(j["dims"]), tuple(j["bins"]))
         classes[key] = classes.get(key, 0) + 1
     t0 = time.perf_counter()
+    tuning = {}
     for (dims, bins), cnt in classes.items():
-        hf.autotune(dims, cnt, bins)
+        plan, ms = hf.autotune(dims, cnt, bins)
+        tuning["x".join(map(str, dims))] = dict(fields=cnt, default_kernel_ms=round(ms["default_ms"], 4),
+                                                tuned_kernel_ms=round(ms["tuned_ms"], 4),
+                                                plan=[k for k, v in plan.items() if v])
     tune_s = time.perf_counter() - t0
     bb = hf.BatchBuffers(jobs)
     st = hf.pipeline_batch(bb)
@@ -240,7 +254,8 @@ def time_uneven_batch(hf, torch, steps, warmup, plain=True):
     bmin = sum(field_bytes_min(tuple(j["dims"])) for j in jobs)
     if not plain:
         return dict(value=round(vox / (ms * 1e-3), 1), unit="voxels/s", ms_per_step=round(ms, 4), fields=len(jobs),
-                    bytes_min=bmin, pipeline_roofline_frac=round(bmin / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+                    bytes_min=bmin, pipeline_roofline_frac=round(bmin / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    tuning=tuning)
     plain = [hf.PipelineBuffers(j["dims"], 1, j["bins"]) for j in jobs]
 
     def plain_step():
@@ -258,7 +273,9 @@ def time_uneven_batch(hf, torch, steps, warmup, plain=True):
     return dict(value=round(vox / (ms * 1e-3), 1), unit="voxels/s", ms_per_step=round(ms, 4),
                 fields=len(jobs), fields_2d=n2, fields_3d=len(jobs) - n2, voxels=vox, shape_classes=len(classes),
                 bytes_min=bmin, pipeline_roofline_frac=round(bmin / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                autotune_s=round(tune_s, 2),
+                autotune_s=round(tune_s, 2), tuning=tuning,
+                tuning_note="per shape class: summed mean kernel time of one class pass sequence (hu_autotune) "
+                            "with the default plan and with the tuned one, and the entries the tuner switched",
                 plain_form=dict(desc="one hu_pipeline call per field, default tiles", ms_per_step=round(pms, 4),
                                 value=round(vox / (pms * 1e-3), 1), batched_speedup=round(pms / ms, 3)))
 
@@ -843,6 +860,7 @@ def main():
         return
 
     cfg = C3 if (args.main_only and args.workload == C3["name"]) else C2
+    tuning = autotune_workload(hf, cfg)
     el, prof = time_pipeline(hf, torch, cfg, args.steps, args.warmup)
     ms = el / args.steps * 1e3
     vox = len(cfg["seeds"]) * math.prod(cfg["dims"])
@@ -858,15 +876,23 @@ def main():
         pipeline_roofline_frac=round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         pipeline_bytes_min=total,
         flops=flops_obj(cfg, ms),
+        tuning=tuning,
     )
     if args.main_only:
         print(json.dumps(line), flush=True)
         return
+    # the same batch with the default plan, for the tuner's gain
+    tuned_plan = hf.plan_query(cfg["dims"], len(cfg["seeds"]), cfg["bins"])
+    hf.plan_set(cfg["dims"], len(cfg["seeds"]), cfg["bins"], [0] * len(hf.PASS_NAMES))
+    del_, _ = time_pipeline(hf, torch, cfg, max(args.steps // 2, 5), 3)
+    hf.plan_set(cfg["dims"], len(cfg["seeds"]), cfg["bins"], [tuned_plan[k] for k in hf.PASS_NAMES])
+    line["tuning"]["default_plan_ms_per_step"] = round(del_ / max(args.steps // 2, 5) * 1e3, 4)
     pel, _ = time_pipeline(hf, torch, cfg, max(args.steps // 5, 3), 2, plain=True)
     pms = pel / max(args.steps // 5, 3) * 1e3
     line["plain_form"] = dict(desc="one pipeline call per field (16 calls)", ms_per_step=round(pms, 4),
                               value=round(vox / (pms * 1e-3), 1), batched_speedup=round(pms / ms, 3))
     if not args.no_3d:
+        tuning3 = autotune_workload(hf, C3)
         el3, prof3 = time_pipeline(hf, torch, C3, max(args.steps // 2, 5), 3)
         ms3 = el3 / max(args.steps // 2, 5) * 1e3
         vox3 = len(C3["seeds"]) * math.prod(C3["dims"])
@@ -874,7 +900,7 @@ def main():
         line["also"] = {C3["name"]: dict(value=round(vox3 / (ms3 * 1e-3), 1), unit="voxels/s",
                                          ms_per_step=round(ms3, 4),
                                          pipeline_roofline_frac=round(total3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                         roofline=roof3)}
+                                         roofline=roof3, tuning=tuning3)}
     if not args.no_extra:
         line.setdefault("also", {})
         line["also"]["c4_uneven_512_fields"] = time_uneven_batch(hf, torch, max(args.steps // 5, 5), 2)

@@ -304,18 +304,29 @@ int hu_workspace_size_batch(const hu_job* jobs, int32_t njobs, size_t* bytes);
 int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t* status, void* work,
                       size_t work_bytes, void* stream);
 
-/* Tile-width autotuner.  Times every kernel family of the pipeline (rows_r2c, cols_y, cols_filter,
- * rows_c2r, cols_bin) in both variants (default tile width, half width) on a synthetic batch of
- * `batch` fields of `dims` with `bins`, keeps the faster variant per family for this shape class
- * (grid, bins, batch size bucket), and, if cache_path is non-NULL, writes all tuned plans as JSON
- * there (read back at start-up from $HUFIELD_TUNE_CACHE).  ms_out (host, optional) receives the
- * 2 x 5 mean launch times in ms.  Allocates and frees its own device buffers and synchronises. */
+/* Plan autotuner.  A plan has 8 entries, each 0 or 1: the tile width of the kernel families
+ * rows_r2c, cols_y, cols_filter, rows_c2r, cols_bin (0 the default, 1 half of it), then three
+ * schedules (0 the default, 1 the other one): bin_schedule (the +-1 binning pass one tile of one
+ * field per workgroup, or persistent with a work counter and the next tile's loads overlapping the
+ * binning; default one-per-workgroup in 2D, persistent in 3D), field_placement (the fields of an
+ * axis-0 tile on consecutive workgroup ids of one XCD, sharing the tile's bin-table slice in its
+ * L2, or field-major; default the former in 2D, the latter in 3D) and y_group (the 3D y passes give
+ * groups of 16 or of 4 neighbouring tiles to one XCD).  hu_autotune searches the plan of a shape
+ * class (grid, bins, batch size bucket) on a synthetic batch of `batch` fields of `dims` with
+ * `bins`: from the default plan it flips one entry at a time and keeps the change when the summed
+ * mean kernel time of the whole pass sequence drops by more than 1 % (the y-pass entries only in
+ * 3D).  The plan is kept in memory and, if cache_path is non-NULL, all tuned plans are written as
+ * JSON there (read back at start-up from $HUFIELD_TUNE_CACHE).  ms_out (host, optional) receives 10
+ * values: the default plan's time, the tuned plan's, and for each entry the time with it flipped
+ * during the search (0 where not tried), in ms.  Allocates and frees its own device buffers and
+ * synchronises.  Every plan gives the same fields and sign maps bit for bit (the spectra to FP64
+ * rounding: the tile width changes how the bins' partials are grouped). */
 int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* cache_path, double* ms_out);
 
-/* The tile variants (5 entries, 0 or 1, order as above) that calls on this shape class use. */
+/* The plan (8 entries, 0 or 1, order as above) that calls on this shape class use. */
 int hu_plan_query(hu_dims dims, int32_t batch, const hu_bins* bins, int32_t* variants);
 
-/* Set the tile variants for a shape class by hand (host array of 5 entries, each 0 or 1). */
+/* Set the plan of a shape class by hand (host array of 8 entries, each 0 or 1). */
 int hu_plan_set(hu_dims dims, int32_t batch, const hu_bins* bins, const int32_t* variants);
 
 const char* hu_strerror(int code);

@@ -25,7 +25,7 @@ hu_outputs offset_outputs(const hu_outputs& o, long long f0, long long N, int nb
   return r;
 }
 
-TunePlan widest_plan() { return TunePlan{{1, 1, 1, 1, 1}}; }   // most tiles: largest partials
+TunePlan widest_plan() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0}}; }   // most tiles: largest partials
 
 // workspace of hu_spectrum_grad: the noise spectrum, the per-bin weights, the per-tile partials
 struct GradLayout {
@@ -141,7 +141,7 @@ int hu_workspace_size(int op, hu_dims dims, int32_t batch, const hu_bins* bins, 
       *bytes = wvar_layout(g, chunk).total;
       return HU_OK;
     case HU_OP_TWO_POINT:
-      HU_TRY(layout(g, chunk, true, TunePlan{{0, 0, 0, 0, 0}}, nullptr, &lay));
+      HU_TRY(layout(g, chunk, true, TunePlan{}, nullptr, &lay));
       *bytes = lay.total;
       return HU_OK;
     default:
@@ -247,8 +247,9 @@ int hu_power_spectrum(hu_dims dims, int32_t batch, const void* x, int32_t dtype,
     BinArgs ba{};
     ba.ntiles = col_tiles(g.n[0], 0, g.Nh / g.n[0]);
     ba.batch = B;
+    ba.persistent = g.nd == 3 ? 1 : 0;
     ba.q = ItemQueue{queue + Q_BIN, ba.ntiles * B, 8};
-    ba.sc = col_sched_fields(g.n[0], 0, g.Nh / g.n[0], B);
+    ba.sc = g.nd == 2 ? col_sched_fields(g.n[0], 0, g.Nh / g.n[0], B) : col_sched(g.n[0], 0, g.Nh / g.n[0], B);
     ba.spec = spec;
     ba.Nh = g.Nhp;
     ba.gm = axis0(g);
@@ -510,7 +511,7 @@ int hu_two_point(hu_dims dims, int32_t batch, const int8_t* pm1, float* s2, void
   if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
   const int chunk = batch < MAX_CHUNK ? batch : MAX_CHUNK;
   Layout lay;
-  HU_TRY(layout(g, chunk, true, TunePlan{{0, 0, 0, 0, 0}}, nullptr, &lay));
+  HU_TRY(layout(g, chunk, true, TunePlan{}, nullptr, &lay));
   if (work_bytes < lay.total) return HU_ERR_WORKSPACE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int Lrow = g.nx / 2;

@@ -6,9 +6,10 @@
 // run beside large ones.  The instantiated graph is cached per batch structure and workspace and
 // replayed on later calls; only the FieldIO table is uploaded each time.
 //
-// hu_autotune times every kernel family of the pipeline in both tile-width variants on a
-// synthetic batch of the requested shape and keeps the faster one per family, in memory and
-// optionally in a JSON file (read back through $HUFIELD_TUNE_CACHE).
+// hu_autotune searches the plan of a shape class (the tile width of every kernel family and three
+// schedule switches) on a synthetic batch of the requested shape: starting from the default plan it
+// flips one choice at a time and keeps it when the whole pass sequence gets faster; the plan is kept
+// in memory and optionally in a JSON file (read back through $HUFIELD_TUNE_CACHE).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -57,7 +58,7 @@ int ensure_streams() {
   return HU_OK;
 }
 
-TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1}}; }
+TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0}}; }
 
 int job_status(const hu_job& j, Geom* g) {
   int rc = make_geom(j.dims, g);
@@ -314,12 +315,10 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
   std::vector<uint64_t> seeds(B);
   for (int i = 0; i < B; ++i) seeds[i] = 1 + i;
   hu_outputs o{field, pm1, stats, counts, cs, cc, ps, pc};
-  double t[2][NPASS] = {};
-  const char* fam[NPASS][2] = {{"rows_r2c_noise", ""}, {"cols_y_fwd", "cols_y_inv"}, {"cols_filter", ""},
-                               {"rows_c2r_thresh", ""}, {"cols_bin", ""}};
   if (rc == HU_OK) rc = prepare_tables(g, bins, st);
-  for (int v = 0; v < 2 && rc == HU_OK; ++v) {
-    const TunePlan plan{{v, v, v, v, v}};
+
+  // the summed mean kernel time of the whole pass sequence under a plan (2 untimed runs, 5 timed)
+  auto time_plan = [&](const TunePlan& plan) -> double {
     auto run = [&]() {
       for (int f0 = 0; f0 < B && rc == HU_OK; f0 += MAX_CHUNK) {
         ClassRun r{};
@@ -349,7 +348,7 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
     run();
     run();
     if (rc == HU_OK && hipStreamSynchronize(st) != hipSuccess) rc = HU_ERR_HIP;
-    if (rc != HU_OK) break;
+    if (rc != HU_OK) return 0.0;
     const bool prof = g_prof;
     rc = profile_reset(true);
     for (int k = 0; k < 5 && rc == HU_OK; ++k) run();
@@ -358,17 +357,44 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
     std::vector<double> ms;
     if (rc == HU_OK) rc = profile_collect(names, cnt, ms);
     (void)profile_reset(prof);
-    for (int p = 0; p < NPASS; ++p)
-      for (size_t i = 0; i < names.size(); ++i)
-        if (names[i] == fam[p][0] || names[i] == fam[p][1]) t[v][p] += ms[i] / 5.0;
+    double t = 0.0;
+    for (double m : ms) t += m / 5.0;
+    return t;
+  };
+
+  // coordinate search from the default plan: each choice flipped in turn, kept when the pass
+  // sequence gets at least 1 % faster (the y-pass choices only exist in 3D).  Each comparison is
+  // paired: the current plan and the candidate are timed alternately twice and the faster time of
+  // each kept, so clock ramps and other drifts hit both alike.
+  double tried[NPASS] = {};
+  TunePlan best{};
+  if (rc == HU_OK) (void)time_plan(best);                  // warm-up of the whole sequence
+  double t_default = 0.0, t_best = 0.0;
+  for (int k = 0; k < NPASS && rc == HU_OK; ++k) {
+    if (g.nd == 2 && (k == P_COLY || k == P_YGROUP)) continue;
+    TunePlan cand = best;
+    cand.v[k] ^= 1;
+    double tb = 1e30, tc = 1e30;
+    for (int rep = 0; rep < 2 && rc == HU_OK; ++rep) {
+      tb = std::min(tb, time_plan(best));
+      tc = std::min(tc, time_plan(cand));
+    }
+    if (rc != HU_OK) break;
+    if (t_default == 0.0) t_default = tb;
+    tried[k] = tc;
+    t_best = tb;
+    if (tc > 0.0 && tc < 0.99 * tb) {
+      best = cand;
+      t_best = tc;
+    }
   }
   if (rc == HU_OK) {
-    TunePlan best{};
-    for (int p = 0; p < NPASS; ++p) best.v[p] = (t[1][p] > 0.0 && t[1][p] < t[0][p]) ? 1 : 0;
     set_plan(plan_key(g, bins, B), best);
-    if (ms_out)
-      for (int v = 0; v < 2; ++v)
-        for (int p = 0; p < NPASS; ++p) ms_out[v * NPASS + p] = t[v][p];
+    if (ms_out) {
+      ms_out[0] = t_default;
+      ms_out[1] = t_best;
+      for (int k = 0; k < NPASS; ++k) ms_out[2 + k] = tried[k];
+    }
     if (cache_path) rc = save_plans(cache_path);
   }
   (void)hipStreamSynchronize(st);

@@ -9,7 +9,7 @@
 
 namespace hu {
 
-// 3D: persistent over the items (tile, field), tile-major, taken from the work counter in chunks: the
+// Persistent (the default in 3D) over the items (tile, field), tile-major, taken from the work counter in chunks: the
 // forward transform of a tile's columns, the per-mode values w |X|^2 into LDS, then (while the next
 // item's columns are already being loaded into the transform's registers) the tile's deterministic
 // bin partials.
@@ -68,8 +68,8 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
   }
 }
 
-// One item per workgroup (2D): the schedule's XCD mapping puts the fields of a tile on one XCD,
-// which then reads the tile's slice of the bin table once.
+// One item per workgroup (the default in 2D, where the schedule's XCD mapping puts the fields of a
+// tile on one XCD, which then reads the tile's slice of the bin table once).
 template <int L, int V>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin_tile(BinArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
@@ -110,7 +110,7 @@ static hipError_t launch_cols_bin_L(BinArgs a, hipStream_t st) {
   a.hx_off = (int)col_bin_base<L, V>();
   a.hq_off = a.hx_off + (a.tb.nloc_max * 4 + 15) / 16 * 16;
   const size_t lds = (size_t)a.hq_off + (size_t)a.tb.nloc_max * 8;
-  if (a.gm.ndim == 2) {
+  if (!a.persistent) {
     hipLaunchKernelGGL((k_cols_bin_tile<L, V>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
     return hipGetLastError();
   }

@@ -131,7 +131,7 @@ void load_plans_locked() {
   size_t n;
   while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
   std::fclose(f);
-  // entries look like  "key": [v0, v1, v2, v3, v4]
+  // entries look like  "key": [v0, v1, ...]  (missing trailing entries are 0)
   size_t pos = 0;
   while ((pos = s.find("\": [", pos)) != std::string::npos) {
     const size_t q = s.rfind('"', pos - 1);
@@ -139,10 +139,17 @@ void load_plans_locked() {
     const std::string key = s.substr(q + 1, pos - q - 1);
     TunePlan p{};
     const char* c = s.c_str() + pos + 4;
-    if (std::sscanf(c, "%d, %d, %d, %d, %d", &p.v[0], &p.v[1], &p.v[2], &p.v[3], &p.v[4]) == 5) {
-      for (int i = 0; i < NPASS; ++i) p.v[i] = p.v[i] ? 1 : 0;
-      g_plans[key] = p;
+    int n = 0;
+    while (n < NPASS) {
+      char* end = nullptr;
+      const long x = std::strtol(c, &end, 10);
+      if (end == c) break;
+      p.v[n++] = x ? 1 : 0;
+      c = end;
+      while (*c == ' ' || *c == ',') ++c;
+      if (*c == ']') break;
     }
+    if (n >= 5) g_plans[key] = p;
     pos += 4;
   }
 }
@@ -762,7 +769,7 @@ TunePlan get_plan(const Geom& g, const hu_bins* bins, int batch) {
   load_plans_locked();
   auto it = g_plans.find(plan_key(g, bins, batch));
   if (it != g_plans.end()) return it->second;
-  return TunePlan{{0, 0, 0, 0, 0}};
+  return TunePlan{};
 }
 
 void set_plan(const std::string& key, const TunePlan& p) {
@@ -775,13 +782,14 @@ int save_plans(const char* path) {
   std::lock_guard<std::mutex> lk(g_mu);
   FILE* f = std::fopen(path, "w");
   if (!f) return HU_ERR_ARG;
-  std::fprintf(f, "{\n  \"format\": \"hufield tile-variant plans: [rows_r2c, cols_y, cols_filter, rows_c2r, cols_bin]\",\n"
-                  "  \"plans\": {\n");
+  std::fprintf(f, "{\n  \"format\": \"hufield plans: tile widths [rows_r2c, cols_y, cols_filter, rows_c2r, cols_bin], "
+                  "schedules [bin_schedule, field_placement, y_group]\",\n  \"plans\": {\n");
   size_t i = 0;
   for (const auto& kv : g_plans) {
     const TunePlan& p = kv.second;
-    std::fprintf(f, "    \"%s\": [%d, %d, %d, %d, %d]%s\n", kv.first.c_str(), p.v[0], p.v[1], p.v[2], p.v[3], p.v[4],
-                 ++i < g_plans.size() ? "," : "");
+    std::fprintf(f, "    \"%s\": [", kv.first.c_str());
+    for (int k = 0; k < NPASS; ++k) std::fprintf(f, "%d%s", p.v[k], k + 1 < NPASS ? ", " : "");
+    std::fprintf(f, "]%s\n", ++i < g_plans.size() ? "," : "");
   }
   std::fprintf(f, "  }\n}\n");
   std::fclose(f);
@@ -851,9 +859,11 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     cy.ncol = g.n[0] * g.nxh;
     cy.inner = g.nxh;
     cy.tw = tw_1;
-    cy.sc = col_sched(g.n[1], r.plan.v[P_COLY], cy.ncol, B, Y_PASS_GROUP);
+    cy.sc = col_sched(g.n[1], r.plan.v[P_COLY], cy.ncol, B, r.plan.v[P_YGROUP] ? 4 : Y_PASS_GROUP);
     HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st); }));
   }
+  // the fields of a tile on consecutive ids of one XCD (2D default) or field-major (3D default)
+  const bool fields_xcd = (g.nd == 2) != (r.plan.v[P_FIELDS] != 0);
 
   FilterArgs fa{};
   fa.spec = spec;
@@ -862,8 +872,8 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fa.gm = axis0(g);
   // 2D: the fields of a tile share its slice of the bin table in one XCD's L2 (the 2D binning
   // pass 111 -> 103 us at 16 x 2048^2); 3D fields, 67 MB apart at 256^3, ran 3 % slower that way
-  fa.sc = g.nd == 2 ? col_sched_fields(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B)
-                    : col_sched(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B);
+  fa.sc = fields_xcd ? col_sched_fields(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B)
+                     : col_sched(g.n[0], r.plan.v[P_FILTER], fa.gm.ncol, B);
   if (!batch_mode) fa.filt = filt_dev(r.filt, g);
   fa.io = r.io;
   fa.tb = tb_c;
@@ -911,8 +921,10 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     BinArgs ba{};
     ba.ntiles = col_tiles(g.n[0], r.plan.v[P_BIN], g.Nh / g.n[0]);
     ba.batch = B;
+    ba.persistent = (g.nd == 3) != (r.plan.v[P_BINSCHED] != 0);
     ba.q = ItemQueue{queue + Q_BIN, ba.ntiles * B, 8};
-    ba.sc = col_sched_fields(g.n[0], r.plan.v[P_BIN], g.Nh / g.n[0], B);
+    ba.sc = fields_xcd ? col_sched_fields(g.n[0], r.plan.v[P_BIN], g.Nh / g.n[0], B)
+                       : col_sched(g.n[0], r.plan.v[P_BIN], g.Nh / g.n[0], B);
     ba.spec = spec;
     ba.Nh = g.Nhp;
     ba.gm = axis0(g);

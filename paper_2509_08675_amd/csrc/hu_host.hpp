@@ -32,8 +32,13 @@ struct Geom {
   long long Nhp;    // per-field half-spectrum storage (padded to whole column groups in 2D)
 };
 
-// kernel families with tunable tile widths
-enum { P_R2C = 0, P_COLY = 1, P_FILTER = 2, P_C2R = 3, P_BIN = 4, NPASS = 5 };
+// Tunable choices of the pass sequence.  Entries 0-4: the tile width of each kernel family (0 the
+// default, 1 half of it).  Entries 5-7: schedules (0 the default): P_BINSCHED the binning pass's
+// (default one item per workgroup in 2D, persistent with a work counter in 3D; 1 the other one),
+// P_FIELDS the axis-0 passes' placement of a tile's fields (default consecutive on one XCD in 2D,
+// field-major in 3D; 1 the other one), P_YGROUP the 3D y passes' tiles per XCD group (16, or 4).
+enum { P_R2C = 0, P_COLY = 1, P_FILTER = 2, P_C2R = 3, P_BIN = 4, P_BINSCHED = 5, P_FIELDS = 6, P_YGROUP = 7,
+       NPASS = 8 };
 struct TunePlan {
   int v[NPASS];
 };

@@ -134,8 +134,9 @@ struct FinalizeArgs {
 
 struct BinArgs {
   int ntiles, batch;
-  ItemQueue q;             // 3D: persistent over the items
-  ColSched sc;             // 2D: one item per workgroup (the fields of a tile on one XCD)
+  int persistent;          // 1: persistent over the items of q; 0: one item per workgroup (sc)
+  ItemQueue q;
+  ColSched sc;
   const float2* spec;
   long long Nh;
   Axis0Geom gm;

@@ -455,7 +455,8 @@ def profile_read(cap=64):
 # ---------------------------------------------------------------------------------------------
 # heterogeneous batches and the autotuner
 # ---------------------------------------------------------------------------------------------
-PASS_NAMES = ("rows_r2c", "cols_y", "cols_filter", "rows_c2r", "cols_bin")
+PASS_NAMES = ("rows_r2c", "cols_y", "cols_filter", "rows_c2r", "cols_bin", "bin_schedule", "field_placement",
+              "y_group")
 
 
 class BatchBuffers:
@@ -517,24 +518,27 @@ def pipeline_batch(bufs, near_tol=1e-5):
 
 
 def autotune(dims, batch, bins, cache_path=None):
-    """Time both tile variants of every kernel family on this shape and keep the faster; returns
-    ({family: chosen variant}, ms array [2, 5])."""
-    ms = (ctypes.c_double * 10)()
+    """Search the plan of this shape class (hu_autotune); returns ({entry: 0 or 1}, dict of the
+    default plan's and the tuned plan's summed kernel ms and, per entry, the ms with it flipped
+    during the search (0 where not tried))."""
+    ms = (ctypes.c_double * (2 + len(PASS_NAMES)))()
     b = make_bins(bins)
     _check(_lib.hu_autotune(make_dims(dims), int(batch), ctypes.byref(b),
                             cache_path.encode() if cache_path else None, ms), "hu_autotune")
-    return plan_query(dims, batch, bins), np.array(list(ms)).reshape(2, 5)
+    v = list(ms)
+    return plan_query(dims, batch, bins), dict(default_ms=v[0], tuned_ms=v[1], flipped_ms=dict(zip(PASS_NAMES, v[2:])))
 
 
 def plan_query(dims, batch, bins):
-    v = (_i32 * 5)()
+    v = (_i32 * len(PASS_NAMES))()
     b = make_bins(bins) if bins is not None else None
     _check(_lib.hu_plan_query(make_dims(dims), int(batch), ctypes.byref(b) if b else None, v), "hu_plan_query")
     return dict(zip(PASS_NAMES, list(v)))
 
 
 def plan_set(dims, batch, bins, variants):
-    v = (_i32 * 5)(*[int(x) for x in variants])
+    variants = list(variants) + [0] * (len(PASS_NAMES) - len(variants))
+    v = (_i32 * len(PASS_NAMES))(*[int(x) for x in variants])
     b = make_bins(bins) if bins is not None else None
     _check(_lib.hu_plan_set(make_dims(dims), int(batch), ctypes.byref(b) if b else None, v), "hu_plan_set")
 

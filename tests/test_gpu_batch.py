@@ -1,4 +1,4 @@
-"""GPU tests of heterogeneous batches (one captured graph) and of the tile-variant autotuner.
+"""GPU tests of heterogeneous batches (one captured graph) and of the plan autotuner.
 
 * every field of an uneven batch equals the same field generated alone (field and sign map
   bit-identical: the per-column arithmetic does not depend on the batch), and sampled fields
@@ -6,7 +6,8 @@
 * the cached graph replays correctly several times in a row with other GPU work in between,
   for new seeds each time;
 * an invalid job gets its error status and does not disturb the others;
-* the half-width tile variants give the same fields as the default ones and match the oracle;
+* the half-width tile variants with every schedule switched give the same fields as the default
+  plan and match the oracle;
 * the autotuner writes a plan the library then reports;
 * the full uneven 512-field batch in the benchmark's launch configuration: one field of every
   shape class (64^2 .. 1024^2, 64^3 .. 128^3) against the oracle to the parity tolerances.
@@ -152,20 +153,20 @@ def test_half_width_variants_match(hf, dims, bins):
     _say("variants", dims)
     filt = W.filt(p=3, semi=(2, 1, 1.5), rot=0.4, alpha=4, k0=0.2, width=0.05)
     seeds = [11, 12]
-    hf.plan_set(dims, 2, bins, [0, 0, 0, 0, 0])
+    hf.plan_set(dims, 2, bins, [0] * 8)
     b0 = hf.PipelineBuffers(dims, 2, bins)
     hf.pipeline(b0, filt, seeds)
-    hf.plan_set(dims, 2, bins, [1, 1, 1, 1, 1])
+    hf.plan_set(dims, 2, bins, [1] * 8)                # every tile width and schedule switched
     b1 = hf.PipelineBuffers(dims, 2, bins)
     hf.pipeline(b1, filt, seeds)
     torch.cuda.synchronize()
-    assert hf.plan_query(dims, 2, bins) == dict(zip(hf.PASS_NAMES, [1] * 5))
+    assert hf.plan_query(dims, 2, bins) == dict(zip(hf.PASS_NAMES, [1] * 8))
     assert torch.equal(b0.field, b1.field) and torch.equal(b0.pm1, b1.pm1)
     np.testing.assert_allclose(b0.pm1_sum.cpu().numpy(), b1.pm1_sum.cpu().numpy(), rtol=1e-10, atol=1e-9)
     ref = O.pipeline(dims, O.FilterParams(**filt), seeds[1], *bins)
     f = b1.field[1].double().cpu().numpy()
     assert np.max(np.abs(f - ref["f"])) <= 1e-5 * math.sqrt(float(np.mean(ref["f"] ** 2)))
-    hf.plan_set(dims, 2, bins, [0, 0, 0, 0, 0])
+    hf.plan_set(dims, 2, bins, [0] * 8)
 
 
 def test_autotune_writes_plan(hf, tmp_path):
@@ -173,8 +174,9 @@ def test_autotune_writes_plan(hf, tmp_path):
     path = str(tmp_path / "tune.json")
     _say("autotune", dims)
     plan, ms = hf.autotune(dims, 4, bins, path)
-    assert set(plan.values()) <= {0, 1}
-    assert ms.shape == (2, 5) and np.all(ms[:, [0, 2, 3, 4]] > 0)
+    assert set(plan.values()) <= {0, 1} and len(plan) == 8
+    assert ms["default_ms"] > 0 and 0 < ms["tuned_ms"] <= ms["default_ms"]
+    assert ms["flipped_ms"]["cols_filter"] > 0 and ms["flipped_ms"]["y_group"] == 0   # 2D: no y passes
     d = json.load(open(path))
     keys = [k for k in d["plans"] if "256x256x1" in k]
     assert keys and d["plans"][keys[0]] == [plan[n] for n in hf.PASS_NAMES]

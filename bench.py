@@ -293,16 +293,8 @@ def time_adjoint(hf, torch, steps, warmup=1):
     out = hf.gen_field(dims, filt, [seed], cont_bins=bins, work=wf, out=field)
     ts, tc = hf.filter_spectrum(dims, C5["target"], bins)
     cs, cc, stt = out["cont_sum"][0], out["cont_cnt"][0], out["stats"][0]
-    cnt = cc[:-1].double()
-    P = torch.where(cnt > 0, cs[:-1] / cnt.clamp(min=1.0), torch.zeros_like(cnt))
-    T = torch.where(cnt > 0, ts[:-1] / cnt.clamp(min=1.0), torch.zeros_like(cnt))
-    mask = cnt > 0
-    mask[0] = False
-    eps = 1e-12
-    d = torch.log(P + eps) - torch.log(T + eps)
-    dL = torch.zeros_like(cs)
-    dL[:-1] = torch.where(mask, 2.0 * d / (P + eps) / mask.sum(), torch.zeros_like(d))
-    loss = float((d[mask] ** 2).mean())
+    loss_t, dL = hf.spectrum_loss_value(bins, cs, cc, ts, tc, 1e-12)      # loss and dL/dP from the library
+    loss = float(loss_t.cpu())
     torch.cuda.synchronize()
 
     def timed(fn, k):

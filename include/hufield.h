@@ -254,6 +254,19 @@ int hu_small_k_exponent(const double* sum, const uint64_t* cnt, hu_bins bins, in
  * Host only. */
 int hu_hyperuniformity_class(double alpha, int32_t d, double tol);
 
+/* Spectrum-matching loss for fitting the filter parameters to a target spectrum (the parameter
+ * optimisation named as the extension in Sec. IV):
+ *   L = (1/|B|) sum_{b in B} (ln(P_b + eps) - ln(T_b + eps))^2,   dL/dP_b = 2 d_b / (|B| (P_b + eps)),
+ * P_b = sum[b] / cnt[b] the bin means of a field's continuous spectrum (hu_gen_field), T_b =
+ * tsum[b] / tcnt[b] those of the target (e.g. hu_filter_spectrum of the target filter), B the bins
+ * of radius r >= 1 that hold modes in both (the DC row r = 0 and the corner slot are excluded).
+ * sum, tsum [R*A+1] FP64, cnt, tcnt [R*A+1] uint64 (device, 8-byte aligned); loss [1] and dL_dP
+ * [R*A+1] FP64 device outputs (dL_dP is 0 outside B; it feeds hu_spectrum_grad).  eps >= 0 (the
+ * parity workloads use 1e-12 sigma_f^2).  One workgroup, fixed-order sums (bit-reproducible).
+ * HU_ERR_ARG for bad bins, pointers or eps; HU_ERR_ALIGN for unaligned arrays. */
+int hu_spectrum_loss(hu_bins bins, const double* sum, const uint64_t* cnt, const double* tsum, const uint64_t* tcnt,
+                     double eps, double* loss, double* dL_dP, void* stream);
+
 /* Adjoint of the binned continuous spectrum with respect to the filter parameters of
  * Eqs. (12)-(13) (the gradient a parameter-fitting loop of Sec. IV needs).  Inputs are the outputs
  * of hu_gen_field(dims, 1, filt, &seed, field, stats, &bins, cont_sum, cont_cnt, ...) for one

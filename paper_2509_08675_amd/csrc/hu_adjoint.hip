@@ -208,7 +208,19 @@ __global__ void __launch_bounds__((ColTile<L, 0>::T)) k_cols_adjoint(AdjointArgs
       const int g0 = tile * C;
       const int ncv = a.gm.ncol - g0 < C ? a.gm.ncol - g0 : C;
       const uint16_t* src = a.table + (size_t)g0 * L;
-      if constexpr (L % 8 == 0) {
+      if constexpr (NDIM == 3 && L % 16 == 0) {
+        // the pairs below read the bins of modes 0 .. L/2 only: the first L/16 + 1 chunks of 8
+        constexpr int HC = L / 16 + 1;
+        for (int i = tid; i < ncv * HC; i += T) {
+          const int col = i / HC, ch = i - col * HC;
+          const uint4 w = reinterpret_cast<const uint4*>(src + (size_t)col * L)[ch];
+          uint32_t* d = reinterpret_cast<uint32_t*>(tb + col * TS + 8 * ch);
+          d[0] = w.x;
+          d[1] = w.y;
+          d[2] = w.z;
+          d[3] = w.w;
+        }
+      } else if constexpr (L % 8 == 0) {
         for (int i = tid; i < ncv * (L / 8); i += T) {
           const uint4 w = reinterpret_cast<const uint4*>(src)[i];
           uint32_t* d = reinterpret_cast<uint32_t*>(tb + ((8 * i) / L) * TS + (8 * i) % L);
@@ -366,6 +378,59 @@ __global__ void __launch_bounds__(256) k_grad_coef(GradCoefArgs a) {
 
 hipError_t launch_grad_coef(const GradCoefArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_grad_coef, dim3(1), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// spectrum-matching loss (one workgroup, fixed-order reduction):
+//   L = (1/|B|) sum_{b in B} d_b^2,  d_b = ln(P_b + eps) - ln(T_b + eps),
+//   dL/dP_b = 2 d_b / (|B| (P_b + eps)),
+// P_b, T_b the bin means of the field's and the target's spectra, B the bins of radius r >= 1 that
+// hold modes in both (the DC row and the corner slot excluded)
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_spectrum_loss(LossArgs a) {
+  __shared__ double red[256];
+  __shared__ unsigned cnt_used[256];
+  __shared__ double nb_used;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  unsigned used = 0;
+  for (int b = tid; b < a.nb - 1; b += 256) {
+    const bool on = b >= a.na && a.cnt[b] > 0 && a.tcnt[b] > 0;
+    if (on) {
+      const double P = a.sum[b] / (double)a.cnt[b], T = a.tsum[b] / (double)a.tcnt[b];
+      const double d = log(P + a.eps) - log(T + a.eps);
+      acc += d * d;
+      ++used;
+    }
+  }
+  red[tid] = acc;
+  cnt_used[tid] = used;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      red[tid] += red[tid + o];
+      cnt_used[tid] += cnt_used[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    nb_used = (double)cnt_used[0];
+    a.loss[0] = cnt_used[0] ? red[0] / nb_used : 0.0;
+  }
+  __syncthreads();
+  for (int b = tid; b < a.nb; b += 256) {
+    double g = 0.0;
+    if (b < a.nb - 1 && b >= a.na && a.cnt[b] > 0 && a.tcnt[b] > 0 && nb_used > 0.0) {
+      const double P = a.sum[b] / (double)a.cnt[b], T = a.tsum[b] / (double)a.tcnt[b];
+      g = 2.0 * (log(P + a.eps) - log(T + a.eps)) / (nb_used * (P + a.eps));
+    }
+    a.dL_dP[b] = g;
+  }
+}
+
+hipError_t launch_spectrum_loss(const LossArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_spectrum_loss, dim3(1), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

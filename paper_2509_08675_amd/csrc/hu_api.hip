@@ -305,6 +305,21 @@ int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double
   return HU_OK;
 }
 
+int hu_spectrum_loss(hu_bins bins, const double* sum, const uint64_t* cnt, const double* tsum, const uint64_t* tcnt,
+                     double eps, double* loss, double* dL_dP, void* stream) {
+  if (bins.n_radial < 1 || bins.n_angular < 1 || (long long)bins.n_radial * bins.n_angular + 1 > 8192)
+    return HU_ERR_ARG;
+  if (!sum || !cnt || !tsum || !tcnt || !loss || !dL_dP) return HU_ERR_ARG;
+  if (!std::isfinite(eps) || eps < 0.0) return HU_ERR_ARG;
+  const void* ptrs[] = {sum, cnt, tsum, tcnt, loss, dL_dP};
+  for (const void* p : ptrs)
+    if (!aligned(p, 8)) return HU_ERR_ALIGN;
+  LossArgs a{sum, cnt, tsum, tcnt, bins.n_radial * bins.n_angular + 1, bins.n_angular, eps, loss, dL_dP};
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  HU_HIP(timed("spectrum_loss", st, [&] { return launch_spectrum_loss(a, st); }));
+  return HU_OK;
+}
+
 int hu_spectrum_grad(hu_dims dims, const hu_filter* filt, uint64_t seed, hu_bins bins, const double* dL_dP,
                      const double* cont_sum, const uint64_t* cont_cnt, const double* stats, double* grad, void* work,
                      size_t work_bytes, void* stream) {

@@ -227,6 +227,18 @@ struct GradCoefArgs {
   double* coef;            // [nb + 1] out
 };
 
+// spectrum-matching loss over the bins r >= 1 with modes (the DC row and the corner slot excluded)
+struct LossArgs {
+  const double* sum;       // [nb]: the field's normalised continuous-spectrum bin sums
+  const uint64_t* cnt;     // [nb]: its mode counts
+  const double* tsum;      // [nb]: the target spectrum's bin sums
+  const uint64_t* tcnt;    // [nb]: the target's mode counts
+  int nb, na;              // slots incl. the corner slot; angular bins per radius
+  double eps;              // added to both bin means inside the logs
+  double* loss;            // [1] out
+  double* dL_dP;           // [nb] out: dL / d(bin mean), 0 for the bins not used
+};
+
 struct GradFinalArgs {
   const double* partials;  // [rows][8]
   int ntiles;              // rows
@@ -275,6 +287,7 @@ hipError_t launch_cols_adjoint(int L, const AdjointArgs& a, hipStream_t st, int*
 // once (cached per device, kernel and LDS size)
 hipError_t resident_blocks(const void* kern, int threads, size_t lds, int* slots);
 hipError_t launch_grad_coef(const GradCoefArgs& a, hipStream_t st);
+hipError_t launch_spectrum_loss(const LossArgs& a, hipStream_t st);
 hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);
 hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st);
 hipError_t launch_rows_r2c(int L, int src, int variant, const RowsArgs& a, int batch, hipStream_t st);

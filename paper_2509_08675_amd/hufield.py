@@ -87,11 +87,12 @@ _lib.hu_level_threshold.argtypes = [ctypes.c_double, ctypes.c_double, _P(ctypes.
 _lib.hu_level_cut.argtypes = [hu_dims, _i32, _vp, ctypes.c_double, ctypes.c_double, _vp, _vp, _f32, _vp]
 _lib.hu_two_point.argtypes = [hu_dims, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.hu_debug_bin_tables.argtypes = [hu_dims, hu_bins, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hu_spectrum_loss.argtypes = [hu_bins, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]
 for _f in ("hu_workspace_size", "hu_gen_field", "hu_threshold", "hu_power_spectrum", "hu_pipeline", "hu_pipeline_noalloc",
            "hu_debug_philox", "hu_profile_enable", "hu_profile_read", "hu_workspace_size_batch",
            "hu_pipeline_batch", "hu_autotune", "hu_plan_query", "hu_plan_set", "hu_filter_spectrum",
            "hu_spectrum_grad", "hu_window_variance", "hu_small_k_exponent", "hu_hyperuniformity_class",
-           "hu_level_threshold", "hu_level_cut", "hu_two_point", "hu_debug_bin_tables"):
+           "hu_level_threshold", "hu_level_cut", "hu_two_point", "hu_debug_bin_tables", "hu_spectrum_loss"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -617,18 +618,51 @@ class FilterSpectrum(torch.autograd.Function):
         return g.to(device=tdev, dtype=tdt), None, None, None, None, None
 
 
+def spectrum_loss_value(bins, cont_sum, cont_cnt, tsum, tcnt, eps):
+    """hu_spectrum_loss: the loss (device FP64 scalar) and dL/dP per bin (device FP64 [R*A+1]) of a
+    field's binned spectrum against a target's."""
+    dev = cont_sum.device
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    dL = torch.empty(cont_sum.shape[0], dtype=torch.float64, device=dev)
+    _check(_lib.hu_spectrum_loss(make_bins(bins), _ptr(cont_sum), _ptr(cont_cnt), _ptr(tsum), _ptr(tcnt), float(eps),
+                                 _ptr(loss), _ptr(dL), _stream(dev)), "hu_spectrum_loss")
+    return loss[0], dL
+
+
+class SpectrumLoss(torch.autograd.Function):
+    """theta [7] -> the spectrum-matching loss of the field generated from `seed` with those filter
+    parameters against the binned target spectrum (tsum, tcnt).  Forward: hu_gen_field and
+    hu_spectrum_loss; backward: hu_spectrum_grad with the library's dL/dP (the noise is regenerated
+    from the seed)."""
+
+    @staticmethod
+    def forward(ctx, theta, dims, seed, bins, alpha, sigma_f, tsum, tcnt, eps):
+        dims = tuple(int(n) for n in dims)
+        filt = filter_with_theta(theta.detach().cpu().tolist(), alpha, sigma_f)
+        dev = theta.device if theta.is_cuda else torch.device("cuda")
+        out = gen_field(dims, filt, [seed], cont_bins=bins, device=dev)
+        check_degenerate(out["stats"])
+        cs, cc, st = out["cont_sum"][0], out["cont_cnt"][0], out["stats"][0]
+        loss, dL = spectrum_loss_value(bins, cs, cc, tsum, tcnt, eps)
+        ctx.save_for_backward(cs, cc, st, dL)
+        ctx.meta = (dims, int(seed), tuple(bins), filt, theta.device, theta.dtype)
+        return loss.to(theta.dtype) if theta.dtype != torch.float64 else loss
+
+    @staticmethod
+    def backward(ctx, gL):
+        cs, cc, st, dL = ctx.saved_tensors
+        dims, seed, bins, filt, tdev, tdt = ctx.meta
+        g = spectrum_grad(dims, filt, seed, bins, dL * gL.to(device=dL.device, dtype=torch.float64), cs, cc, st)
+        return g.to(device=tdev, dtype=tdt), None, None, None, None, None, None, None, None
+
+
 def spectrum_loss(theta, dims, seed, n_radial, target, alpha, sigma_f=1.0, eps_rel=1e-12):
     """Spectrum-matching loss L = mean over radial bins 1..R-1 with modes of
     (ln(P_b + eps) - ln(T_b + eps))^2, eps = eps_rel sigma_f^2, P the field's radial continuous
-    spectrum (FilterSpectrum, differentiable in theta) and T the expected spectrum of the
-    `target` filter; returns a scalar tensor."""
+    spectrum and T the expected spectrum of the `target` filter, both binned by the library and
+    the loss and its gradient computed by it (hu_spectrum_loss, hu_spectrum_grad); returns a scalar
+    tensor differentiable in theta."""
     bins = (int(n_radial), 1)
-    P = FilterSpectrum.apply(theta, dims, seed, bins, alpha, sigma_f)
-    ts, tc = filter_spectrum(dims, target, bins, device=P.device)
-    cnt = tc[:-1].to(torch.float64)
-    T = torch.where(cnt > 0, ts[:-1] / cnt.clamp(min=1.0), torch.zeros_like(cnt))
-    mask = cnt > 0
-    mask[0] = False
-    eps = eps_rel * float(sigma_f) ** 2
-    d = torch.log(P + eps) - torch.log(T + eps)
-    return (d[mask] ** 2).mean()
+    dev = theta.device if theta.is_cuda else torch.device("cuda")
+    ts, tc = filter_spectrum(dims, target, bins, device=dev)
+    return SpectrumLoss.apply(theta, dims, seed, bins, alpha, sigma_f, ts, tc, eps_rel * float(sigma_f) ** 2)

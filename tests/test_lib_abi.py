@@ -226,3 +226,16 @@ def test_pipeline_noalloc_refusals_on_the_host(hf):
     assert lib.hu_pipeline_noalloc(hf.make_dims((24, 50)), 1, ctypes.byref(filt), seeds, hf.make_bins((11, 3)),
                                    1e-5, ctypes.byref(o), None) == hf.HU_ERR_SIZE
     assert "tables" in hf.strerror(hf.HU_ERR_TABLES)
+
+
+def test_spectrum_loss_validation(hf):
+    """The loss entry point checks its arguments on the host before any launch."""
+    lib = hf.lib_handle()
+    p = ctypes.c_void_p(1 << 20)
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    b = hf.make_bins((16, 1))
+    assert lib.hu_spectrum_loss(b, None, p, p, p, 1e-12, p, p, None) == hf.HU_ERR_ARG
+    assert lib.hu_spectrum_loss(b, p, p, p, p, -1.0, p, p, None) == hf.HU_ERR_ARG
+    assert lib.hu_spectrum_loss(b, p, p, p, p, float("nan"), p, p, None) == hf.HU_ERR_ARG
+    assert lib.hu_spectrum_loss(hf.make_bins((0, 1)), p, p, p, p, 1e-12, p, p, None) == hf.HU_ERR_ARG
+    assert lib.hu_spectrum_loss(b, odd, p, p, p, 1e-12, p, p, None) == hf.HU_ERR_ALIGN

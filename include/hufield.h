@@ -48,10 +48,10 @@
  *   A filter with no support on the lattice (max ln chi < -80) cannot be detected on the host
  *   without a pass over the lattice, so it is reported in the stats output (flag = 1) and the
  *   field is then all zeros.
- * Determinism: fields, sign maps, counts and the statistics (mean and variance come from a
- *   fixed-order reduction) are bit-reproducible, also across batch sizes and batch layouts;
- *   the FP64 bin sums are accumulated with FP64 atomics and may differ in the last bits
- *   between runs.
+ * Determinism: fields, sign maps, counts, the statistics (mean and variance come from a
+ *   fixed-order reduction) and the binned spectra (tile partials combined in integer
+ *   arithmetic, then summed in a fixed order) are bit-reproducible for a given plan (see
+ *   hu_autotune), also across batch layouts and, under the default plans, across batch sizes.
  */
 #ifndef HUFIELD_H
 #define HUFIELD_H
@@ -197,8 +197,9 @@ int hu_pipeline_noalloc(hu_dims dims, int32_t batch, const hu_filter* filt, cons
  * with the half-spectrum multiplicities w exactly like the continuous spectrum of a field, so
  * that sum / cnt is the expected bin mean.  The target of a spectrum-matching loss (parameter
  * optimisation is the extension named in Sec. IV).  sum [R*A+1] FP64 and cnt [R*A+1] (or NULL),
- * device.  The bin sums use FP64 atomics (last-bit order effects, as the other spectra).
- * Workspace: hu_workspace_size(HU_OP_FILTER_SPECTRUM, dims, 1, &bins, ...). */
+ * device.  The bin sums are formed without floating-point atomics (runs combined in integer
+ * arithmetic per chunk of modes, per-workgroup rows summed in a fixed order): bit-reproducible.
+ * Workspace: hu_workspace_size(HU_OP_FILTER_SPECTRUM, dims, 1, &bins, ...) (bins required). */
 int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double* sum, uint64_t* cnt,
                        void* work, size_t work_bytes, void* stream);
 
@@ -317,29 +318,36 @@ int hu_workspace_size_batch(const hu_job* jobs, int32_t njobs, size_t* bytes);
 int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t* status, void* work,
                       size_t work_bytes, void* stream);
 
-/* Plan autotuner.  A plan has 8 entries, each 0 or 1: the tile width of the kernel families
+/* Plan autotuner.  A plan has 9 entries, each 0 or 1: the tile width of the kernel families
  * rows_r2c, cols_y, cols_filter, rows_c2r, cols_bin (0 the default, 1 half of it), then three
  * schedules (0 the default, 1 the other one): bin_schedule (the +-1 binning pass one tile of one
  * field per workgroup, or persistent with a work counter and the next tile's loads overlapping the
  * binning; default one-per-workgroup in 2D, persistent in 3D), field_placement (the fields of an
  * axis-0 tile on consecutive workgroup ids of one XCD, sharing the tile's bin-table slice in its
  * L2, or field-major; default the former in 2D, the latter in 3D) and y_group (the 3D y passes give
- * groups of 16 or of 4 neighbouring tiles to one XCD).  hu_autotune searches the plan of a shape
- * class (grid, bins, batch size bucket) on a synthetic batch of `batch` fields of `dims` with
- * `bins`: from the default plan it flips one entry at a time and keeps the change when the summed
- * mean kernel time of the whole pass sequence drops by more than 1 % (the y-pass entries only in
- * 3D).  The plan is kept in memory and, if cache_path is non-NULL, all tuned plans are written as
- * JSON there (read back at start-up from $HUFIELD_TUNE_CACHE).  ms_out (host, optional) receives 10
- * values: the default plan's time, the tuned plan's, and for each entry the time with it flipped
- * during the search (0 where not tried), in ms.  Allocates and frees its own device buffers and
- * synchronises.  Every plan gives the same fields and sign maps bit for bit (the spectra to FP64
- * rounding: the tile width changes how the bins' partials are grouped). */
+ * groups of 16 or of 4 neighbouring tiles to one XCD); last `radix`, the radix lists of the
+ * column passes (y, filter, binning): 0 each length's default Stockham plan, 1 its alternative
+ * order of radices where the length has one (256: 16.4.4 for 16.16; 512: 16.8.4 for 8.8.8; 1024:
+ * 8.8.16 for 16.8.8; 2048: 16.8.16 for 16.16.8), same elements per thread.  hu_autotune searches
+ * the plan of a shape class (grid, bins, batch size bucket) on a synthetic batch of `batch` fields
+ * of `dims` with `bins`: after about 50 ms of warm-up runs it flips one entry at a time from the
+ * default plan and keeps the change when the summed mean kernel time of the whole pass sequence,
+ * timed alternately with the current plan, drops by more than 1 % (the y-pass entries only in 3D,
+ * the radix entry only where a column length has an alternative).  The plan is kept in memory and,
+ * if cache_path is non-NULL, all tuned plans are written as JSON there (read back at start-up from
+ * $HUFIELD_TUNE_CACHE).  ms_out (host, optional) receives 11 values: the default plan's time and
+ * the tuned plan's (timed side by side after the search), and for each entry the time with it
+ * flipped during the search (0 where not tried), in ms.  Allocates and frees its own device
+ * buffers and synchronises.  The tile-width and schedule entries leave fields and sign maps the
+ * same bit for bit (the spectra to FP64 rounding: the tile width changes how the bins' partials
+ * are grouped); the radix entry changes the FP32 rounding of the column transforms, so fields
+ * under the two radix choices agree to FP32 rounding, not bit for bit. */
 int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* cache_path, double* ms_out);
 
-/* The plan (8 entries, 0 or 1, order as above) that calls on this shape class use. */
+/* The plan (9 entries, 0 or 1, order as above) that calls on this shape class use. */
 int hu_plan_query(hu_dims dims, int32_t batch, const hu_bins* bins, int32_t* variants);
 
-/* Set the plan of a shape class by hand (host array of 8 entries, each 0 or 1). */
+/* Set the plan of a shape class by hand (host array of 9 entries, each 0 or 1). */
 int hu_plan_set(hu_dims dims, int32_t batch, const hu_bins* bins, const int32_t* variants);
 
 const char* hu_strerror(int code);

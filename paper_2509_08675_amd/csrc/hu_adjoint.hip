@@ -474,45 +474,78 @@ hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// expected spectrum of a filter: per-block LDS histogram of w H_sym^2 over runs of consecutive
-// modes (column-major [g][n0] order, as the bin table), per-block totals, then one workgroup
-// scales by sigma_f^2 N / sum w H^2 and copies the counts
+// Expected spectrum of a filter, deterministic.  The modes in column-major [g][n0] order (the
+// order of the bin table) are taken in chunks of FS_THREADS x FS_RUN, chunk c by workgroup
+// c mod gridDim.x; thread t of a chunk evaluates w H_sym^2 of its FS_RUN consecutive modes (FP32,
+// widened to FP64) and sums each run of equal bins in FP64 in mode order.  The runs of a chunk are
+// combined per bin in integer arithmetic (largest binary exponent, then fixed-point adds at
+// 2^(exponent - 48), as in the tile binning of the axis-0 passes), so the chunk's bin sums do not
+// depend on the order of the atomics; each bin's slot of the workgroup's partial row is owned by
+// one thread, which adds the chunk sums in chunk order.  k_filter_spectrum_final then sums the
+// rows in workgroup order and scales by sigma_f^2 N / sum w H^2.
 // ---------------------------------------------------------------------------------------------
 constexpr int FS_THREADS = 256, FS_RUN = 16;
 
 template <int NDIM>
 __global__ void __launch_bounds__(FS_THREADS) k_filter_spectrum(FilterSpecArgs a) {
-  extern __shared__ double hs[];
+  extern __shared__ unsigned long long hq[];      // [nb] fixed-point sums, then [nb] int exponents
+  int* hx = reinterpret_cast<int*>(hq + a.nb);
   __shared__ double red[FS_THREADS / 64];
   const int tid = threadIdx.x;
-  for (int i = tid; i < a.nb; i += FS_THREADS) hs[i] = 0.0;
-  __syncthreads();
+  double* row = a.rows + (long long)blockIdx.x * a.nb;
+  for (int i = tid; i < a.nb; i += FS_THREADS) {
+    hx[i] = HX_EMPTY;
+    hq[i] = 0ull;
+    row[i] = 0.0;
+  }
   const long long n0 = a.gm.n0;
   const long long chunk = (long long)FS_THREADS * FS_RUN;
   double tot = 0.0;
   for (long long base = (long long)blockIdx.x * chunk; base < a.Nh; base += (long long)gridDim.x * chunk) {
     const long long i0 = base + (long long)tid * FS_RUN;
-    int cur = -1;
-    double run = 0.0;
+    int bin[FS_RUN];
+    double val[FS_RUN];
+#pragma unroll
     for (int q = 0; q < FS_RUN; ++q) {
       const long long i = i0 + q;
-      if (i >= a.Nh) break;
-      const int g = (int)(i / n0);
-      const int e = (int)(i - (long long)g * n0);
-      const ColCoord cc = col_coord(a.gm, g);
-      float lnc;
-      const float H = amp_sym<NDIM, true>(a.filt, a.gm, cc, e, lnc);
-      const double val = (double)(cc.wm * H * H);
-      const int bin = (int)a.table[i];
-      tot += val;
-      if (bin != cur) {
-        if (cur >= 0) atomicAdd(hs + cur, run);
-        cur = bin;
-        run = 0.0;
+      bin[q] = -1;
+      val[q] = 0.0;
+      if (i < a.Nh) {
+        const int g = (int)(i / n0);
+        const int e = (int)(i - (long long)g * n0);
+        const ColCoord cc = col_coord(a.gm, g);
+        float lnc;
+        const float H = amp_sym<NDIM, true>(a.filt, a.gm, cc, e, lnc);
+        val[q] = (double)(cc.wm * H * H);
+        bin[q] = (int)a.table[i];
+        tot += val[q];
       }
-      run += val;
     }
-    if (cur >= 0) atomicAdd(hs + cur, run);
+    __syncthreads();                               // the previous chunk's flush is done
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      int cur = -1;
+      double run = 0.0;
+#pragma unroll
+      for (int q = 0; q < FS_RUN; ++q) {
+        if (bin[q] != cur) {
+          if (cur >= 0) pass ? run_commit<true>(cur, run, hx, hq) : run_commit<false>(cur, run, hx, hq);
+          cur = bin[q];
+          run = 0.0;
+        }
+        run += val[q];
+      }
+      if (cur >= 0) pass ? run_commit<true>(cur, run, hx, hq) : run_commit<false>(cur, run, hx, hq);
+      __syncthreads();
+    }
+    for (int i = tid; i < a.nb; i += FS_THREADS) {
+      const int ex = hx[i];
+      if (ex != HX_EMPTY) {
+        row[i] += ldexp((double)hq[i], ex - HQ_SHIFT);
+        hx[i] = HX_EMPTY;
+        hq[i] = 0ull;
+      }
+    }
   }
   tot = wave_sum(tot);
   if ((tid & 63) == 0) red[tid >> 6] = tot;
@@ -522,13 +555,11 @@ __global__ void __launch_bounds__(FS_THREADS) k_filter_spectrum(FilterSpecArgs a
     for (int w = 0; w < FS_THREADS / 64; ++w) s += red[w];
     a.partials[blockIdx.x] = s;
   }
-  for (int i = tid; i < a.nb; i += FS_THREADS)
-    if (hs[i] != 0.0) atomicAdd(a.sum + i, hs[i]);
 }
 
+// one thread per bin: the rows in workgroup order; every workgroup forms the same total
 __global__ void __launch_bounds__(256) k_filter_spectrum_final(FilterSpecArgs a) {
   __shared__ double red[256];
-  __shared__ double fac;
   const int tid = threadIdx.x;
   double s = 0.0;
   for (int t = tid; t < a.nblocks; t += 256) s += a.partials[t];
@@ -538,23 +569,24 @@ __global__ void __launch_bounds__(256) k_filter_spectrum_final(FilterSpecArgs a)
     if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  if (tid == 0) fac = red[0] > 0.0 ? a.sigma_f * a.sigma_f * (double)a.N / red[0] : 0.0;
-  __syncthreads();
-  for (int i = tid; i < a.nb; i += 256) {
-    a.sum[i] *= fac;
-    if (a.cnt) a.cnt[i] = a.counts[i];
-  }
+  const double fac = red[0] > 0.0 ? a.sigma_f * a.sigma_f * (double)a.N / red[0] : 0.0;
+  const int i = blockIdx.x * 256 + tid;
+  if (i >= a.nb) return;
+  double b = 0.0;
+  for (int r = 0; r < a.nblocks; ++r) b += a.rows[(long long)r * a.nb + i];
+  a.sum[i] = b * fac;
+  if (a.cnt) a.cnt[i] = a.counts[i];
 }
 
 hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st) {
-  const size_t lds = (size_t)a.nb * 8;
+  const size_t lds = (size_t)a.nb * 12;
   if (a.gm.ndim == 2)
     hipLaunchKernelGGL(k_filter_spectrum<2>, dim3(a.nblocks), dim3(FS_THREADS), lds, st, a);
   else
     hipLaunchKernelGGL(k_filter_spectrum<3>, dim3(a.nblocks), dim3(FS_THREADS), lds, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_filter_spectrum_final, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_filter_spectrum_final, dim3((a.nb + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

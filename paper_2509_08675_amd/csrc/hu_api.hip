@@ -25,7 +25,7 @@ hu_outputs offset_outputs(const hu_outputs& o, long long f0, long long N, int nb
   return r;
 }
 
-TunePlan widest_plan() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0}}; }   // most tiles: largest partials
+TunePlan widest_plan() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0}}; }   // most tiles: largest partials
 
 // workspace of hu_spectrum_grad: the noise spectrum, the per-bin weights, the per-tile partials
 struct GradLayout {
@@ -57,13 +57,14 @@ WvarLayout wvar_layout(const Geom& g, int chunk) {
   return L;
 }
 
-// workspace of hu_filter_spectrum: the per-block totals
-constexpr int FS_MAX_BLOCKS = 1024;
+// workspace of hu_filter_spectrum: the per-workgroup totals, then the per-workgroup bin rows
+constexpr int FS_MAX_BLOCKS = 256;
 int fs_blocks(const Geom& g) {
   const long long chunk = 256LL * 16;
   const long long n = (g.Nh + chunk - 1) / chunk;
   return (int)(n < FS_MAX_BLOCKS ? n : FS_MAX_BLOCKS);
 }
+size_t fs_bytes(const Geom& g, int nb) { return up256((size_t)fs_blocks(g) * 8) + up256((size_t)fs_blocks(g) * nb * 8); }
 
 
 }  // namespace
@@ -135,7 +136,8 @@ int hu_workspace_size(int op, hu_dims dims, int32_t batch, const hu_bins* bins, 
       *bytes = grad_layout(g, bins->n_radial * bins->n_angular + 1).total;
       return HU_OK;
     case HU_OP_FILTER_SPECTRUM:
-      *bytes = up256((size_t)FS_MAX_BLOCKS * 8);
+      if (!bins) return HU_ERR_ARG;
+      *bytes = fs_bytes(g, bins->n_radial * bins->n_angular + 1);
       return HU_OK;
     case HU_OP_WINDOW_VARIANCE:
       *bytes = wvar_layout(g, chunk).total;
@@ -278,10 +280,10 @@ int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double
   if (!sum) return HU_ERR_ARG;
   if (!aligned(sum, 16) || (cnt && !aligned(cnt, 16))) return HU_ERR_ALIGN;
   if (!work || !aligned(work, 256)) return work ? HU_ERR_ALIGN : HU_ERR_ARG;
-  if (work_bytes < up256((size_t)FS_MAX_BLOCKS * 8)) return HU_ERR_WORKSPACE;
+  const int nb = bins.n_radial * bins.n_angular + 1;
+  if (work_bytes < fs_bytes(g, nb)) return HU_ERR_WORKSPACE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HU_TRY(prepare_tables(g, &bins, st));
-  const int nb = bins.n_radial * bins.n_angular + 1;
   BinDev bd{};
   HU_TRY(make_bindev(g, bins, &bd));
   BinGeo geo{nullptr, nullptr};
@@ -296,11 +298,11 @@ int hu_filter_spectrum(hu_dims dims, const hu_filter* filt, hu_bins bins, double
   a.sum = sum;
   a.partials = reinterpret_cast<double*>(work);
   a.nblocks = fs_blocks(g);
+  a.rows = reinterpret_cast<double*>(reinterpret_cast<char*>(work) + up256((size_t)a.nblocks * 8));
   a.N = g.N;
   a.sigma_f = filt->sigma_f;
   a.counts = geo.counts;
   a.cnt = cnt;
-  HU_HIP(timed("zero", st, [&] { return launch_zero_u64(reinterpret_cast<uint64_t*>(sum), nb, st); }));
   HU_HIP(timed("filter_spectrum", st, [&] { return launch_filter_spectrum(a, st); }));
   return HU_OK;
 }

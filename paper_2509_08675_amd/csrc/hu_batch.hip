@@ -6,10 +6,11 @@
 // run beside large ones.  The instantiated graph is cached per batch structure and workspace and
 // replayed on later calls; only the FieldIO table is uploaded each time.
 //
-// hu_autotune searches the plan of a shape class (the tile width of every kernel family and three
-// schedule switches) on a synthetic batch of the requested shape: starting from the default plan it
-// flips one choice at a time and keeps it when the whole pass sequence gets faster; the plan is kept
-// in memory and optionally in a JSON file (read back through $HUFIELD_TUNE_CACHE).
+// hu_autotune searches the plan of a shape class (the tile width of every kernel family, three
+// schedule switches and the radix lists of the column passes) on a synthetic batch of the
+// requested shape: starting from the default plan it flips one choice at a time and keeps it when
+// the whole pass sequence gets faster; the plan is kept in memory and optionally in a JSON file
+// (read back through $HUFIELD_TUNE_CACHE).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -58,7 +59,7 @@ int ensure_streams() {
   return HU_OK;
 }
 
-TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0}}; }
+TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0}}; }
 
 int job_status(const hu_job& j, Geom* g) {
   int rc = make_geom(j.dims, g);
@@ -362,31 +363,44 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
     return t;
   };
 
+  // paired comparison: the two plans timed alternately twice, the faster time of each kept, so
+  // clock ramps and other drifts hit both alike
+  auto paired = [&](const TunePlan& a, const TunePlan& b, double& ta, double& tb) {
+    ta = tb = 1e30;
+    for (int rep = 0; rep < 2 && rc == HU_OK; ++rep) {
+      ta = std::min(ta, time_plan(a));
+      tb = std::min(tb, time_plan(b));
+    }
+  };
+
   // coordinate search from the default plan: each choice flipped in turn, kept when the pass
-  // sequence gets at least 1 % faster (the y-pass choices only exist in 3D).  Each comparison is
-  // paired: the current plan and the candidate are timed alternately twice and the faster time of
-  // each kept, so clock ramps and other drifts hit both alike.
+  // sequence gets at least 1 % faster (the y-pass choices only exist in 3D, the radix choice where
+  // a column length has an alternative list).  The GPU first runs the sequence for about 50 ms of
+  // kernel time, so that its clocks have settled before the first comparison.
   double tried[NPASS] = {};
   TunePlan best{};
-  if (rc == HU_OK) (void)time_plan(best);                  // warm-up of the whole sequence
-  double t_default = 0.0, t_best = 0.0;
+  double warm = 0.0;
+  for (int i = 0; i < 64 && warm < 50.0 && rc == HU_OK; ++i) warm += 7.0 * time_plan(best);
   for (int k = 0; k < NPASS && rc == HU_OK; ++k) {
     if (g.nd == 2 && (k == P_COLY || k == P_YGROUP)) continue;
+    if (k == P_RADIX && !plan_has_alt(g.n[0]) && !(g.nd == 3 && plan_has_alt(g.n[1]))) continue;
     TunePlan cand = best;
     cand.v[k] ^= 1;
-    double tb = 1e30, tc = 1e30;
-    for (int rep = 0; rep < 2 && rc == HU_OK; ++rep) {
-      tb = std::min(tb, time_plan(best));
-      tc = std::min(tc, time_plan(cand));
-    }
+    double tb = 0.0, tc = 0.0;
+    paired(best, cand, tb, tc);
     if (rc != HU_OK) break;
-    if (t_default == 0.0) t_default = tb;
     tried[k] = tc;
-    t_best = tb;
-    if (tc > 0.0 && tc < 0.99 * tb) {
-      best = cand;
-      t_best = tc;
-    }
+    if (tc > 0.0 && tc < 0.99 * tb) best = cand;
+  }
+  // the default and the tuned plan measured side by side once the search is done; the default is
+  // kept unless the tuned plan still wins there
+  double t_default = 0.0, t_best = 0.0;
+  if (rc == HU_OK) paired(TunePlan{}, best, t_default, t_best);
+  bool same = true;
+  for (int k = 0; k < NPASS; ++k) same = same && best.v[k] == 0;
+  if (same || t_best >= t_default) {
+    best = TunePlan{};
+    t_default = t_best = std::min(t_default, t_best);
   }
   if (rc == HU_OK) {
     set_plan(plan_key(g, bins, B), best);

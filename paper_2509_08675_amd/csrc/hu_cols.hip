@@ -5,10 +5,10 @@
 
 namespace hu {
 
-template <int L, bool INV, int V>
+template <int L, bool INV, int V, int RV>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols(ColsArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C;
-  using Rad = typename Plan<L>::fwd;
+  using Rad = typename Plan<L, RV>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
   extern __shared__ float2 lds[];
   int b;
@@ -21,7 +21,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols(ColsArgs a) {
   const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.inner, g, p);
   float2 v[E];
   col_load<L, R1, P, E>(v, io);
-  fft_run<L, P, E, INV>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
+  fft_run<L, P, E, INV, false, RV>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
   if (valid) col_store<L, RL, P, E>(v, io);
 }
 
@@ -63,19 +63,21 @@ ColSched col_sched_fields(int L, int variant, long long ncol, int batch) {
 
 int col_tiles(int L, int variant, long long ncol) { return col_sched(L, variant, ncol, 1).ntiles; }
 
-template <int L, bool INV, int V>
+template <int L, bool INV, int V, int RV>
 static hipError_t launch_cols_L(const ColsArgs& a, hipStream_t st) {
   constexpr int T = ColTile<L, V>::T;
-  hipLaunchKernelGGL((k_cols<L, INV, V>), dim3(sched_blocks(a.sc)), dim3(T), (col_xchg_bytes<L, V>()), st, a);
+  hipLaunchKernelGGL((k_cols<L, INV, V, RV>), dim3(sched_blocks(a.sc)), dim3(T), (col_xchg_bytes<L, V>()), st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st) {
+hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st, int radix) {
   switch (L) {
-#define X(LL)                                                                                    \
-  case LL:                                                                                       \
-    if (variant) return inv ? launch_cols_L<LL, true, 1>(a, st) : launch_cols_L<LL, false, 1>(a, st); \
-    return inv ? launch_cols_L<LL, true, 0>(a, st) : launch_cols_L<LL, false, 0>(a, st);
+#define X(LL)                                                                                        \
+  case LL:                                                                                           \
+    return with_choices<LL>(variant, radix, [&](auto v, auto r) {                                    \
+      constexpr int V = decltype(v)::value, RV = decltype(r)::value;                                \
+      return inv ? launch_cols_L<LL, true, V, RV>(a, st) : launch_cols_L<LL, false, V, RV>(a, st); \
+    });
     HU_COL_LENGTHS(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -53,6 +53,18 @@ struct ColTile {
 
 __host__ __device__ constexpr int pw_index(int e) { return e + (e >> 4) * 4; }
 
+// Calls f(width, radix) with the tile-width choice V and the radix choice RV as integral
+// constants; a length without an alternative radix list instantiates only RV = 0.
+template <int L, class F>
+inline hipError_t with_choices(int variant, int radix, F&& f) {
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  if constexpr (Plan<L, 1>::alt) {
+    if (radix) return variant ? f(I1{}, I1{}) : f(I0{}, I1{});
+  }
+  return variant ? f(I1{}, I0{}) : f(I0{}, I0{});
+}
+
 // ---------------------------------------------------------------------------------------------
 // block reductions
 // ---------------------------------------------------------------------------------------------

@@ -149,19 +149,33 @@ __device__ __forceinline__ void dft(float2* a) {
 
 // ---------------------------------------------------------------------------------------------
 // Stockham plans.  Plan<L>: E elements per thread, P = L / E threads per transform, radix list
-// fwd (first radix first) and its reverse.  Every radix divides E.
+// fwd (first radix first) and its reverse.  Every radix divides E.  Plan<L, 1>: an alternative
+// order of radices with the same E (so the same tile shapes), chosen per shape class by the
+// autotuner; lengths without one (alt false) keep their default list under either choice.
 // ---------------------------------------------------------------------------------------------
 template <int... Rs>
 struct Radices {};
 
-template <int L>
+template <int... Rs>
+struct RadProd;
+template <>
+struct RadProd<> { static constexpr int value = 1; };
+template <int R0, int... Rs>
+struct RadProd<R0, Rs...> { static constexpr int value = R0 * RadProd<Rs...>::value; };
+template <int E, int... Rs>
+struct RadDivE { static constexpr bool value = ((E % Rs == 0) && ...); };
+
+template <int L, int RV = 0>
 struct Plan;
-#define HU_PLAN(LEN, EPT, ...)                         \
-  template <>                                          \
-  struct Plan<LEN> {                                   \
-    static constexpr int E = EPT;                      \
-    static constexpr int P = LEN / EPT;                \
-    using fwd = Radices<__VA_ARGS__>;                  \
+#define HU_PLAN(LEN, EPT, ...)                                                               \
+  template <>                                                                                \
+  struct Plan<LEN, 0> {                                                                      \
+    static constexpr int E = EPT;                                                            \
+    static constexpr int P = LEN / EPT;                                                      \
+    static constexpr bool alt = false;                                                       \
+    using fwd = Radices<__VA_ARGS__>;                                                        \
+    static_assert(RadProd<__VA_ARGS__>::value == LEN && RadDivE<EPT, __VA_ARGS__>::value, \
+                  "radices multiply to the length and divide E");                           \
   };
 HU_PLAN(2, 2, 2)
 HU_PLAN(3, 3, 3)
@@ -185,6 +199,28 @@ HU_PLAN(1024, 16, 16, 8, 8)
 HU_PLAN(1536, 24, 3, 8, 8, 8)
 HU_PLAN(2048, 16, 16, 16, 8)
 #undef HU_PLAN
+
+template <int L>
+struct Plan<L, 1> : Plan<L, 0> {};
+#define HU_ALT_PLAN(LEN, ...)                                                                  \
+  template <>                                                                                  \
+  struct Plan<LEN, 1> {                                                                        \
+    static constexpr int E = Plan<LEN, 0>::E;                                                  \
+    static constexpr int P = Plan<LEN, 0>::P;                                                  \
+    static constexpr bool alt = true;                                                          \
+    using fwd = Radices<__VA_ARGS__>;                                                          \
+    static_assert(RadProd<__VA_ARGS__>::value == LEN && RadDivE<E, __VA_ARGS__>::value,     \
+                  "radices multiply to the length and divide E");                             \
+  };
+HU_ALT_PLAN(256, 16, 4, 4)
+HU_ALT_PLAN(512, 16, 8, 4)
+HU_ALT_PLAN(1024, 8, 8, 16)
+HU_ALT_PLAN(2048, 16, 8, 16)
+#undef HU_ALT_PLAN
+
+// the radix choice a kernel of length L runs under the requested one (0 where L has no alternative)
+template <int L>
+constexpr int radix_choice(int rv) { return rv && Plan<L, 1>::alt ? 1 : 0; }
 
 template <int R0, int... Rs>
 struct FirstR { static constexpr int value = R0; };
@@ -235,10 +271,11 @@ struct PlanTab;
 template <int... Rs>
 struct PlanTab<Radices<Rs...>> { static constexpr int size = TabSize<1, Rs...>::value; };
 
-// complex entries of the stage table of length L (forward rows, then reversed-plan rows)
-template <int L>
+// complex entries of the stage table of length L under radix choice RV (forward rows, then
+// reversed-plan rows)
+template <int L, int RV = 0>
 struct StageTab {
-  using F = typename Plan<L>::fwd;
+  using F = typename Plan<L, RV>::fwd;
   static constexpr int fwd = PlanTab<F>::size;
   static constexpr int total = fwd + PlanTab<Reverse<F>>::size;
 };
@@ -405,17 +442,20 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int p, c
   }
 }
 
-// The transform with radix list Rs (the forward plan of L or its reverse); tw = the stage table
-// of L.  WAVE: the P threads of each transform lie in one wave and the region `lds` is theirs
+// The transform with radix list Rs (the forward list of Plan<L, RV> or its reverse); tw = the
+// stage table of L under radix choice RV, whose reversed-plan rows follow the forward rows.  A
+// list that reads the same both ways uses the forward rows for both directions (they are the same
+// rows).  WAVE: the P threads of each transform lie in one wave and the region `lds` is theirs
 // alone (row passes with P dividing 64), so the exchanges synchronise the wave only.
-template <int L, int P, int E, bool INV, bool WAVE = false, int... Rs>
+template <int L, int P, int E, bool INV, bool WAVE = false, int RV = 0, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[E], float2* lds, int p,
                                         const float2* __restrict__ tw) {
-  using F = typename Plan<L>::fwd;
-  constexpr bool is_fwd = std::is_same<Radices<Rs...>, F>::value;
-  static_assert(is_fwd || std::is_same<Radices<Rs...>, Reverse<F>>::value, "radix list is not a plan of L");
+  using A = Radices<Rs...>;
+  using F = typename Plan<L, RV>::fwd;
+  constexpr bool is_fwd = std::is_same<A, F>::value;
+  static_assert(is_fwd || std::is_same<A, Reverse<F>>::value, "radix list is not a plan of L");
   static_assert(!WAVE || (64 % P) == 0, "wave-local exchange needs each transform inside one wave");
-  fft_stages<L, P, E, INV, WAVE, 1, (is_fwd ? 0 : StageTab<L>::fwd), Rs...>(v, lds, p, tw);
+  fft_stages<L, P, E, INV, WAVE, 1, (is_fwd ? 0 : StageTab<L, RV>::fwd), Rs...>(v, lds, p, tw);
 }
 
 // ---------------------------------------------------------------------------------------------

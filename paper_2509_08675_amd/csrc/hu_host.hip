@@ -18,7 +18,7 @@ namespace hu {
 namespace {
 
 std::mutex g_mu;
-std::map<std::pair<int, int>, float2*> g_tw, g_tw2;
+std::map<std::pair<int, int>, float2*> g_tw, g_tw2, g_tw_alt;   // g_tw_alt: tables of Plan<L, 1>
 std::map<std::pair<int, int>, double*> g_edges;
 std::map<std::vector<long long>, BinGeo> g_bingeo;
 
@@ -243,14 +243,14 @@ static void append_stage_rows(int L, const std::vector<int>& rad, std::vector<fl
   }
 }
 
-template <int L>
+template <int L, int RV>
 static int make_stage_table_L(float2** out) {
-  using F = typename Plan<L>::fwd;
+  using F = typename Plan<L, RV>::fwd;
   std::vector<float2> h;
   append_stage_rows(L, radix_vec(F{}), h);
-  if ((int)h.size() != StageTab<L>::fwd) return HU_ERR_HIP;
+  if ((int)h.size() != StageTab<L, RV>::fwd) return HU_ERR_HIP;
   append_stage_rows(L, radix_vec(Reverse<F>{}), h);
-  if ((int)h.size() != StageTab<L>::total) return HU_ERR_HIP;
+  if ((int)h.size() != StageTab<L, RV>::total) return HU_ERR_HIP;
   h.push_back(make_float2(0.f, 0.f));           // never empty (lengths with one stage)
   float2* d = nullptr;
   if (hipMalloc(&d, sizeof(float2) * h.size()) != hipSuccess) return HU_ERR_HIP;
@@ -259,25 +259,39 @@ static int make_stage_table_L(float2** out) {
   return HU_OK;
 }
 
-static int make_stage_table(int L, float2** out) {
+#define HU_TW_LENGTHS(X) \
+  X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) \
+  X(1024) X(1536) X(2048)
+
+static int make_stage_table(int L, int rv, float2** out) {
   switch (L) {
-#define X(LL) case LL: return make_stage_table_L<LL>(out);
-    X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768)
-    X(1024) X(1536) X(2048)
+#define X(LL) case LL: return rv ? make_stage_table_L<LL, 1>(out) : make_stage_table_L<LL, 0>(out);
+    HU_TW_LENGTHS(X)
 #undef X
     default: return HU_ERR_SIZE;
   }
 }
 
-int get_tw(int L, const float2** tw) {
+bool plan_has_alt(int L) {
+  switch (L) {
+#define X(LL) case LL: return Plan<LL, 1>::alt;
+    HU_TW_LENGTHS(X)
+#undef X
+    default: return false;
+  }
+}
+
+int get_tw(int L, const float2** tw, int radix) {
   std::lock_guard<std::mutex> lk(g_mu);
+  const int rv = radix && plan_has_alt(L) ? 1 : 0;
+  auto& tab = rv ? g_tw_alt : g_tw;
   auto key = std::make_pair(current_device(), L);
-  auto it = g_tw.find(key);
-  if (it == g_tw.end()) {
+  auto it = tab.find(key);
+  if (it == tab.end()) {
     float2* d;
-    int rc = make_stage_table(L, &d);
+    int rc = make_stage_table(L, rv, &d);
     if (rc) return rc;
-    it = g_tw.emplace(key, d).first;
+    it = tab.emplace(key, d).first;
   }
   *tw = it->second;
   return HU_OK;
@@ -722,6 +736,8 @@ int tables_ready(const Geom& g, const hu_bins* bins) {
   if (!g_tw.count({dev, g.nx / 2}) || !g_tw2.count({dev, g.nx / 2}) || !g_tw.count({dev, g.n[0]}))
     return HU_ERR_TABLES;
   if (g.nd == 3 && !g_tw.count({dev, g.n[1]})) return HU_ERR_TABLES;
+  if (plan_has_alt(g.n[0]) && !g_tw_alt.count({dev, g.n[0]})) return HU_ERR_TABLES;
+  if (g.nd == 3 && plan_has_alt(g.n[1]) && !g_tw_alt.count({dev, g.n[1]})) return HU_ERR_TABLES;
   if (bins) {
     if (!g_edges.count({dev, bins->n_angular})) return HU_ERR_TABLES;
     const std::vector<long long> key = {dev, g.nd, g.n[0], g.n[1], g.n[2], bins->n_radial, bins->n_angular};
@@ -736,14 +752,16 @@ int tables_ready(const Geom& g, const hu_bins* bins) {
 }
 
 // every table a class needs, created before any launch (and before a graph capture); the tile
-// tables for both tile widths
+// tables for both tile widths, the stage tables for both radix choices
 int prepare_tables(const Geom& g, const hu_bins* bins, hipStream_t st) {
   (void)st;
   const float2 *a, *b;
   HU_TRY(get_tw(g.nx / 2, &a));
   HU_TRY(get_tw2(g.nx / 2, &b));
-  HU_TRY(get_tw(g.n[0], &a));
-  if (g.nd == 3) HU_TRY(get_tw(g.n[1], &a));
+  for (int rv = 0; rv < 2; ++rv) {
+    HU_TRY(get_tw(g.n[0], &a, rv));
+    if (g.nd == 3) HU_TRY(get_tw(g.n[1], &a, rv));
+  }
   if (bins) {
     BinDev bd{};
     BinGeo geo;
@@ -806,8 +824,9 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   const float2 *tw_row, *tw2_row, *tw_0, *tw_1 = nullptr;
   HU_TRY(get_tw(Lrow, &tw_row));
   HU_TRY(get_tw2(Lrow, &tw2_row));
-  HU_TRY(get_tw(g.n[0], &tw_0));
-  if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1));
+  const int rad = r.plan.v[P_RADIX];        // the column passes' radix lists (tables to match)
+  HU_TRY(get_tw(g.n[0], &tw_0, rad));
+  if (g.nd == 3) HU_TRY(get_tw(g.n[1], &tw_1, rad));
   const int nb = r.bins ? r.bins->n_radial * r.bins->n_angular + 1 : 0;
   BinGeo geo{nullptr, nullptr};
   TileBinDev tb_c{}, tb_p{};
@@ -860,7 +879,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     cy.inner = g.nxh;
     cy.tw = tw_1;
     cy.sc = col_sched(g.n[1], r.plan.v[P_COLY], cy.ncol, B, r.plan.v[P_YGROUP] ? 4 : Y_PASS_GROUP);
-    HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st); }));
+    HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st, rad); }));
   }
   // the fields of a tile on consecutive ids of one XCD (2D default) or field-major (3D default)
   const bool fields_xcd = (g.nd == 2) != (r.plan.v[P_FIELDS] != 0);
@@ -882,7 +901,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fa.partials = partials;
   fa.any_gen = (batch_mode ? r.any_gen : filt_general(r.filt, g)) ? 1 : 0;
   if (fa.sc.ntiles > r.lay.tiles) return HU_ERR_WORKSPACE;
-  HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], r.plan.v[P_FILTER], fa, st); }));
+  HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], r.plan.v[P_FILTER], fa, st, rad); }));
   FinalizeArgs fz{};
   fz.partials = partials;
   fz.ntiles = fa.sc.ntiles;
@@ -893,7 +912,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fz.io = r.io;
   HU_HIP(timed("finalize", st, [&] { return launch_finalize(fz, B, st); }));
 
-  if (g.nd == 3) HU_HIP(timed("cols_y_inv", st, [&] { return launch_cols(g.n[1], true, r.plan.v[P_COLY], cy, st); }));
+  if (g.nd == 3) HU_HIP(timed("cols_y_inv", st, [&] { return launch_cols(g.n[1], true, r.plan.v[P_COLY], cy, st, rad); }));
 
   RowsZArgs za{};
   za.spec = spec;
@@ -917,7 +936,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
                [&] { return launch_rows_c2r(Lrow, r.thresh, r.plan.v[P_C2R], za, B, st); }));
 
   if (want_pm1) {
-    if (g.nd == 3) HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st); }));
+    if (g.nd == 3) HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st, rad); }));
     BinArgs ba{};
     ba.ntiles = col_tiles(g.n[0], r.plan.v[P_BIN], g.Nh / g.n[0]);
     ba.batch = B;
@@ -931,7 +950,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     ba.tb = tb_p;
     ba.parts = parts_p;
     ba.tw = tw_0;
-    HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], r.plan.v[P_BIN], ba, st); }));
+    HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], r.plan.v[P_BIN], ba, st, rad); }));
   }
   if (want_cont || want_pm1 || want_counts) {
     SpecFinalArgs sf{};

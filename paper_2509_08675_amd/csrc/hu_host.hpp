@@ -37,8 +37,10 @@ struct Geom {
 // (default one item per workgroup in 2D, persistent with a work counter in 3D; 1 the other one),
 // P_FIELDS the axis-0 passes' placement of a tile's fields (default consecutive on one XCD in 2D,
 // field-major in 3D; 1 the other one), P_YGROUP the 3D y passes' tiles per XCD group (16, or 4).
+// Entry 8, P_RADIX: the radix lists of the column passes (y, filter, binning): 0 the default plan
+// of each length, 1 its alternative order where the length has one (Plan<L, 1>).
 enum { P_R2C = 0, P_COLY = 1, P_FILTER = 2, P_C2R = 3, P_BIN = 4, P_BINSCHED = 5, P_FIELDS = 6, P_YGROUP = 7,
-       NPASS = 8 };
+       P_RADIX = 8, NPASS = 9 };
 struct TunePlan {
   int v[NPASS];
 };
@@ -74,7 +76,10 @@ FiltDev filt_dev(const hu_filter& f, const Geom& g);
 bool filt_general(const hu_filter& f, const Geom& g);
 Axis0Geom axis0(const Geom& g);
 int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd);
-int get_tw(int L, const float2** tw);
+// the stage table of length L under radix choice `radix` (the default list where L has no
+// alternative)
+int get_tw(int L, const float2** tw, int radix = 0);
+bool plan_has_alt(int L);
 int get_tw2(int L, const float2** tw2);
 int get_bingeo(const Geom& g, const hu_bins& bins, BinGeo* out);
 // the tile-local bin tables of the axis-0 passes for tiles of C columns (device copy)

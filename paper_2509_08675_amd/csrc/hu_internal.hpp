@@ -252,8 +252,9 @@ struct FilterSpecArgs {
   BinDev bd;
   int nb;
   const uint16_t* table;
-  double* sum;             // [nb] raw sums of w H^2 (zeroed before the launch)
-  double* partials;        // [gridDim.x]: per-block sum of w H^2
+  double* sum;             // [nb] output: expected bin sums
+  double* partials;        // [gridDim.x]: per-workgroup sum of w H^2
+  double* rows;            // [gridDim.x][nb]: per-workgroup bin sums of w H^2
   int nblocks;
   long long N;
   double sigma_f;
@@ -291,12 +292,13 @@ hipError_t launch_spectrum_loss(const LossArgs& a, hipStream_t st);
 hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);
 hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st);
 hipError_t launch_rows_r2c(int L, int src, int variant, const RowsArgs& a, int batch, hipStream_t st);
-hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st);
-hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st);
+// radix: the alternative radix list of L where it has one (Plan<L, 1>)
+hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st, int radix = 0);
+hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st, int radix = 0);
 // columns per tile of the axis-0 passes with tile variant `variant`
 int col_width(int L, int variant);
 hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st);
-hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st);
+hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st, int radix = 0);
 hipError_t launch_rows_c2r(int L, bool thresh, int variant, const RowsZArgs& a, int batch, hipStream_t st);
 int row_tiles(int L, int variant, long long nrows);
 hipError_t launch_spec_final(const SpecFinalArgs& a, int batch, hipStream_t st);

@@ -88,6 +88,22 @@ def test_filter_spectrum_angular_matches_oracle(hf):
     np.testing.assert_allclose(s.cpu().numpy(), ref, rtol=1e-5, atol=1e-9 * ref.max())
 
 
+@pytest.mark.parametrize("dims,bins", [((96, 64), (16, 6)), ((512, 512), (128, 36)), ((128, 128, 128), (64, 1))])
+def test_filter_spectrum_is_bit_reproducible(hf, dims, bins):
+    """No floating-point atomics in the expected spectrum: repeated calls give the same bits (the
+    2D 512^2 case spans many chunks per workgroup, the 128^3 one many workgroups per bin)."""
+    filt = W.filt(p=3, semi=(2, 1, 1.5), rot=0.4, alpha=4, k0=0.2, width=0.05)
+    runs = []
+    for _ in range(3):
+        s, c = hf.filter_spectrum(dims, filt, bins)
+        torch.cuda.synchronize()
+        runs.append((s.cpu().numpy().copy(), hf.u64_view(c).copy()))
+    for s, c in runs[1:]:
+        assert np.array_equal(s.view(np.uint64), runs[0][0].view(np.uint64))
+        assert np.array_equal(c, runs[0][1])
+    assert np.all(np.isfinite(runs[0][0])) and runs[0][0].sum() > 0
+
+
 def _gpu_loss_grad(hf, dims, filt, seed, target, nr):
     theta = torch.tensor(_theta(filt), dtype=torch.float64, requires_grad=True)
     L = hf.spectrum_loss(theta, dims, seed, nr, target, filt["alpha"], filt.get("sigma_f", 1.0))

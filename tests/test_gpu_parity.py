@@ -157,6 +157,23 @@ def test_paper_operating_points(hf, name, dims, filt, bins, seeds):
     _compare_pipeline(hf, name, dims, filt, bins, seeds)
 
 
+# The alternative radix lists of the column passes (plan entry `radix`): every length that has
+# one, along axis 0 (filter and binning passes) and along the 3D y axis.
+RADIX_CASES = [("radix_2048x64", (2048, 64), (24, 8)), ("radix_1024x96", (1024, 96), (32, 6)),
+               ("radix_512x256x8", (512, 256, 8), (32, 1)), ("radix_256x256x16", (256, 256, 16), (48, 1))]
+
+
+@pytest.mark.parametrize("name,dims,bins", RADIX_CASES, ids=[c[0] for c in RADIX_CASES])
+def test_radix_alternatives_match_oracle(hf, name, dims, bins):
+    filt = _filt(p=3.0, semi=(2.0, 1.0, 1.5), rot=0.4, alpha=4.0, k0=0.2, width=0.05)
+    hf.plan_set(dims, 2, bins, [0] * 8 + [1])
+    try:
+        assert hf.plan_query(dims, 2, bins)["radix"] == 1
+        _compare_pipeline(hf, name, dims, filt, bins, [71, 72])
+    finally:
+        hf.plan_set(dims, 2, bins, [0] * 9)
+
+
 def test_gen_field_matches_pipeline_field(hf):
     dims, filt = (64, 96), _filt(p=3, semi=(2, 1), rot=0.5, alpha=4, k0=0.2, width=0.05)
     _say("gen_field vs pipeline", dims)
@@ -233,13 +250,18 @@ def test_power_spectrum_standalone(hf, dims, bins, kind):
 # ---------------------------------------------------------------------------------------------
 # full benchmark sizes, in the benchmark's launch configuration, sampled fields vs the oracle
 # ---------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("cfg,sample", [(W.C2, [0, 15]), (W.C3, [0])], ids=["c2_2048sq_x16", "c3_256cube_x4"])
-def test_full_size_sampled(hf, cfg, sample):
+@pytest.mark.parametrize("cfg,sample,radix", [(W.C2, [0, 15], 0), (W.C3, [0], 0), (W.C2, [7], 1), (W.C3, [3], 1)],
+                         ids=["c2_2048sq_x16", "c3_256cube_x4", "c2_2048sq_x16_radix1", "c3_256cube_x4_radix1"])
+def test_full_size_sampled(hf, cfg, sample, radix):
     dims, bins, seeds = cfg["dims"], cfg["bins"], cfg["seeds"]
-    _say("full size", cfg["name"])
+    _say("full size", cfg["name"], "radix", radix)
+    hf.plan_set(dims, len(seeds), bins, [0] * 8 + [radix])
     bufs = hf.PipelineBuffers(dims, len(seeds), bins)
-    hf.pipeline(bufs, cfg["filt"], seeds)
-    torch.cuda.synchronize()
+    try:
+        hf.pipeline(bufs, cfg["filt"], seeds)
+        torch.cuda.synchronize()
+    finally:
+        hf.plan_set(dims, len(seeds), bins, [0] * 9)
     hf.check_degenerate(bufs.stats)
     N = int(np.prod(dims))
     for i in sample:

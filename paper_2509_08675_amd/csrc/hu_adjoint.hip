@@ -557,7 +557,8 @@ __global__ void __launch_bounds__(FS_THREADS) k_filter_spectrum(FilterSpecArgs a
   }
 }
 
-// one thread per bin: the rows in workgroup order; every workgroup forms the same total
+// one wave per bin: lane l adds rows l, l + 64, ... in order, then a fixed butterfly; every
+// workgroup forms the same total of the per-workgroup sums
 __global__ void __launch_bounds__(256) k_filter_spectrum_final(FilterSpecArgs a) {
   __shared__ double red[256];
   const int tid = threadIdx.x;
@@ -570,12 +571,15 @@ __global__ void __launch_bounds__(256) k_filter_spectrum_final(FilterSpecArgs a)
     __syncthreads();
   }
   const double fac = red[0] > 0.0 ? a.sigma_f * a.sigma_f * (double)a.N / red[0] : 0.0;
-  const int i = blockIdx.x * 256 + tid;
+  const int i = blockIdx.x * 4 + (tid >> 6), lane = tid & 63;
   if (i >= a.nb) return;
   double b = 0.0;
-  for (int r = 0; r < a.nblocks; ++r) b += a.rows[(long long)r * a.nb + i];
-  a.sum[i] = b * fac;
-  if (a.cnt) a.cnt[i] = a.counts[i];
+  for (int r = lane; r < a.nblocks; r += 64) b += a.rows[(long long)r * a.nb + i];
+  b = wave_sum(b);
+  if (lane == 0) {
+    a.sum[i] = b * fac;
+    if (a.cnt) a.cnt[i] = a.counts[i];
+  }
 }
 
 hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st) {
@@ -586,7 +590,7 @@ hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_filter_spectrum<3>, dim3(a.nblocks), dim3(FS_THREADS), lds, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_filter_spectrum_final, dim3((a.nb + 255) / 256), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_filter_spectrum_final, dim3((a.nb + 3) / 4), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

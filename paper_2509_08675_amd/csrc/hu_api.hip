@@ -58,7 +58,7 @@ WvarLayout wvar_layout(const Geom& g, int chunk) {
 }
 
 // workspace of hu_filter_spectrum: the per-workgroup totals, then the per-workgroup bin rows
-constexpr int FS_MAX_BLOCKS = 256;
+constexpr int FS_MAX_BLOCKS = 1024;
 int fs_blocks(const Geom& g) {
   const long long chunk = 256LL * 16;
   const long long n = (g.Nh + chunk - 1) / chunk;

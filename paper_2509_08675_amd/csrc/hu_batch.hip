@@ -59,7 +59,7 @@ int ensure_streams() {
   return HU_OK;
 }
 
-TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0}}; }
+TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0}}; }
 
 int job_status(const hu_job& j, Geom* g) {
   int rc = make_geom(j.dims, g);
@@ -381,16 +381,26 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
   TunePlan best{};
   double warm = 0.0;
   for (int i = 0; i < 64 && warm < 50.0 && rc == HU_OK; ++i) warm += 7.0 * time_plan(best);
-  for (int k = 0; k < NPASS && rc == HU_OK; ++k) {
-    if (g.nd == 2 && (k == P_COLY || k == P_YGROUP)) continue;
-    if (k == P_RADIX && !plan_has_alt(g.n[0]) && !(g.nd == 3 && plan_has_alt(g.n[1]))) continue;
-    TunePlan cand = best;
-    cand.v[k] ^= 1;
-    double tb = 0.0, tc = 0.0;
-    paired(best, cand, tb, tc);
-    if (rc != HU_OK) break;
-    tried[k] = tc;
-    if (tc > 0.0 && tc < 0.99 * tb) best = cand;
+  // a second sweep when the first changed something (choices interact: the split exchange only
+  // adds resident workgroups together with the narrower filter tiles)
+  for (int sweep = 0; sweep < 2 && rc == HU_OK; ++sweep) {
+    bool changed = false;
+    for (int k = 0; k < NPASS && rc == HU_OK; ++k) {
+      if (g.nd == 2 && (k == P_COLY || k == P_YGROUP)) continue;
+      if (k == P_RADIX && !plan_has_alt(g.n[0]) && !(g.nd == 3 && plan_has_alt(g.n[1]))) continue;
+      if ((k == P_BSPLIT || k == P_FSPLIT) && !split_length(g.n[0])) continue;
+      TunePlan cand = best;
+      cand.v[k] ^= 1;
+      double tb = 0.0, tc = 0.0;
+      paired(best, cand, tb, tc);
+      if (rc != HU_OK) break;
+      tried[k] = tc;
+      if (tc > 0.0 && tc < 0.99 * tb) {
+        best = cand;
+        changed = true;
+      }
+    }
+    if (!changed) break;
   }
   // the default and the tuned plan measured side by side once the search is done; the default is
   // kept unless the tuned plan still wins there

@@ -13,7 +13,7 @@ namespace hu {
 // forward transform of a tile's columns, the per-mode values w |X|^2 into LDS, then (while the next
 // item's columns are already being loaded into the transform's registers) the tile's deterministic
 // bin partials.
-template <int L, int V, int RV>
+template <int L, int V, int RV, bool SPLIT>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
   constexpr int LP = ColTile<L, V>::LP;
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
       const int tile = it / a.batch, b = it - tile * a.batch;
       const int g = tile * C + c;
       const bool valid = g < a.gm.ncol;
-      fft_run<L, P, E, false, false, RV>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
+      fft_run<L, P, E, false, false, RV>(Rad{}, v, col_region<L, V, SPLIT>(lds, c), p, a.tw);
       const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
       __syncthreads();                              // the exchange buffer is free from here
 #pragma unroll
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin(BinArgs a) {
 
 // One item per workgroup (the default in 2D, where the schedule's XCD mapping puts the fields of a
 // tile on one XCD, which then reads the tile's slice of the bin table once).
-template <int L, int V, int RV>
+template <int L, int V, int RV, bool SPLIT>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin_tile(BinArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
   constexpr int LP = ColTile<L, V>::LP;
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin_tile(BinArgs a)
   const bool valid = g < a.gm.ncol;
   float2 v[E];
   col_load<L, R1, P, E>(v, col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, g, p));
-  fft_run<L, P, E, false, false, RV>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
+  fft_run<L, P, E, false, false, RV>(Rad{}, v, col_region<L, V, SPLIT>(lds, c), p, a.tw);
   const float wm = (valid && col_coord(a.gm, g).wm > 1.5f) ? 2.0f : 1.0f;
   for (int j = tid; j < a.tb.nloc_max; j += T) {
     hx[j] = HX_EMPTY;
@@ -103,31 +103,31 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_bin_tile(BinArgs a)
   tile_bins<L, E, C, LP, T>(pw, hx, hq, a.tb, (int)tile, a.gm.ncol, a.parts + (long long)b * a.tb.M, tid);
 }
 
-template <int L, int V, int RV>
+template <int L, int V, int RV, bool SPLIT>
 static hipError_t launch_cols_bin_L(BinArgs a, hipStream_t st) {
   constexpr int T = ColTile<L, V>::T;
   if (a.q.nitems <= 0) return hipSuccess;
-  a.hx_off = (int)col_bin_base<L, V>();
+  a.hx_off = (int)col_bin_base<L, V, SPLIT>();
   a.hq_off = a.hx_off + (a.tb.nloc_max * 4 + 15) / 16 * 16;
   const size_t lds = (size_t)a.hq_off + (size_t)a.tb.nloc_max * 8;
   if (!a.persistent) {
-    hipLaunchKernelGGL((k_cols_bin_tile<L, V, RV>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
+    hipLaunchKernelGGL((k_cols_bin_tile<L, V, RV, SPLIT>), dim3(sched_blocks(a.sc)), dim3(T), lds, st, a);
     return hipGetLastError();
   }
   int slots = 0;
-  const hipError_t e = resident_blocks(reinterpret_cast<const void*>(&k_cols_bin<L, V, RV>), T, lds, &slots);
+  const hipError_t e = resident_blocks(reinterpret_cast<const void*>(&k_cols_bin<L, V, RV, SPLIT>), T, lds, &slots);
   if (e != hipSuccess) return e;
   const unsigned grid = (unsigned)(slots < a.q.nitems ? slots : a.q.nitems);
-  hipLaunchKernelGGL((k_cols_bin<L, V, RV>), dim3(grid), dim3(T), lds, st, a);
+  hipLaunchKernelGGL((k_cols_bin<L, V, RV, SPLIT>), dim3(grid), dim3(T), lds, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st, int radix) {
+hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st, int radix, int split) {
   switch (L) {
-#define X(LL)                                                                                \
-  case LL:                                                                                   \
-    return with_choices<LL>(variant, radix, [&](auto v, auto r) {                            \
-      return launch_cols_bin_L<LL, decltype(v)::value, decltype(r)::value>(a, st);         \
+#define X(LL)                                                                                             \
+  case LL:                                                                                                \
+    return with_choices3<LL>(variant, radix, split, [&](auto v, auto r, auto s) {                         \
+      return launch_cols_bin_L<LL, decltype(v)::value, decltype(r)::value, decltype(s)::value>(a, st);    \
     });
     HU_COL_LENGTHS(X)
 #undef X

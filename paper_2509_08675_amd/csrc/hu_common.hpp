@@ -31,6 +31,24 @@ struct RowTile {
   static constexpr int RS = Region<L>::value;          // exchange region per row
 };
 
+// Offset of the split-exchange region stride beyond L + L/16 floats for the default plan of L and
+// C columns per tile: the value in 0 .. 32 with the fewest LDS bank conflicts over every exchange
+// store and load of the transform, counted for 32 four-byte banks and 32 lanes per LDS cycle
+// (conflict-free for most tiles; 384, 512 and 768 keep some two-way conflicts).
+constexpr int split_extra(int L, int C) {
+  switch (L) {
+    case 6: case 12: case 32: return 1;
+    case 48: return C >= 32 ? 0 : 3;
+    case 64: case 128: case 192: case 256: return C >= 32 ? 1 : 2;
+    case 96: return C >= 32 ? 1 : 0;
+    case 384: return C >= 20 ? 14 : 4;
+    case 512: return C >= 16 ? 2 : 4;
+    case 768: return C >= 10 ? 11 : 8;
+    case 1024: return C >= 8 ? 4 : 8;
+    case 2048: return C >= 4 ? 8 : 16;
+    default: return 0;
+  }
+}
 template <int L, int V = 0>
 struct ColTile {
   static constexpr int P = Plan<L>::P;
@@ -49,6 +67,8 @@ struct ColTile {
   // padded power-value layout for run-length binning: 4 floats after every 16, and an odd
   // number of words per column
   static constexpr int LP = (L + (L / 16) * 4 + 31) / 32 * 32 + 1;
+  // split exchange (real and imaginary parts in two rounds): floats per column region
+  static constexpr int RSH = L + (L >> 4) + split_extra(L, C);
 };
 
 __host__ __device__ constexpr int pw_index(int e) { return e + (e >> 4) * 4; }
@@ -63,6 +83,15 @@ inline hipError_t with_choices(int variant, int radix, F&& f) {
     if (radix) return variant ? f(I1{}, I1{}) : f(I0{}, I1{});
   }
   return variant ? f(I1{}, I0{}) : f(I0{}, I0{});
+}
+// the same with the exchange choice as a third constant (split only where split_length(L))
+template <int L, class F>
+inline hipError_t with_choices3(int variant, int radix, int split, F&& f) {
+  if constexpr (split_length(L)) {
+    if (split)
+      return with_choices<L>(variant, radix, [&](auto v, auto r) { return f(v, r, std::true_type{}); });
+  }
+  return with_choices<L>(variant, radix, [&](auto v, auto r) { return f(v, r, std::false_type{}); });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -448,18 +477,25 @@ __device__ __forceinline__ void tile_bins(const float* pw, int* hx, unsigned lon
   }
 }
 
-template <int L, int V>
+template <int L, int V, bool SPLIT = false>
 __host__ __device__ constexpr size_t col_xchg_bytes() {
-  return (size_t)ColTile<L, V>::C * ColTile<L, V>::RS * 8;
+  return SPLIT ? (size_t)ColTile<L, V>::C * ColTile<L, V>::RSH * 4 : (size_t)ColTile<L, V>::C * ColTile<L, V>::RS * 8;
 }
 
 // LDS of an axis-0 pass that bins: the exchange buffer (the power values reuse it), then the tile
 // histogram (nloc_max exponents and fixed-point sums)
-template <int L, int V>
+template <int L, int V, bool SPLIT = false>
 __host__ __device__ constexpr size_t col_bin_base() {
-  return ((col_xchg_bytes<L, V>() > (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4
-               ? col_xchg_bytes<L, V>()
+  return ((col_xchg_bytes<L, V, SPLIT>() > (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4
+               ? col_xchg_bytes<L, V, SPLIT>()
                : (size_t)ColTile<L, V>::C * ColTile<L, V>::LP * 4) + 15) / 16 * 16;
+}
+
+// the exchange region of column c of a tile: complex, or floats for the split exchange
+template <int L, int V, bool SPLIT>
+__device__ __forceinline__ auto col_region(float2* lds, int c) {
+  if constexpr (SPLIT) return reinterpret_cast<float*>(lds) + c * ColTile<L, V>::RSH;
+  else return lds + c * ColTile<L, V>::RS;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -392,6 +392,49 @@ __device__ __forceinline__ void stage_load(float2 (&v)[E], const float2* lds, in
   }
 }
 
+// Split exchange: the same positions in a region of floats, one component (COMP 0: real, 1:
+// imaginary) per round, so the region takes half the LDS of a complex one.
+template <int COMP>
+__device__ __forceinline__ float& part(float2& a) { return COMP ? a.y : a.x; }
+template <int COMP>
+__device__ __forceinline__ float part(const float2& a) { return COMP ? a.y : a.x; }
+
+template <int L, int R, int NS, int P, int E, int COMP>
+__device__ __forceinline__ void stage_store(const float2 (&v)[E], float* lds, int p) {
+  using M = StoreMap<R, NS, P, E>;
+  if constexpr (M::lin) {
+    float* sp = lds + lidx(M::base(p));
+#pragma unroll
+    for (int b = 0; b < E / R; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) sp[M::off(0, b, r)] = part<COMP>(v[b * R + r]);
+  } else {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+      const int base = M::base(p + P * b);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lidx(base + r * NS)] = part<COMP>(v[b * R + r]);
+    }
+  }
+}
+
+template <int L, int R, int P, int E, int COMP>
+__device__ __forceinline__ void stage_load(float2 (&v)[E], const float* lds, int p) {
+  using M = LoadMap<L, R, P, E>;
+  if constexpr (M::lin) {
+    const float* lp = lds + lidx(p);
+#pragma unroll
+    for (int b = 0; b < E / R; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) part<COMP>(v[b * R + r]) = lp[M::off(0, b, r)];
+  } else {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b)
+#pragma unroll
+      for (int r = 0; r < R; ++r) part<COMP>(v[b * R + r]) = lds[lidx(p + P * b + r * (L / R))];
+  }
+}
+
 template <int L, int R, int P, int E>
 __device__ __forceinline__ void slot_store(const float2 (&v)[E], float2* lds, int p) {
   using M = LoadMap<L, R, P, E>;
@@ -429,16 +472,29 @@ __device__ __forceinline__ void xchg_sync() {
   }
 }
 
-template <int L, int P, int E, bool INV, bool WAVE, int NS, int SOFF, int R, int... Rest>
-__device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int p, const float2* __restrict__ tw) {
+// X = float2: one complex exchange per stage; X = float: the split exchange, real parts then
+// imaginary parts through the same float region (two more barriers, half the LDS).
+template <class X, int L, int P, int E, bool INV, bool WAVE, int NS, int SOFF, int R, int... Rest>
+__device__ __forceinline__ void fft_stages(float2 (&v)[E], X* lds, int p, const float2* __restrict__ tw) {
   stage_compute<L, R, NS, P, E, INV, SOFF>(v, p, tw);
   if constexpr (sizeof...(Rest) > 0) {
     constexpr int R2 = FirstR<Rest...>::value;
-    xchg_sync<WAVE>();
-    stage_store<L, R, NS, P, E>(v, lds, p);
-    xchg_sync<WAVE>();
-    stage_load<L, R2, P, E>(v, lds, p);
-    fft_stages<L, P, E, INV, WAVE, NS * R, (NS > 1 ? SOFF + NS * rpad(R) : SOFF), Rest...>(v, lds, p, tw);
+    if constexpr (std::is_same<X, float>::value) {
+      xchg_sync<WAVE>();
+      stage_store<L, R, NS, P, E, 0>(v, lds, p);
+      xchg_sync<WAVE>();
+      stage_load<L, R2, P, E, 0>(v, lds, p);
+      xchg_sync<WAVE>();
+      stage_store<L, R, NS, P, E, 1>(v, lds, p);
+      xchg_sync<WAVE>();
+      stage_load<L, R2, P, E, 1>(v, lds, p);
+    } else {
+      xchg_sync<WAVE>();
+      stage_store<L, R, NS, P, E>(v, lds, p);
+      xchg_sync<WAVE>();
+      stage_load<L, R2, P, E>(v, lds, p);
+    }
+    fft_stages<X, L, P, E, INV, WAVE, NS * R, (NS > 1 ? SOFF + NS * rpad(R) : SOFF), Rest...>(v, lds, p, tw);
   }
 }
 
@@ -446,16 +502,17 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[E], float2* lds, int p, c
 // stage table of L under radix choice RV, whose reversed-plan rows follow the forward rows.  A
 // list that reads the same both ways uses the forward rows for both directions (they are the same
 // rows).  WAVE: the P threads of each transform lie in one wave and the region `lds` is theirs
-// alone (row passes with P dividing 64), so the exchanges synchronise the wave only.
-template <int L, int P, int E, bool INV, bool WAVE = false, int RV = 0, int... Rs>
-__device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[E], float2* lds, int p,
+// alone (row passes with P dividing 64), so the exchanges synchronise the wave only.  `lds` is a
+// complex region (X = float2) or, for the split exchange, a float region of the same positions.
+template <int L, int P, int E, bool INV, bool WAVE = false, int RV = 0, class X = float2, int... Rs>
+__device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[E], X* lds, int p,
                                         const float2* __restrict__ tw) {
   using A = Radices<Rs...>;
   using F = typename Plan<L, RV>::fwd;
   constexpr bool is_fwd = std::is_same<A, F>::value;
   static_assert(is_fwd || std::is_same<A, Reverse<F>>::value, "radix list is not a plan of L");
   static_assert(!WAVE || (64 % P) == 0, "wave-local exchange needs each transform inside one wave");
-  fft_stages<L, P, E, INV, WAVE, 1, (is_fwd ? 0 : StageTab<L, RV>::fwd), Rs...>(v, lds, p, tw);
+  fft_stages<X, L, P, E, INV, WAVE, 1, (is_fwd ? 0 : StageTab<L, RV>::fwd), Rs...>(v, lds, p, tw);
 }
 
 // ---------------------------------------------------------------------------------------------

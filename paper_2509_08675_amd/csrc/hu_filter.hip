@@ -9,7 +9,7 @@
 namespace hu {
 
 // One tile of C columns of one field per workgroup.
-template <int L, int NDIM, int V, bool GEN, int RV>
+template <int L, int NDIM, int V, bool GEN, int RV, bool SPLIT>
 __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a) {
   constexpr int P = Plan<L>::P, E = Plan<L>::E, C = ColTile<L, V>::C, T = ColTile<L, V>::T;
   constexpr int LP = ColTile<L, V>::LP;
@@ -29,7 +29,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   const ColIO io = col_io<L>(a.spec + (long long)b * a.Nh, a.Nh, a.gm.inner0, g, p);
   float2 v[E];
   col_load<L, R1, P, E>(v, io);
-  fft_run<L, P, E, false, false, RV>(Rad{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
+  fft_run<L, P, E, false, false, RV>(Rad{}, v, col_region<L, V, SPLIT>(lds, c), p, a.tw);
 
   // ---- filter and per-thread statistics
   const bool do_bins = a.parts != nullptr;
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__((ColTile<L, V>::T)) k_cols_filter(FilterArgs a
   }
 
   // ---- inverse transform along axis 0 (first radix = last forward radix: no exchange needed)
-  fft_run<L, P, E, true, false, RV>(RadI{}, v, lds + c * ColTile<L, V>::RS, p, a.tw);
+  fft_run<L, P, E, true, false, RV>(RadI{}, v, col_region<L, V, SPLIT>(lds, c), p, a.tw);
   __builtin_amdgcn_s_setprio(2);                 // the stores out ahead of other workgroups' transforms
   if (valid) col_store<L, R1, P, E>(v, io);
   __builtin_amdgcn_s_setprio(0);
@@ -158,23 +158,23 @@ hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int L, int V, int RV>
+template <int L, int V, int RV, bool SPLIT>
 static hipError_t launch_cols_filter_L(FilterArgs a, hipStream_t st) {
   constexpr int T = ColTile<L, V>::T;
-  size_t lds = col_xchg_bytes<L, V>();
+  size_t lds = col_xchg_bytes<L, V, SPLIT>();
   if (a.parts) {
-    a.hx_off = (int)col_bin_base<L, V>();
+    a.hx_off = (int)col_bin_base<L, V, SPLIT>();
     a.hq_off = a.hx_off + (a.tb.nloc_max * 4 + 15) / 16 * 16;
     lds = (size_t)a.hq_off + (size_t)a.tb.nloc_max * 8;
   }
   // the tabulated-form and FP64 branches only in the instantiation launched when a field may use one
   const dim3 grid(sched_blocks(a.sc));
   if (a.gm.ndim == 2) {
-    if (a.any_gen) hipLaunchKernelGGL((k_cols_filter<L, 2, V, true, RV>), grid, dim3(T), lds, st, a);
-    else hipLaunchKernelGGL((k_cols_filter<L, 2, V, false, RV>), grid, dim3(T), lds, st, a);
+    if (a.any_gen) hipLaunchKernelGGL((k_cols_filter<L, 2, V, true, RV, SPLIT>), grid, dim3(T), lds, st, a);
+    else hipLaunchKernelGGL((k_cols_filter<L, 2, V, false, RV, SPLIT>), grid, dim3(T), lds, st, a);
   } else {
-    if (a.any_gen) hipLaunchKernelGGL((k_cols_filter<L, 3, V, true, RV>), grid, dim3(T), lds, st, a);
-    else hipLaunchKernelGGL((k_cols_filter<L, 3, V, false, RV>), grid, dim3(T), lds, st, a);
+    if (a.any_gen) hipLaunchKernelGGL((k_cols_filter<L, 3, V, true, RV, SPLIT>), grid, dim3(T), lds, st, a);
+    else hipLaunchKernelGGL((k_cols_filter<L, 3, V, false, RV, SPLIT>), grid, dim3(T), lds, st, a);
   }
   return hipGetLastError();
 }
@@ -188,12 +188,12 @@ int col_width(int L, int variant) {
   }
 }
 
-hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st, int radix) {
+hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st, int radix, int split) {
   switch (L) {
-#define X(LL)                                                                                \
-  case LL:                                                                                   \
-    return with_choices<LL>(variant, radix, [&](auto v, auto r) {                            \
-      return launch_cols_filter_L<LL, decltype(v)::value, decltype(r)::value>(a, st);      \
+#define X(LL)                                                                                             \
+  case LL:                                                                                                \
+    return with_choices3<LL>(variant, radix, split, [&](auto v, auto r, auto s) {                         \
+      return launch_cols_filter_L<LL, decltype(v)::value, decltype(r)::value, decltype(s)::value>(a, st); \
     });
     HU_COL_LENGTHS(X)
 #undef X

@@ -901,7 +901,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fa.partials = partials;
   fa.any_gen = (batch_mode ? r.any_gen : filt_general(r.filt, g)) ? 1 : 0;
   if (fa.sc.ntiles > r.lay.tiles) return HU_ERR_WORKSPACE;
-  HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], r.plan.v[P_FILTER], fa, st, rad); }));
+  HU_HIP(timed("cols_filter", st, [&] { return launch_cols_filter(g.n[0], r.plan.v[P_FILTER], fa, st, rad, r.plan.v[P_FSPLIT]); }));
   FinalizeArgs fz{};
   fz.partials = partials;
   fz.ntiles = fa.sc.ntiles;
@@ -950,7 +950,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     ba.tb = tb_p;
     ba.parts = parts_p;
     ba.tw = tw_0;
-    HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], r.plan.v[P_BIN], ba, st, rad); }));
+    HU_HIP(timed("cols_bin", st, [&] { return launch_cols_bin(g.n[0], r.plan.v[P_BIN], ba, st, rad, (g.nd == 2) != (r.plan.v[P_BSPLIT] != 0)); }));
   }
   if (want_cont || want_pm1 || want_counts) {
     SpecFinalArgs sf{};

@@ -38,9 +38,13 @@ struct Geom {
 // P_FIELDS the axis-0 passes' placement of a tile's fields (default consecutive on one XCD in 2D,
 // field-major in 3D; 1 the other one), P_YGROUP the 3D y passes' tiles per XCD group (16, or 4).
 // Entry 8, P_RADIX: the radix lists of the column passes (y, filter, binning): 0 the default plan
-// of each length, 1 its alternative order where the length has one (Plan<L, 1>).
+// of each length, 1 its alternative order where the length has one (Plan<L, 1>).  Entries 9 and
+// 10, P_BSPLIT and P_FSPLIT: the exchange of the binning and of the filter pass along axis 0,
+// complex or split (real and imaginary parts in two rounds: half the LDS, more resident
+// workgroups, two more barriers per exchange; axis-0 lengths >= 192).  Default: the binning pass
+// split in 2D and complex in 3D, the filter pass complex; 1 the other one.
 enum { P_R2C = 0, P_COLY = 1, P_FILTER = 2, P_C2R = 3, P_BIN = 4, P_BINSCHED = 5, P_FIELDS = 6, P_YGROUP = 7,
-       P_RADIX = 8, NPASS = 9 };
+       P_RADIX = 8, P_BSPLIT = 9, P_FSPLIT = 10, NPASS = 11 };
 struct TunePlan {
   int v[NPASS];
 };

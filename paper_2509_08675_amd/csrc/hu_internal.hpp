@@ -9,6 +9,11 @@
 
 namespace hu {
 
+// lengths whose axis-0 filter and binning passes are compiled with the split exchange too
+// (shorter columns have small exchange buffers)
+constexpr bool split_length(int L) { return L >= 192; }
+
+
 enum { SRC_NOISE = 0, SRC_F32 = 1, SRC_I8 = 2 };
 constexpr int MAX_CHUNK = 64;   // fields per launch when seeds travel in the kernel arguments
 constexpr int NVARIANT = 2;     // tile-width variants per kernel: 0 = default, 1 = half width
@@ -294,11 +299,12 @@ hipError_t launch_filter_spectrum(const FilterSpecArgs& a, hipStream_t st);
 hipError_t launch_rows_r2c(int L, int src, int variant, const RowsArgs& a, int batch, hipStream_t st);
 // radix: the alternative radix list of L where it has one (Plan<L, 1>)
 hipError_t launch_cols(int L, bool inv, int variant, const ColsArgs& a, hipStream_t st, int radix = 0);
-hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st, int radix = 0);
+// split: the split exchange (real and imaginary parts in two rounds, half the LDS), lengths >= 192
+hipError_t launch_cols_filter(int L, int variant, const FilterArgs& a, hipStream_t st, int radix = 0, int split = 0);
 // columns per tile of the axis-0 passes with tile variant `variant`
 int col_width(int L, int variant);
 hipError_t launch_finalize(const FinalizeArgs& a, int batch, hipStream_t st);
-hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st, int radix = 0);
+hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st, int radix = 0, int split = 0);
 hipError_t launch_rows_c2r(int L, bool thresh, int variant, const RowsZArgs& a, int batch, hipStream_t st);
 int row_tiles(int L, int variant, long long nrows);
 hipError_t launch_spec_final(const SpecFinalArgs& a, int batch, hipStream_t st);

@@ -148,25 +148,26 @@ def test_batch_invalid_job_keeps_others(hf):
 
 
 @pytest.mark.parametrize("dims,bins", [((256, 512), (32, 12)), ((2048, 64), (16, 4)), ((32, 64, 48), (24, 1)),
-                                       ((96, 96, 96), (32, 1))])
+                                       ((96, 96, 96), (32, 1)), ((256, 32, 16), (24, 1))])
 def test_half_width_variants_match(hf, dims, bins):
     _say("variants", dims)
     filt = W.filt(p=3, semi=(2, 1, 1.5), rot=0.4, alpha=4, k0=0.2, width=0.05)
     seeds = [11, 12]
-    hf.plan_set(dims, 2, bins, [0] * 9)
+    hf.plan_set(dims, 2, bins, [0] * 11)
     b0 = hf.PipelineBuffers(dims, 2, bins)
     hf.pipeline(b0, filt, seeds)
-    hf.plan_set(dims, 2, bins, [1] * 8 + [0])          # every tile width and schedule switched
+    switched = [1] * 8 + [0, 1, 1]                      # every tile width, schedule and exchange
+    hf.plan_set(dims, 2, bins, switched)
     b1 = hf.PipelineBuffers(dims, 2, bins)
     hf.pipeline(b1, filt, seeds)
     torch.cuda.synchronize()
-    assert hf.plan_query(dims, 2, bins) == dict(zip(hf.PASS_NAMES, [1] * 8 + [0]))
+    assert hf.plan_query(dims, 2, bins) == dict(zip(hf.PASS_NAMES, switched))
     assert torch.equal(b0.field, b1.field) and torch.equal(b0.pm1, b1.pm1)
     np.testing.assert_allclose(b0.pm1_sum.cpu().numpy(), b1.pm1_sum.cpu().numpy(), rtol=1e-10, atol=1e-9)
     ref = O.pipeline(dims, O.FilterParams(**filt), seeds[1], *bins)
     f = b1.field[1].double().cpu().numpy()
     assert np.max(np.abs(f - ref["f"])) <= 1e-5 * math.sqrt(float(np.mean(ref["f"] ** 2)))
-    hf.plan_set(dims, 2, bins, [0] * 9)
+    hf.plan_set(dims, 2, bins, [0] * 11)
 
 
 def test_autotune_writes_plan(hf, tmp_path):
@@ -174,12 +175,13 @@ def test_autotune_writes_plan(hf, tmp_path):
     path = str(tmp_path / "tune.json")
     _say("autotune", dims)
     plan, ms = hf.autotune(dims, 4, bins, path)
-    assert set(plan.values()) <= {0, 1} and len(plan) == 9
+    assert set(plan.values()) <= {0, 1} and len(plan) == 11
     assert ms["default_ms"] > 0 and 0 < ms["tuned_ms"] <= ms["default_ms"]
     assert ms["flipped_ms"]["cols_filter"] > 0 and ms["flipped_ms"]["y_group"] == 0   # 2D: no y passes
     assert ms["flipped_ms"]["radix"] > 0                # 256 has an alternative radix list
+    assert ms["flipped_ms"]["bin_exchange"] > 0 and ms["flipped_ms"]["filter_exchange"] > 0
     d = json.load(open(path))
     keys = [k for k in d["plans"] if "256x256x1" in k]
     assert keys and d["plans"][keys[0]] == [plan[n] for n in hf.PASS_NAMES]
     assert hf.plan_query(dims, 4, bins) == plan
-    hf.plan_set(dims, 4, bins, [0] * 9)                 # later tests run the default plan
+    hf.plan_set(dims, 4, bins, [0] * 11)                # later tests run the default plan

@@ -166,12 +166,12 @@ RADIX_CASES = [("radix_2048x64", (2048, 64), (24, 8)), ("radix_1024x96", (1024, 
 @pytest.mark.parametrize("name,dims,bins", RADIX_CASES, ids=[c[0] for c in RADIX_CASES])
 def test_radix_alternatives_match_oracle(hf, name, dims, bins):
     filt = _filt(p=3.0, semi=(2.0, 1.0, 1.5), rot=0.4, alpha=4.0, k0=0.2, width=0.05)
-    hf.plan_set(dims, 2, bins, [0] * 8 + [1])
+    hf.plan_set(dims, 2, bins, [0] * 8 + [1, 0, 0])
     try:
         assert hf.plan_query(dims, 2, bins)["radix"] == 1
         _compare_pipeline(hf, name, dims, filt, bins, [71, 72])
     finally:
-        hf.plan_set(dims, 2, bins, [0] * 9)
+        hf.plan_set(dims, 2, bins, [0] * 11)
 
 
 def test_gen_field_matches_pipeline_field(hf):
@@ -250,18 +250,27 @@ def test_power_spectrum_standalone(hf, dims, bins, kind):
 # ---------------------------------------------------------------------------------------------
 # full benchmark sizes, in the benchmark's launch configuration, sampled fields vs the oracle
 # ---------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("cfg,sample,radix", [(W.C2, [0, 15], 0), (W.C3, [0], 0), (W.C2, [7], 1), (W.C3, [3], 1)],
-                         ids=["c2_2048sq_x16", "c3_256cube_x4", "c2_2048sq_x16_radix1", "c3_256cube_x4_radix1"])
-def test_full_size_sampled(hf, cfg, sample, radix):
+# full-size fields under the default plan, under the alternative radix lists, and with both
+# axis-0 exchanges flipped and half-width filter tiles (the plans the autotuner picks from)
+FULL_PLANS = {"default": [0] * 11, "radix1": [0] * 8 + [1, 0, 0],
+              "xsplit": [0, 0, 1, 0, 0, 0, 0, 0, 0, 1, 1]}
+
+
+@pytest.mark.parametrize("cfg,sample,plan", [(W.C2, [0, 15], "default"), (W.C3, [0], "default"),
+                                             (W.C2, [7], "radix1"), (W.C3, [3], "radix1"),
+                                             (W.C2, [11], "xsplit"), (W.C3, [2], "xsplit")],
+                         ids=["c2_2048sq_x16", "c3_256cube_x4", "c2_2048sq_x16_radix1", "c3_256cube_x4_radix1",
+                              "c2_2048sq_x16_xsplit", "c3_256cube_x4_xsplit"])
+def test_full_size_sampled(hf, cfg, sample, plan):
     dims, bins, seeds = cfg["dims"], cfg["bins"], cfg["seeds"]
-    _say("full size", cfg["name"], "radix", radix)
-    hf.plan_set(dims, len(seeds), bins, [0] * 8 + [radix])
+    _say("full size", cfg["name"], "plan", plan)
+    hf.plan_set(dims, len(seeds), bins, FULL_PLANS[plan])
     bufs = hf.PipelineBuffers(dims, len(seeds), bins)
     try:
         hf.pipeline(bufs, cfg["filt"], seeds)
         torch.cuda.synchronize()
     finally:
-        hf.plan_set(dims, len(seeds), bins, [0] * 9)
+        hf.plan_set(dims, len(seeds), bins, [0] * 11)
     hf.check_degenerate(bufs.stats)
     N = int(np.prod(dims))
     for i in sample:

@@ -328,7 +328,7 @@ int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t
  * groups of 16 or of 4 neighbouring tiles to one XCD); last `radix`, the radix lists of the
  * column passes (y, filter, binning): 0 each length's default Stockham plan, 1 its alternative
  * order of radices where the length has one (256: 16.4.4 for 16.16; 512: 16.8.4 for 8.8.8; 1024:
- * 8.8.16 for 16.8.8; 2048: 16.8.16 for 16.16.8), same elements per thread; then bin_exchange
+ * 8.8.16 for 16.8.8; 2048: 16.16.8 for 16.8.16), same elements per thread; then bin_exchange
  * and filter_exchange, the exchange of the axis-0 binning and filter passes: complex values
  * through LDS, or split (real and imaginary parts in two rounds through half the LDS, so more
  * workgroups are resident, at two more barriers per exchange; axis-0 lengths of 192 and more);

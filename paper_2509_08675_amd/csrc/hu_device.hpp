@@ -197,7 +197,7 @@ HU_PLAN(512, 16, 8, 8, 8)
 HU_PLAN(768, 24, 3, 8, 8, 4)
 HU_PLAN(1024, 16, 16, 8, 8)
 HU_PLAN(1536, 24, 3, 8, 8, 8)
-HU_PLAN(2048, 16, 16, 16, 8)
+HU_PLAN(2048, 16, 16, 8, 16)
 #undef HU_PLAN
 
 template <int L>
@@ -215,7 +215,7 @@ struct Plan<L, 1> : Plan<L, 0> {};
 HU_ALT_PLAN(256, 16, 4, 4)
 HU_ALT_PLAN(512, 16, 8, 4)
 HU_ALT_PLAN(1024, 8, 8, 16)
-HU_ALT_PLAN(2048, 16, 8, 16)
+HU_ALT_PLAN(2048, 16, 16, 8)
 #undef HU_ALT_PLAN
 
 // the radix choice a kernel of length L runs under the requested one (0 where L has no alternative)

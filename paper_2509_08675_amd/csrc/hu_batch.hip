@@ -59,7 +59,7 @@ int ensure_streams() {
   return HU_OK;
 }
 
-TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0}}; }
+TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0}}; }
 
 int job_status(const hu_job& j, Geom* g) {
   int rc = make_geom(j.dims, g);
@@ -179,10 +179,12 @@ int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t
   for (const Class& c : cls) {
     const TunePlan p = get_plan(c.g, c.has_bins ? &c.bins : nullptr, (int)c.jobs.size());
     plans.push_back(p);
-    std::snprintf(buf, sizeof buf, "%d:%d,%d,%d:%d,%d:%zu:%d%d%d:%d%d%d%d%d|", c.g.nd, c.g.n[0], c.g.n[1], c.g.n[2],
+    std::snprintf(buf, sizeof buf, "%d:%d,%d,%d:%d,%d:%zu:%d%d%d:", c.g.nd, c.g.n[0], c.g.n[1], c.g.n[2],
                   c.has_bins ? c.bins.n_radial : 0, c.has_bins ? c.bins.n_angular : 0, c.jobs.size(), c.want_cont,
-                  c.want_pm1, c.any_gen, p.v[0], p.v[1], p.v[2], p.v[3], p.v[4]);
+                  c.want_pm1, c.any_gen);
     key += buf;
+    for (int k = 0; k < NPASS; ++k) key += (char)('0' + p.v[k]);   // every plan entry: a changed
+    key += '|';                                                     // plan captures a new graph
   }
 
   std::lock_guard<std::mutex> lk(g_bmu);
@@ -389,6 +391,7 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
       if (g.nd == 2 && (k == P_COLY || k == P_YGROUP)) continue;
       if (k == P_RADIX && !plan_has_alt(g.n[0]) && !(g.nd == 3 && plan_has_alt(g.n[1]))) continue;
       if ((k == P_BSPLIT || k == P_FSPLIT) && !split_length(g.n[0])) continue;
+      if (k == P_WHOLE && !whole_field_ok(g, nb)) continue;
       TunePlan cand = best;
       cand.v[k] ^= 1;
       double tb = 0.0, tc = 0.0;

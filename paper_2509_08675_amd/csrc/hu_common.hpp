@@ -73,6 +73,13 @@ struct ColTile {
 
 __host__ __device__ constexpr int pw_index(int e) { return e + (e >> 4) * 4; }
 
+// a value the whole wave holds, in scalar registers (the noise seed of a field)
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // Calls f(width, radix) with the tile-width choice V and the radix choice RV as integral
 // constants; a length without an alternative radix list instantiates only RV = 0.
 template <int L, class F>

@@ -272,6 +272,12 @@ static int make_stage_table(int L, int rv, float2** out) {
   }
 }
 
+bool whole_field_ok(const Geom& g, int nb) {
+  if (g.nd != 2) return false;
+  const size_t lds = small_lds_bytes(g.nx / 2, g.n[0], nb);
+  return lds > 0 && lds + 1024 <= LDS_BYTES;
+}
+
 bool plan_has_alt(int L) {
   switch (L) {
 #define X(LL) case LL: return Plan<LL, 1>::alt;
@@ -838,6 +844,43 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   }
   const bool want_cont = batch_mode ? (r.want_cont && r.bins) : (o.cont_sum != nullptr);
   const bool want_pm1 = r.thresh && (batch_mode ? (r.want_pm1_spec && r.bins) : (o.pm1_sum != nullptr));
+
+  // small 2D grids under plan entry whole_field: the whole path in one workgroup per field, the
+  // half spectrum resident in LDS (the workspace is not touched)
+  if (r.plan.v[P_WHOLE] && whole_field_ok(g, nb)) {
+    const float2* tw_c;
+    HU_TRY(get_tw(g.n[0], &tw_c, 0));
+    SmallArgs sa{};
+    sa.io = r.io;
+    if (!batch_mode) {
+      for (int i = 0; i < B; ++i) sa.seeds[i] = r.seeds[i];
+      sa.filt = filt_dev(r.filt, g);
+      sa.sigma_f = r.filt.sigma_f;
+      sa.near_abs = r.near_abs;
+      sa.field = o.field;
+      sa.pm1 = r.thresh ? o.pm1 : nullptr;
+      sa.stats = o.stats;
+      sa.counts = r.thresh ? o.counts : nullptr;
+      sa.cont_sum = o.cont_sum;
+      sa.cont_cnt = o.cont_cnt;
+      sa.pm1_sum = o.pm1_sum;
+      sa.pm1_cnt = o.pm1_cnt;
+    }
+    sa.thresh = r.thresh ? 1 : 0;
+    sa.want_cont = want_cont ? 1 : 0;
+    sa.want_pm1 = want_pm1 ? 1 : 0;
+    sa.any_gen = (batch_mode ? r.any_gen : filt_general(r.filt, g)) ? 1 : 0;
+    sa.nb = nb;
+    sa.N = g.N;
+    sa.gm = axis0(g);
+    sa.table = geo.table;
+    sa.counts_tab = geo.counts;
+    sa.tw_row = tw_row;
+    sa.tw2 = tw2_row;
+    sa.tw_col = tw_c;
+    HU_HIP(timed("field_lds", st, [&] { return launch_field_lds(Lrow, g.n[0], sa, B, st); }));
+    return HU_OK;
+  }
 
   float2* spec = reinterpret_cast<float2*>(r.work + r.lay.spec);
   double* partials = reinterpret_cast<double*>(r.work + r.lay.partials);

@@ -42,9 +42,12 @@ struct Geom {
 // 10, P_BSPLIT and P_FSPLIT: the exchange of the binning and of the filter pass along axis 0,
 // complex or split (real and imaginary parts in two rounds: half the LDS, more resident
 // workgroups, two more barriers per exchange; axis-0 lengths >= 192).  Default: the binning pass
-// split in 2D and complex in 3D, the filter pass complex; 1 the other one.
+// split in 2D and complex in 3D, the filter pass complex; 1 the other one.  Entry 11, P_WHOLE:
+// for 2D grids whose half spectrum fits in one workgroup's LDS (n_x and n0 up to 128), 1 runs the
+// whole path as one kernel with one workgroup per field (whole_field_ok), 0 the pass sequence.
 enum { P_R2C = 0, P_COLY = 1, P_FILTER = 2, P_C2R = 3, P_BIN = 4, P_BINSCHED = 5, P_FIELDS = 6, P_YGROUP = 7,
-       P_RADIX = 8, P_BSPLIT = 9, P_FSPLIT = 10, NPASS = 11 };
+       P_RADIX = 8, P_BSPLIT = 9, P_FSPLIT = 10, P_WHOLE = 11, NPASS = 12 };
+constexpr size_t LDS_BYTES = 160 * 1024;     // per workgroup on gfx950
 struct TunePlan {
   int v[NPASS];
 };
@@ -84,6 +87,9 @@ int make_bindev(const Geom& g, const hu_bins& b, BinDev* bd);
 // alternative)
 int get_tw(int L, const float2** tw, int radix = 0);
 bool plan_has_alt(int L);
+// the grid (2D, n_x / 2 in 8 .. 64 and n0 in 16 .. 128, powers of two) and nb bins fit the
+// whole-field kernel
+bool whole_field_ok(const Geom& g, int nb);
 int get_tw2(int L, const float2** tw2);
 int get_bingeo(const Geom& g, const hu_bins& bins, BinGeo* out);
 // the tile-local bin tables of the axis-0 passes for tiles of C columns (device copy)

@@ -89,6 +89,34 @@ struct Axis0Geom {
   long long dfac_0, dfac_y, dfac_x;   // D / n_i, D = lcm of the dims
 };
 
+// The whole path of small 2D fields, one workgroup per field (hu_small.hip).  Uniform mode
+// (io null): seeds, filter and outputs at base + field * stride; batch mode: io[b].
+struct SmallArgs {
+  uint64_t seeds[MAX_CHUNK];
+  const FieldIO* io;
+  FiltDev filt;
+  double sigma_f;
+  float near_abs;
+  int thresh, want_cont, want_pm1, any_gen;
+  int nb;                  // bins + 1 (0: no spectra)
+  long long N;
+  Axis0Geom gm;
+  float* field;
+  int8_t* pm1;
+  double* stats;
+  uint64_t* counts;
+  double* cont_sum;
+  uint64_t* cont_cnt;
+  double* pm1_sum;
+  uint64_t* pm1_cnt;
+  const uint16_t* table;                   // [n_x/2 + 1][n0] bin of each mode
+  const unsigned long long* counts_tab;    // [nb] modes per bin
+  const float2* tw_row;                    // stage table of n_x / 2
+  const float2* tw2;                       // exp(-2 pi i k / n_x), k < n_x / 2
+  const float2* tw_col;                    // stage table of n0
+};
+
+
 // Tile-local bin tables of the axis-0 passes for one tile width.  The modes of a tile touch few of
 // the bins; each tile has one partial sum per distinct bin (in ascending bin order), stored grouped
 // by bin so that a bin's partials are contiguous, and the partials of a bin are combined in a
@@ -308,6 +336,10 @@ hipError_t launch_cols_bin(int L, int variant, const BinArgs& a, hipStream_t st,
 hipError_t launch_rows_c2r(int L, bool thresh, int variant, const RowsZArgs& a, int batch, hipStream_t st);
 int row_tiles(int L, int variant, long long nrows);
 hipError_t launch_spec_final(const SpecFinalArgs& a, int batch, hipStream_t st);
+// the whole-field kernel for row half-length LR (8 .. 64) and n0 (16 .. 128), powers of two;
+// small_lds_bytes: its LDS for nb bins (0 for an unsupported shape)
+size_t small_lds_bytes(int LR, int N0, int nb);
+hipError_t launch_field_lds(int LR, int N0, const SmallArgs& a, int batch, hipStream_t st);
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st);
 // `group` tiles in a row per XCD (see ColSched)
 ColSched col_sched(int L, int variant, long long ncol, int batch, int group = 1);

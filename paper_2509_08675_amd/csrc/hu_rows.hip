@@ -262,12 +262,6 @@ __device__ __forceinline__ void tile_geom(long long row0, long long nrows, unsig
   }
 }
 
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
 // grid (ceil(nrows / C), B), block C * P; thread (c, p) = (tid / P, tid % P) transforms row c.
 template <int L, int SRC, bool TILED, int V>
 __global__ void __launch_bounds__((RowTile<L, V>::T)) k_rows_r2c(RowsArgs a) {

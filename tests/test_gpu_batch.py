@@ -98,6 +98,35 @@ def job_host(hf, bb, i):
     return h
 
 
+def test_whole_field_kernel_in_a_batch_equals_single_calls(hf):
+    """The small 2D classes of a mixed batch under plan entry whole_field (one kernel per class,
+    per-field parameters from the batch table) give the bits of single calls under the same entry,
+    and agree with the oracle.  The same batch structure ran under the default plans in the tests
+    above: the cached graph must follow the changed plan (a new capture)."""
+    jobs = mixed_jobs(seed0=700)
+    keys = set()
+    for j in jobs:
+        if len(j["dims"]) == 2 and max(j["dims"]) <= 128:
+            keys.add((tuple(j["dims"]), j["bins"]))            # the batch classes
+            keys.add((tuple(j["dims"]), j["bins"] or (4, 1)))  # the single calls
+    def plans(v):
+        for dims, bins in keys:
+            for n in (1, 2, 8):                                 # every batch-size bucket used here
+                hf.plan_set(dims, n, bins, v)
+    plans([0] * 11 + [1])
+    try:
+        bb = hf.BatchBuffers(jobs)
+        st = hf.pipeline_batch(bb)
+        torch.cuda.synchronize()
+        assert st == [0] * len(jobs)
+        _check_against_singles(hf, bb, jobs)
+        for i in (0, 2):
+            j = jobs[i]
+            P.compare_field("whole_batch_job%d" % i, j["dims"], j["filt"], j["seed"], j["bins"], job_host(hf, bb, i))
+    finally:
+        plans([0] * 12)
+
+
 def test_full_uneven_batch_sampled(hf):
     jobs = W.c4_jobs()
     _say("uneven batch of", len(jobs))
@@ -153,10 +182,10 @@ def test_half_width_variants_match(hf, dims, bins):
     _say("variants", dims)
     filt = W.filt(p=3, semi=(2, 1, 1.5), rot=0.4, alpha=4, k0=0.2, width=0.05)
     seeds = [11, 12]
-    hf.plan_set(dims, 2, bins, [0] * 11)
+    hf.plan_set(dims, 2, bins, [0] * 12)
     b0 = hf.PipelineBuffers(dims, 2, bins)
     hf.pipeline(b0, filt, seeds)
-    switched = [1] * 8 + [0, 1, 1]                      # every tile width, schedule and exchange
+    switched = [1] * 8 + [0, 1, 1, 0]                   # every tile width, schedule and exchange
     hf.plan_set(dims, 2, bins, switched)
     b1 = hf.PipelineBuffers(dims, 2, bins)
     hf.pipeline(b1, filt, seeds)
@@ -167,7 +196,7 @@ def test_half_width_variants_match(hf, dims, bins):
     ref = O.pipeline(dims, O.FilterParams(**filt), seeds[1], *bins)
     f = b1.field[1].double().cpu().numpy()
     assert np.max(np.abs(f - ref["f"])) <= 1e-5 * math.sqrt(float(np.mean(ref["f"] ** 2)))
-    hf.plan_set(dims, 2, bins, [0] * 11)
+    hf.plan_set(dims, 2, bins, [0] * 12)
 
 
 def test_autotune_writes_plan(hf, tmp_path):
@@ -175,7 +204,7 @@ def test_autotune_writes_plan(hf, tmp_path):
     path = str(tmp_path / "tune.json")
     _say("autotune", dims)
     plan, ms = hf.autotune(dims, 4, bins, path)
-    assert set(plan.values()) <= {0, 1} and len(plan) == 11
+    assert set(plan.values()) <= {0, 1} and len(plan) == 12
     assert ms["default_ms"] > 0 and 0 < ms["tuned_ms"] <= ms["default_ms"]
     assert ms["flipped_ms"]["cols_filter"] > 0 and ms["flipped_ms"]["y_group"] == 0   # 2D: no y passes
     assert ms["flipped_ms"]["radix"] > 0                # 256 has an alternative radix list
@@ -184,4 +213,4 @@ def test_autotune_writes_plan(hf, tmp_path):
     keys = [k for k in d["plans"] if "256x256x1" in k]
     assert keys and d["plans"][keys[0]] == [plan[n] for n in hf.PASS_NAMES]
     assert hf.plan_query(dims, 4, bins) == plan
-    hf.plan_set(dims, 4, bins, [0] * 11)                # later tests run the default plan
+    hf.plan_set(dims, 4, bins, [0] * 12)                # later tests run the default plan

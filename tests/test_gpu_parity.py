@@ -166,12 +166,62 @@ RADIX_CASES = [("radix_2048x64", (2048, 64), (24, 8)), ("radix_1024x96", (1024, 
 @pytest.mark.parametrize("name,dims,bins", RADIX_CASES, ids=[c[0] for c in RADIX_CASES])
 def test_radix_alternatives_match_oracle(hf, name, dims, bins):
     filt = _filt(p=3.0, semi=(2.0, 1.0, 1.5), rot=0.4, alpha=4.0, k0=0.2, width=0.05)
-    hf.plan_set(dims, 2, bins, [0] * 8 + [1, 0, 0])
+    hf.plan_set(dims, 2, bins, [0] * 8 + [1, 0, 0, 0])
     try:
         assert hf.plan_query(dims, 2, bins)["radix"] == 1
         _compare_pipeline(hf, name, dims, filt, bins, [71, 72])
     finally:
-        hf.plan_set(dims, 2, bins, [0] * 11)
+        hf.plan_set(dims, 2, bins, [0] * 12)
+
+
+# The whole-field kernel (plan entry whole_field): shape classes of its row and column
+# transforms, radial and angular bins, and a filter evaluated in FP64 (alpha = 20); the profiler
+# shows that the kernel ran in place of the pass sequence.
+WHOLE_CASES = [("whole_64x64", (64, 64), _filt(p=3.0, semi=(2.0, 1.0), rot=0.4, alpha=4.0, k0=0.2, width=0.05), (32, 1)),
+               ("whole_128x128", (128, 128), W.C1["filt"], (64, 1)),
+               ("whole_16x16", (16, 16), _filt(p=2.0, semi=(1.0, 1.0), alpha=2.0, k0=0.4, width=0.2), (8, 1)),
+               ("whole_32x128_angular", (32, 128), _filt(p=4.0, semi=(3.0, 1.0), rot=0.5, alpha=4.0, k0=0.2, width=0.05), (16, 6)),
+               ("whole_128x16_angular", (128, 16), _filt(p=2.5, semi=(1.0, 2.0), rot=0.2, alpha=2.0, k0=0.3, width=0.1), (24, 4)),
+               ("whole_64x128_angular", (64, 128), _filt(p=3.0, semi=(2.0, 1.0), rot=0.4, alpha=4.0, k0=0.2, width=0.05), (48, 8)),
+               ("whole_128x128_paper_a20", (128, 128), W.paper_preset(128, 100.0 * 128 / 1024, alpha=20.0, p=0.5), (64, 1))]
+
+
+@pytest.mark.parametrize("name,dims,filt,bins", WHOLE_CASES, ids=[c[0] for c in WHOLE_CASES])
+def test_whole_field_kernel_matches_oracle(hf, name, dims, filt, bins):
+    hf.plan_set(dims, 2, bins, [0] * 11 + [1])
+    try:
+        hf.profile_enable(True)
+        _compare_pipeline(hf, name, dims, filt, bins, [81, 82])
+        prof = hf.profile_read()
+        hf.profile_enable(False)
+        assert "field_lds" in prof and "cols_filter" not in prof, sorted(prof)
+    finally:
+        hf.profile_enable(False)
+        hf.plan_set(dims, 2, bins, [0] * 12)
+
+
+def test_whole_field_kernel_generator_and_repeat(hf):
+    """hu_gen_field through the whole-field kernel (no sign map, no +-1 spectrum) against the
+    oracle's field, statistics and continuous spectrum; repeated calls give the same bits."""
+    dims, bins, seeds = (128, 64), (32, 4), [91, 92, 93]
+    filt = _filt(p=3.0, semi=(2.0, 1.0), rot=0.3, alpha=4.0, k0=0.25, width=0.05)
+    hf.plan_set(dims, 3, bins, [0] * 11 + [1])
+    try:
+        outs = []
+        for _ in range(2):
+            o = hf.gen_field(dims, filt, seeds, bins)
+            torch.cuda.synchronize()
+            outs.append(o)
+        for k in ("field", "stats", "cont_sum", "cont_cnt"):
+            assert torch.equal(outs[0][k], outs[1][k]), k
+        o = outs[0]
+        for i, s in enumerate(seeds):
+            got = dict(field=o["field"][i].cpu().numpy(), stats=o["stats"][i].cpu().numpy(),
+                       cont_sum=o["cont_sum"][i].cpu().numpy(), cont_cnt=hf.u64_view(o["cont_cnt"][i]))
+            ref = O.gen_field(dims, O.FilterParams(**filt), s)
+            P.compare_field("whole_gen_128x64", dims, filt, s, bins, got, ref=ref)
+    finally:
+        hf.plan_set(dims, 3, bins, [0] * 12)
 
 
 def test_gen_field_matches_pipeline_field(hf):
@@ -252,8 +302,8 @@ def test_power_spectrum_standalone(hf, dims, bins, kind):
 # ---------------------------------------------------------------------------------------------
 # full-size fields under the default plan, under the alternative radix lists, and with both
 # axis-0 exchanges flipped and half-width filter tiles (the plans the autotuner picks from)
-FULL_PLANS = {"default": [0] * 11, "radix1": [0] * 8 + [1, 0, 0],
-              "xsplit": [0, 0, 1, 0, 0, 0, 0, 0, 0, 1, 1]}
+FULL_PLANS = {"default": [0] * 12, "radix1": [0] * 8 + [1, 0, 0, 0],
+              "xsplit": [0, 0, 1, 0, 0, 0, 0, 0, 0, 1, 1, 0]}
 
 
 @pytest.mark.parametrize("cfg,sample,plan", [(W.C2, [0, 15], "default"), (W.C3, [0], "default"),
@@ -270,7 +320,7 @@ def test_full_size_sampled(hf, cfg, sample, plan):
         hf.pipeline(bufs, cfg["filt"], seeds)
         torch.cuda.synchronize()
     finally:
-        hf.plan_set(dims, len(seeds), bins, [0] * 11)
+        hf.plan_set(dims, len(seeds), bins, [0] * 12)
     hf.check_degenerate(bufs.stats)
     N = int(np.prod(dims))
     for i in sample:

@@ -389,6 +389,31 @@ def time_two_point(hf, torch, cfg, steps, phi=0.35):
                 bytes_min=total, roofline_frac=round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), kernels=kern)
 
 
+def time_small_fields(hf, torch, steps):
+    """Small 2D grids through the pass sequence and through the whole-field kernel (plan entry
+    whole_field, the half spectrum kept in one workgroup's LDS): the single 128^2 field of the
+    parity configuration, and batches of 256 fields of 128^2 and of 64^2.  Compulsory bytes: the
+    outputs, 5N per field."""
+    from paper_2509_08675_amd.workloads import C1
+    out = {}
+    for name, dims, B in (("2d_128x128_x1", (128, 128), 1), ("2d_128x128_x256", (128, 128), 256),
+                          ("2d_64x64_x256", (64, 64), 256)):
+        cfg = dict(C1, name=name, dims=dims, seeds=[1 + i for i in range(B)])
+        rec = dict(fields=B)
+        for label, whole in (("pass_sequence", 0), ("whole_field", 1)):
+            hf.plan_set(dims, B, cfg["bins"], [0] * (len(hf.PASS_NAMES) - 1) + [whole])
+            el, prof = time_pipeline(hf, torch, cfg, steps, 3)
+            ms = el / steps * 1e3
+            rec[label] = dict(ms_per_call=round(ms, 4), value=round(B * math.prod(dims) / (ms * 1e-3), 1),
+                              kernels={k: round(v[1] / v[0], 5) for k, v in prof.items()})
+        hf.plan_set(dims, B, cfg["bins"], [0] * len(hf.PASS_NAMES))
+        rec["bytes_min"] = B * field_bytes_min(dims)
+        best = min(rec["pass_sequence"]["ms_per_call"], rec["whole_field"]["ms_per_call"])
+        rec["roofline_frac_best"] = round(rec["bytes_min"] / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        out[name] = rec
+    return out
+
+
 def flops_obj(cfg, ms):
     """Transform FLOPs of one step: three real transforms per field (the noise's forward, the
     inverse to the field, the +-1 map's forward), counted as 5 N log2 N each (the convention of the
@@ -902,6 +927,7 @@ def main():
         line["also"]["level_cut_and_two_point_2048sq_x16"] = time_two_point(hf, torch, C2, max(args.steps // 5, 5))
         line["also"]["level_cut_and_two_point_256cube_x4"] = time_two_point(hf, torch, C3, max(args.steps // 5, 5))
         line["also"]["mask_variants_2048sq_x16"] = time_mask_variants(hf, torch, C2, max(args.steps // 5, 5))
+        line["also"]["small_2d_fields"] = time_small_fields(hf, torch, max(args.steps // 5, 5))
     line["parity"] = parity_c1(hf, torch)
     line["paper_context"] = paper_context(hf, torch)
     if not args.no_cpu_baseline:

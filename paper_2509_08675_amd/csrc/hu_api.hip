@@ -92,10 +92,12 @@ int hu::run_generator(hu_dims dims, int32_t batch, const hu_filter* filt, const 
   const int nb = bins ? bins->n_radial * bins->n_angular + 1 : 0;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   HU_TRY(prepare_tables(g, bins, st));
-  for (int f0 = 0; f0 < batch; f0 += MAX_CHUNK) {
+  // the whole-field kernel takes more fields per launch (it uses no workspace)
+  const int step = plan.v[P_WHOLE] && whole_field_ok(g, nb) ? MAX_WHOLE_CHUNK : MAX_CHUNK;
+  for (int f0 = 0; f0 < batch; f0 += step) {
     ClassRun r{};
     r.g = g;
-    r.B = batch - f0 < MAX_CHUNK ? batch - f0 : MAX_CHUNK;
+    r.B = batch - f0 < step ? batch - f0 : step;
     r.plan = plan;
     r.bins = bins;
     r.thresh = thresh;

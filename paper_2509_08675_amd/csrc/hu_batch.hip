@@ -323,10 +323,11 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
   // the summed mean kernel time of the whole pass sequence under a plan (2 untimed runs, 5 timed)
   auto time_plan = [&](const TunePlan& plan) -> double {
     auto run = [&]() {
-      for (int f0 = 0; f0 < B && rc == HU_OK; f0 += MAX_CHUNK) {
+      const int step = plan.v[P_WHOLE] && whole_field_ok(g, nb) ? MAX_WHOLE_CHUNK : MAX_CHUNK;
+      for (int f0 = 0; f0 < B && rc == HU_OK; f0 += step) {
         ClassRun r{};
         r.g = g;
-        r.B = B - f0 < MAX_CHUNK ? B - f0 : MAX_CHUNK;
+        r.B = B - f0 < step ? B - f0 : step;
         r.plan = plan;
         r.bins = bins;
         r.thresh = true;

@@ -848,6 +848,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   // small 2D grids under plan entry whole_field: the whole path in one workgroup per field, the
   // half spectrum resident in LDS (the workspace is not touched)
   if (r.plan.v[P_WHOLE] && whole_field_ok(g, nb)) {
+    if (!batch_mode && B > MAX_WHOLE_CHUNK) return HU_ERR_ARG;
     const float2* tw_c;
     HU_TRY(get_tw(g.n[0], &tw_c, 0));
     SmallArgs sa{};
@@ -882,6 +883,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     return HU_OK;
   }
 
+  if (!batch_mode && B > MAX_CHUNK) return HU_ERR_ARG;
   float2* spec = reinterpret_cast<float2*>(r.work + r.lay.spec);
   double* partials = reinterpret_cast<double*>(r.work + r.lay.partials);
   double* fstats = reinterpret_cast<double*>(r.work + r.lay.fstats);

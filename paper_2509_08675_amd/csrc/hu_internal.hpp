@@ -16,6 +16,9 @@ constexpr bool split_length(int L) { return L >= 192; }
 
 enum { SRC_NOISE = 0, SRC_F32 = 1, SRC_I8 = 2 };
 constexpr int MAX_CHUNK = 64;   // fields per launch when seeds travel in the kernel arguments
+// fields per launch of the whole-field kernel, which needs no workspace: enough to give every CU
+// a field (its arguments stay under the 4 KB kernel-argument limit)
+constexpr int MAX_WHOLE_CHUNK = 256;
 constexpr int NVARIANT = 2;     // tile-width variants per kernel: 0 = default, 1 = half width
 
 // Per-field parameters and outputs of a heterogeneous batch, in device memory.  When a kernel's
@@ -92,7 +95,7 @@ struct Axis0Geom {
 // The whole path of small 2D fields, one workgroup per field (hu_small.hip).  Uniform mode
 // (io null): seeds, filter and outputs at base + field * stride; batch mode: io[b].
 struct SmallArgs {
-  uint64_t seeds[MAX_CHUNK];
+  uint64_t seeds[MAX_WHOLE_CHUNK];
   const FieldIO* io;
   FiltDev filt;
   double sigma_f;

@@ -111,7 +111,7 @@ __global__ void __launch_bounds__((SmallShape<LR, N0>::T)) k_field_lds(SmallArgs
       seed = io->seed;
     } else {
 #pragma unroll
-      for (int i = 0; i < MAX_CHUNK; ++i) seed = i == b ? a.seeds[i] : seed;
+      for (int i = 0; i < MAX_WHOLE_CHUNK; ++i) seed = i == b ? a.seeds[i] : seed;
     }
     seed = uniform_u64(seed);
     const uint64_t m0 = (uint64_t)r * (NX / 4);

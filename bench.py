@@ -401,7 +401,9 @@ def time_small_fields(hf, torch, steps):
         cfg = dict(C1, name=name, dims=dims, seeds=[1 + i for i in range(B)])
         rec = dict(fields=B)
         for label, whole in (("pass_sequence", 0), ("whole_field", 1)):
-            hf.plan_set(dims, B, cfg["bins"], [0] * (len(hf.PASS_NAMES) - 1) + [whole])
+            plan = [0] * len(hf.PASS_NAMES)
+            plan[hf.PASS_NAMES.index("whole_field")] = whole
+            hf.plan_set(dims, B, cfg["bins"], plan)
             el, prof = time_pipeline(hf, torch, cfg, steps, 3)
             ms = el / steps * 1e3
             rec[label] = dict(ms_per_call=round(ms, 4), value=round(B * math.prod(dims) / (ms * 1e-3), 1),

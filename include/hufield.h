@@ -318,7 +318,7 @@ int hu_workspace_size_batch(const hu_job* jobs, int32_t njobs, size_t* bytes);
 int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t* status, void* work,
                       size_t work_bytes, void* stream);
 
-/* Plan autotuner.  A plan has 12 entries, each 0 or 1: the tile width of the kernel families
+/* Plan autotuner.  A plan has 13 entries, each 0 or 1: the tile width of the kernel families
  * rows_r2c, cols_y, cols_filter, rows_c2r, cols_bin (0 the default, 1 half of it), then three
  * schedules (0 the default, 1 the other one): bin_schedule (the +-1 binning pass one tile of one
  * field per workgroup, or persistent with a work counter and the next tile's loads overlapping the
@@ -335,30 +335,33 @@ int hu_pipeline_batch(const hu_job* jobs, int32_t njobs, float near_tol, int32_t
  * default the binning pass split in 2D and complex in 3D, the filter pass complex, 1 the other
  * one; last whole_field (2D grids with n_x / 2 in 8 .. 64 and n0 in 16 .. 128, powers of two, whose
  * half spectrum and bins fit in one workgroup's LDS): 1 runs the whole path as one kernel, one
- * workgroup per field, the spectrum never leaving LDS (HBM traffic: the outputs only).
+ * workgroup per field, the spectrum never leaving LDS (HBM traffic: the outputs only); and plane
+ * (3D grids with n_x / 2 in {16, 24, 32, 48, 64} and n_y in {32, 48, 64, 96, 128}): 1 runs the x
+ * and y transforms of each z-plane in one kernel, so noise, the x rows and the forward y pass
+ * are one pass and the inverse y pass, the last row pass and the y pass of the +-1 field another.
  * hu_autotune searches
  * the plan of a shape class (grid, bins, batch size bucket) on a synthetic batch of `batch` fields
  * of `dims` with `bins`: after about 50 ms of warm-up runs it flips one entry at a time from the
  * default plan and keeps the change when the summed mean kernel time of the whole pass sequence,
  * timed alternately with the current plan, drops by more than 1 % (the y-pass entries only in 3D,
  * the radix entry only where a column length has an alternative, the exchange entries from
- * axis-0 length 192, whole_field where the grid fits),
+ * axis-0 length 192, whole_field and plane where the grid fits),
  * sweeping the entries a second time when the first sweep changed the plan.  The plan is kept in memory and,
  * if cache_path is non-NULL, all tuned plans are written as JSON there (read back at start-up from
- * $HUFIELD_TUNE_CACHE).  ms_out (host, optional) receives 14 values: the default plan's time and
+ * $HUFIELD_TUNE_CACHE).  ms_out (host, optional) receives 15 values: the default plan's time and
  * the tuned plan's (timed side by side after the search), and for each entry the time with it
  * flipped during the search (0 where not tried), in ms.  Allocates and frees its own device
  * buffers and synchronises.  The tile-width, schedule and exchange entries leave fields and sign
  * maps the same bit for bit (the spectra to FP64 rounding: the tile width changes how the bins' partials
- * are grouped); the radix and whole_field entries change the FP32 rounding (other transforms,
+ * are grouped); the radix, whole_field and plane entries change the FP32 rounding (other transforms,
  * another order of the sums), so fields under them agree with the others to FP32 rounding, not
  * bit for bit. */
 int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* cache_path, double* ms_out);
 
-/* The plan (12 entries, 0 or 1, order as above) that calls on this shape class use. */
+/* The plan (13 entries, 0 or 1, order as above) that calls on this shape class use. */
 int hu_plan_query(hu_dims dims, int32_t batch, const hu_bins* bins, int32_t* variants);
 
-/* Set the plan of a shape class by hand (host array of 12 entries, each 0 or 1). */
+/* Set the plan of a shape class by hand (host array of 13 entries, each 0 or 1). */
 int hu_plan_set(hu_dims dims, int32_t batch, const hu_bins* bins, const int32_t* variants);
 
 const char* hu_strerror(int code);

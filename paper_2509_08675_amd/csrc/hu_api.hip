@@ -25,7 +25,7 @@ hu_outputs offset_outputs(const hu_outputs& o, long long f0, long long N, int nb
   return r;
 }
 
-TunePlan widest_plan() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0}}; }   // most tiles: largest partials
+TunePlan widest_plan() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 0}}; }   // most tiles: largest partials
 
 // workspace of hu_spectrum_grad: the noise spectrum, the per-bin weights, the per-tile partials
 struct GradLayout {

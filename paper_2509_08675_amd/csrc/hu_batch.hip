@@ -59,7 +59,7 @@ int ensure_streams() {
   return HU_OK;
 }
 
-TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0}}; }
+TunePlan widest() { return TunePlan{{1, 1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 0}}; }
 
 int job_status(const hu_job& j, Geom* g) {
   int rc = make_geom(j.dims, g);
@@ -393,6 +393,7 @@ int hu_autotune(hu_dims dims, int32_t batch, const hu_bins* bins, const char* ca
       if (k == P_RADIX && !plan_has_alt(g.n[0]) && !(g.nd == 3 && plan_has_alt(g.n[1]))) continue;
       if ((k == P_BSPLIT || k == P_FSPLIT) && !split_length(g.n[0])) continue;
       if (k == P_WHOLE && !whole_field_ok(g, nb)) continue;
+      if (k == P_PLANE && !plane_ok(g)) continue;
       TunePlan cand = best;
       cand.v[k] ^= 1;
       double tb = 0.0, tc = 0.0;

@@ -272,6 +272,12 @@ static int make_stage_table(int L, int rv, float2** out) {
   }
 }
 
+bool plane_ok(const Geom& g) {
+  if (g.nd != 3) return false;
+  const size_t lds = plane_lds_bytes(g.nx / 2, g.n[1]);
+  return lds > 0 && lds + 1024 <= LDS_BYTES;
+}
+
 bool whole_field_ok(const Geom& g, int nb) {
   if (g.nd != 2) return false;
   const size_t lds = small_lds_bytes(g.nx / 2, g.n[0], nb);
@@ -388,9 +394,11 @@ int layout(const Geom& g, int batch, bool need_stats, const TunePlan& plan, cons
     L.fstats = off;
     off += up256((size_t)batch * 8 * sizeof(double));
     // per-tile counts of the last row pass, for either row-tile width
+    // (or per plane, for the plane kernels of 3D grids)
     const int rt0 = row_tiles(g.nx / 2, 0, g.nrows), rt1 = row_tiles(g.nx / 2, 1, g.nrows);
+    const int rtm = std::max(std::max(rt0, rt1), g.nd == 3 ? g.n[0] : 0);
     L.cpart = off;
-    off += up256((size_t)batch * (rt0 > rt1 ? rt0 : rt1) * 2 * sizeof(uint32_t));
+    off += up256((size_t)batch * rtm * 2 * sizeof(uint32_t));
   }
   if (bins) {
     // room for the partials of either tile width (the plan of a later call may differ)
@@ -884,6 +892,10 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   }
 
   if (!batch_mode && B > MAX_CHUNK) return HU_ERR_ARG;
+  // 3D grids under plan entry plane: the x and y transforms of a plane in one kernel
+  const bool planes = g.nd == 3 && r.plan.v[P_PLANE] && plane_ok(g);
+  const float2* tw_y0 = nullptr;
+  if (planes) HU_TRY(get_tw(g.n[1], &tw_y0, 0));
   float2* spec = reinterpret_cast<float2*>(r.work + r.lay.spec);
   double* partials = reinterpret_cast<double*>(r.work + r.lay.partials);
   double* fstats = reinterpret_cast<double*>(r.work + r.lay.fstats);
@@ -914,7 +926,12 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     if (o.pm1_cnt && r.thresh) ra.fill[fs++] = FillSpan{reinterpret_cast<uint32_t*>(o.pm1_cnt), cnt_src, 2 * nb};
     ra.fill_spans = fs;
   }
-  HU_HIP(timed("rows_r2c_noise", st, [&] { return launch_rows_r2c(Lrow, SRC_NOISE, r.plan.v[P_R2C], ra, B, st); }));
+  if (planes) {
+    ra.tw_y = tw_y0;
+    HU_HIP(timed("plane_fwd", st, [&] { return launch_plane_fwd(Lrow, g.n[1], ra, g.n[0], B, st); }));
+  } else {
+    HU_HIP(timed("rows_r2c_noise", st, [&] { return launch_rows_r2c(Lrow, SRC_NOISE, r.plan.v[P_R2C], ra, B, st); }));
+  }
 
   ColsArgs cy{};
   if (g.nd == 3) {
@@ -924,7 +941,8 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     cy.inner = g.nxh;
     cy.tw = tw_1;
     cy.sc = col_sched(g.n[1], r.plan.v[P_COLY], cy.ncol, B, r.plan.v[P_YGROUP] ? 4 : Y_PASS_GROUP);
-    HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st, rad); }));
+    if (!planes)
+      HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st, rad); }));
   }
   // the fields of a tile on consecutive ids of one XCD (2D default) or field-major (3D default)
   const bool fields_xcd = (g.nd == 2) != (r.plan.v[P_FIELDS] != 0);
@@ -957,7 +975,8 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   fz.io = r.io;
   HU_HIP(timed("finalize", st, [&] { return launch_finalize(fz, B, st); }));
 
-  if (g.nd == 3) HU_HIP(timed("cols_y_inv", st, [&] { return launch_cols(g.n[1], true, r.plan.v[P_COLY], cy, st, rad); }));
+  if (g.nd == 3 && !planes)
+    HU_HIP(timed("cols_y_inv", st, [&] { return launch_cols(g.n[1], true, r.plan.v[P_COLY], cy, st, rad); }));
 
   RowsZArgs za{};
   za.spec = spec;
@@ -977,11 +996,19 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
   const bool want_counts = r.thresh && (batch_mode || o.counts != nullptr);
   uint32_t* cpart = reinterpret_cast<uint32_t*>(r.work + r.lay.cpart);
   za.cpart = want_counts ? cpart : nullptr;
-  HU_HIP(timed(r.thresh ? "rows_c2r_thresh" : "rows_c2r", st,
-               [&] { return launch_rows_c2r(Lrow, r.thresh, r.plan.v[P_C2R], za, B, st); }));
+  if (planes) {
+    za.tw_y = tw_y0;
+    za.pm1_spec = want_pm1 ? 1 : 0;
+    HU_HIP(timed(r.thresh ? "plane_inv_thresh" : "plane_inv", st,
+                 [&] { return launch_plane_inv(Lrow, g.n[1], za, r.thresh, g.n[0], B, st); }));
+  } else {
+    HU_HIP(timed(r.thresh ? "rows_c2r_thresh" : "rows_c2r", st,
+                 [&] { return launch_rows_c2r(Lrow, r.thresh, r.plan.v[P_C2R], za, B, st); }));
+  }
 
   if (want_pm1) {
-    if (g.nd == 3) HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st, rad); }));
+    if (g.nd == 3 && !planes)
+      HU_HIP(timed("cols_y_fwd", st, [&] { return launch_cols(g.n[1], false, r.plan.v[P_COLY], cy, st, rad); }));
     BinArgs ba{};
     ba.ntiles = col_tiles(g.n[0], r.plan.v[P_BIN], g.Nh / g.n[0]);
     ba.batch = B;
@@ -1016,7 +1043,7 @@ int enqueue_class(const ClassRun& r, hipStream_t st) {
     }
     if (want_counts) {
       sf.cpart = cpart;
-      sf.ntc = row_tiles(Lrow, r.plan.v[P_C2R], g.nrows);
+      sf.ntc = planes ? g.n[0] : row_tiles(Lrow, r.plan.v[P_C2R], g.nrows);
       sf.counts = batch_mode ? nullptr : o.counts;
     }
     sf.io = r.io;

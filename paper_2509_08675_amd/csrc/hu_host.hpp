@@ -46,7 +46,10 @@ struct Geom {
 // for 2D grids whose half spectrum fits in one workgroup's LDS (n_x and n0 up to 128), 1 runs the
 // whole path as one kernel with one workgroup per field (whole_field_ok), 0 the pass sequence.
 enum { P_R2C = 0, P_COLY = 1, P_FILTER = 2, P_C2R = 3, P_BIN = 4, P_BINSCHED = 5, P_FIELDS = 6, P_YGROUP = 7,
-       P_RADIX = 8, P_BSPLIT = 9, P_FSPLIT = 10, P_WHOLE = 11, NPASS = 12 };
+       P_RADIX = 8, P_BSPLIT = 9, P_FSPLIT = 10, P_WHOLE = 11, P_PLANE = 12, NPASS = 13 };
+// Entry 12, P_PLANE: for 3D grids whose xy-plane fits in one workgroup's LDS, 1 runs the x and y
+// transforms of a plane in one kernel (plane_ok): noise, R2C rows and the forward y pass in one,
+// the inverse y pass, the last row pass and the y pass of the +-1 field in another.
 constexpr size_t LDS_BYTES = 160 * 1024;     // per workgroup on gfx950
 struct TunePlan {
   int v[NPASS];
@@ -90,6 +93,8 @@ bool plan_has_alt(int L);
 // the grid (2D, n_x / 2 in 8 .. 64 and n0 in 16 .. 128, powers of two) and nb bins fit the
 // whole-field kernel
 bool whole_field_ok(const Geom& g, int nb);
+// the 3D grid's plane fits the plane kernels
+bool plane_ok(const Geom& g);
 int get_tw2(int L, const float2** tw2);
 int get_bingeo(const Geom& g, const hu_bins& bins, BinGeo* out);
 // the tile-local bin tables of the axis-0 passes for tiles of C columns (device copy)

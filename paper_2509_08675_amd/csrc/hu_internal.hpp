@@ -70,6 +70,7 @@ struct RowsArgs {
   int fill_spans;
   unsigned* zero;          // words cleared by block (0, 0) before the later passes read them
   int nzero;               // (the work counter of the persistent binning pass)
+  const float2* tw_y;      // plane kernels (3D): stage table of n_y
 };
 
 struct ColsArgs {
@@ -214,6 +215,8 @@ struct RowsZArgs {
   uint32_t* cpart;         // [B][row tiles][2]: n_pos, n_near of each tile (THRESH), or null
   float near_tol;          // absolute
   const FieldIO* io;       // per-field outputs (batch path) or null
+  const float2* tw_y;      // plane kernels (3D): stage table of n_y
+  int pm1_spec;            // plane kernels: transform the +-1 plane for its spectrum
 };
 
 struct ThreshArgs {
@@ -342,6 +345,11 @@ hipError_t launch_spec_final(const SpecFinalArgs& a, int batch, hipStream_t st);
 // the whole-field kernel for row half-length LR (8 .. 64) and n0 (16 .. 128), powers of two;
 // small_lds_bytes: its LDS for nb bins (0 for an unsupported shape)
 size_t small_lds_bytes(int LR, int N0, int nb);
+// the plane kernels of 3D grids (hu_plane.hip) for row half-length LR and n_y = NY; their LDS (0:
+// no instantiation for the shape); grid (n0 planes, batch)
+size_t plane_lds_bytes(int LR, int NY);
+hipError_t launch_plane_fwd(int LR, int NY, const RowsArgs& a, int n0, int batch, hipStream_t st);
+hipError_t launch_plane_inv(int LR, int NY, const RowsZArgs& a, bool thresh, int n0, int batch, hipStream_t st);
 hipError_t launch_field_lds(int LR, int N0, const SmallArgs& a, int batch, hipStream_t st);
 hipError_t launch_threshold(const ThreshArgs& a, int batch, hipStream_t st);
 // `group` tiles in a row per XCD (see ColSched)

@@ -457,7 +457,7 @@ def profile_read(cap=64):
 # heterogeneous batches and the autotuner
 # ---------------------------------------------------------------------------------------------
 PASS_NAMES = ("rows_r2c", "cols_y", "cols_filter", "rows_c2r", "cols_bin", "bin_schedule", "field_placement",
-              "y_group", "radix", "bin_exchange", "filter_exchange", "whole_field")
+              "y_group", "radix", "bin_exchange", "filter_exchange", "whole_field", "plane")
 
 
 class BatchBuffers:

@@ -113,7 +113,7 @@ def test_whole_field_kernel_in_a_batch_equals_single_calls(hf):
         for dims, bins in keys:
             for n in (1, 2, 8):                                 # every batch-size bucket used here
                 hf.plan_set(dims, n, bins, v)
-    plans([0] * 11 + [1])
+    plans([0] * 11 + [1, 0])
     try:
         bb = hf.BatchBuffers(jobs)
         st = hf.pipeline_batch(bb)
@@ -124,7 +124,38 @@ def test_whole_field_kernel_in_a_batch_equals_single_calls(hf):
             j = jobs[i]
             P.compare_field("whole_batch_job%d" % i, j["dims"], j["filt"], j["seed"], j["bins"], job_host(hf, bb, i))
     finally:
-        plans([0] * 12)
+        plans([0] * 13)
+
+
+def test_plane_kernels_in_a_batch_equal_single_calls(hf):
+    """3D classes under plan entry plane (per-field parameters from the batch table) give the bits
+    of single calls under the same entry, and agree with the oracle."""
+    rng = np.random.default_rng(11)
+    shapes = [((32, 64, 64), (16, 1)), ((32, 64, 64), (16, 1)), ((48, 32, 96), (12, 1)), ((16, 48, 32), (12, 1))]
+    jobs = []
+    for i, (dims, bins) in enumerate(shapes):
+        k0 = float(rng.uniform(0.15, 0.35))
+        f = W.filt(p=float(rng.uniform(1.5, 8)), semi=(float(rng.uniform(1, 3)), 1.0, 1.5),
+                   rot=float(rng.uniform(0, math.pi)), alpha=float(rng.choice([2, 4])), k0=k0, width=0.5 * k0)
+        jobs.append(dict(dims=dims, filt=f, seed=900 + i, bins=bins))
+    on = [0] * 12 + [1]
+    keys = {(tuple(j["dims"]), j["bins"]) for j in jobs}
+    def plans(v):
+        for dims, bins in keys:
+            for n in (1, 2):
+                hf.plan_set(dims, n, bins, v)
+    plans(on)
+    try:
+        bb = hf.BatchBuffers(jobs)
+        st = hf.pipeline_batch(bb)
+        torch.cuda.synchronize()
+        assert st == [0] * len(jobs)
+        _check_against_singles(hf, bb, jobs)
+        for i in (0, 2, 3):
+            j = jobs[i]
+            P.compare_field("plane_batch_job%d" % i, j["dims"], j["filt"], j["seed"], j["bins"], job_host(hf, bb, i))
+    finally:
+        plans([0] * 13)
 
 
 def test_full_uneven_batch_sampled(hf):
@@ -182,10 +213,10 @@ def test_half_width_variants_match(hf, dims, bins):
     _say("variants", dims)
     filt = W.filt(p=3, semi=(2, 1, 1.5), rot=0.4, alpha=4, k0=0.2, width=0.05)
     seeds = [11, 12]
-    hf.plan_set(dims, 2, bins, [0] * 12)
+    hf.plan_set(dims, 2, bins, [0] * 13)
     b0 = hf.PipelineBuffers(dims, 2, bins)
     hf.pipeline(b0, filt, seeds)
-    switched = [1] * 8 + [0, 1, 1, 0]                   # every tile width, schedule and exchange
+    switched = [1] * 8 + [0, 1, 1, 0, 0]                # every tile width, schedule and exchange
     hf.plan_set(dims, 2, bins, switched)
     b1 = hf.PipelineBuffers(dims, 2, bins)
     hf.pipeline(b1, filt, seeds)
@@ -196,7 +227,7 @@ def test_half_width_variants_match(hf, dims, bins):
     ref = O.pipeline(dims, O.FilterParams(**filt), seeds[1], *bins)
     f = b1.field[1].double().cpu().numpy()
     assert np.max(np.abs(f - ref["f"])) <= 1e-5 * math.sqrt(float(np.mean(ref["f"] ** 2)))
-    hf.plan_set(dims, 2, bins, [0] * 12)
+    hf.plan_set(dims, 2, bins, [0] * 13)
 
 
 def test_autotune_writes_plan(hf, tmp_path):
@@ -204,7 +235,7 @@ def test_autotune_writes_plan(hf, tmp_path):
     path = str(tmp_path / "tune.json")
     _say("autotune", dims)
     plan, ms = hf.autotune(dims, 4, bins, path)
-    assert set(plan.values()) <= {0, 1} and len(plan) == 12
+    assert set(plan.values()) <= {0, 1} and len(plan) == 13
     assert ms["default_ms"] > 0 and 0 < ms["tuned_ms"] <= ms["default_ms"]
     assert ms["flipped_ms"]["cols_filter"] > 0 and ms["flipped_ms"]["y_group"] == 0   # 2D: no y passes
     assert ms["flipped_ms"]["radix"] > 0                # 256 has an alternative radix list
@@ -213,4 +244,4 @@ def test_autotune_writes_plan(hf, tmp_path):
     keys = [k for k in d["plans"] if "256x256x1" in k]
     assert keys and d["plans"][keys[0]] == [plan[n] for n in hf.PASS_NAMES]
     assert hf.plan_query(dims, 4, bins) == plan
-    hf.plan_set(dims, 4, bins, [0] * 12)                # later tests run the default plan
+    hf.plan_set(dims, 4, bins, [0] * 13)                # later tests run the default plan

@@ -166,12 +166,12 @@ RADIX_CASES = [("radix_2048x64", (2048, 64), (24, 8)), ("radix_1024x96", (1024, 
 @pytest.mark.parametrize("name,dims,bins", RADIX_CASES, ids=[c[0] for c in RADIX_CASES])
 def test_radix_alternatives_match_oracle(hf, name, dims, bins):
     filt = _filt(p=3.0, semi=(2.0, 1.0, 1.5), rot=0.4, alpha=4.0, k0=0.2, width=0.05)
-    hf.plan_set(dims, 2, bins, [0] * 8 + [1, 0, 0, 0])
+    hf.plan_set(dims, 2, bins, [0] * 8 + [1, 0, 0, 0, 0])
     try:
         assert hf.plan_query(dims, 2, bins)["radix"] == 1
         _compare_pipeline(hf, name, dims, filt, bins, [71, 72])
     finally:
-        hf.plan_set(dims, 2, bins, [0] * 12)
+        hf.plan_set(dims, 2, bins, [0] * 13)
 
 
 # The whole-field kernel (plan entry whole_field): shape classes of its row and column
@@ -188,7 +188,7 @@ WHOLE_CASES = [("whole_64x64", (64, 64), _filt(p=3.0, semi=(2.0, 1.0), rot=0.4, 
 
 @pytest.mark.parametrize("name,dims,filt,bins", WHOLE_CASES, ids=[c[0] for c in WHOLE_CASES])
 def test_whole_field_kernel_matches_oracle(hf, name, dims, filt, bins):
-    hf.plan_set(dims, 2, bins, [0] * 11 + [1])
+    hf.plan_set(dims, 2, bins, [0] * 11 + [1, 0])
     try:
         hf.profile_enable(True)
         _compare_pipeline(hf, name, dims, filt, bins, [81, 82])
@@ -197,7 +197,7 @@ def test_whole_field_kernel_matches_oracle(hf, name, dims, filt, bins):
         assert "field_lds" in prof and "cols_filter" not in prof, sorted(prof)
     finally:
         hf.profile_enable(False)
-        hf.plan_set(dims, 2, bins, [0] * 12)
+        hf.plan_set(dims, 2, bins, [0] * 13)
 
 
 def test_whole_field_kernel_generator_and_repeat(hf):
@@ -205,7 +205,7 @@ def test_whole_field_kernel_generator_and_repeat(hf):
     oracle's field, statistics and continuous spectrum; repeated calls give the same bits."""
     dims, bins, seeds = (128, 64), (32, 4), [91, 92, 93]
     filt = _filt(p=3.0, semi=(2.0, 1.0), rot=0.3, alpha=4.0, k0=0.25, width=0.05)
-    hf.plan_set(dims, 3, bins, [0] * 11 + [1])
+    hf.plan_set(dims, 3, bins, [0] * 11 + [1, 0])
     try:
         outs = []
         for _ in range(2):
@@ -221,7 +221,58 @@ def test_whole_field_kernel_generator_and_repeat(hf):
             ref = O.gen_field(dims, O.FilterParams(**filt), s)
             P.compare_field("whole_gen_128x64", dims, filt, s, bins, got, ref=ref)
     finally:
-        hf.plan_set(dims, 3, bins, [0] * 12)
+        hf.plan_set(dims, 3, bins, [0] * 13)
+
+
+def _plan(**on):
+    v = [0] * 13
+    for k, x in on.items():
+        v[["rows_r2c", "cols_y", "cols_filter", "rows_c2r", "cols_bin", "bin_schedule", "field_placement", "y_group",
+           "radix", "bin_exchange", "filter_exchange", "whole_field", "plane"].index(k)] = x
+    return v
+
+
+# The plane kernels of 3D grids (plan entry plane): row and y lengths of every size class they
+# cover, and a filter evaluated in FP64; the profiler shows that they replaced the row and y passes.
+_F3 = _filt(p=3.0, semi=(2.0, 1.0, 1.5), rot=0.4, alpha=4.0, k0=0.2, width=0.05)
+PLANE_CASES = [("plane_64cube", (64, 64, 64), _F3, (32, 1)), ("plane_96cube", (96, 96, 96), _F3, (48, 1)),
+               ("plane_128cube", (128, 128, 128), _F3, (64, 1)), ("plane_32x48x32", (32, 48, 32), _F3, (16, 1)),
+               ("plane_24x128x128", (24, 128, 128), _F3, (40, 1)), ("plane_48x32x96", (48, 32, 96), _F3, (24, 1)),
+               ("plane_128cube_paper_a20", (128, 128, 128), W.paper_preset(128, 128 * 25.0 / 256, alpha=20.0, p=0.5), (64, 1))]
+
+
+@pytest.mark.parametrize("name,dims,filt,bins", PLANE_CASES, ids=[c[0] for c in PLANE_CASES])
+def test_plane_kernels_match_oracle(hf, name, dims, filt, bins):
+    hf.plan_set(dims, 2, bins, _plan(plane=1))
+    try:
+        hf.profile_enable(True)
+        _compare_pipeline(hf, name, dims, filt, bins, [61, 62])
+        prof = hf.profile_read()
+        hf.profile_enable(False)
+        assert "plane_fwd" in prof and "plane_inv_thresh" in prof, sorted(prof)
+        assert "cols_y_fwd" not in prof and "rows_r2c_noise" not in prof, sorted(prof)
+    finally:
+        hf.profile_enable(False)
+        hf.plan_set(dims, 2, bins, [0] * 13)
+
+
+def test_plane_kernels_generator_and_repeat(hf):
+    """hu_gen_field through the plane kernels (no sign map, no +-1 spectrum) against the oracle;
+    repeated calls give the same bits."""
+    dims, bins, seeds = (32, 64, 64), (24, 1), [71, 72]
+    hf.plan_set(dims, 2, bins, _plan(plane=1))
+    try:
+        outs = [hf.gen_field(dims, _F3, seeds, bins) for _ in range(2)]
+        torch.cuda.synchronize()
+        for k in ("field", "stats", "cont_sum", "cont_cnt"):
+            assert torch.equal(outs[0][k], outs[1][k]), k
+        o = outs[0]
+        for i, s in enumerate(seeds):
+            got = dict(field=o["field"][i].cpu().numpy(), stats=o["stats"][i].cpu().numpy(),
+                       cont_sum=o["cont_sum"][i].cpu().numpy(), cont_cnt=hf.u64_view(o["cont_cnt"][i]))
+            P.compare_field("plane_gen_32x64x64", dims, _F3, s, bins, got, ref=O.gen_field(dims, O.FilterParams(**_F3), s))
+    finally:
+        hf.plan_set(dims, 2, bins, [0] * 13)
 
 
 def test_gen_field_matches_pipeline_field(hf):
@@ -302,8 +353,8 @@ def test_power_spectrum_standalone(hf, dims, bins, kind):
 # ---------------------------------------------------------------------------------------------
 # full-size fields under the default plan, under the alternative radix lists, and with both
 # axis-0 exchanges flipped and half-width filter tiles (the plans the autotuner picks from)
-FULL_PLANS = {"default": [0] * 12, "radix1": [0] * 8 + [1, 0, 0, 0],
-              "xsplit": [0, 0, 1, 0, 0, 0, 0, 0, 0, 1, 1, 0]}
+FULL_PLANS = {"default": [0] * 13, "radix1": [0] * 8 + [1, 0, 0, 0, 0],
+              "xsplit": [0, 0, 1, 0, 0, 0, 0, 0, 0, 1, 1, 0, 0]}
 
 
 @pytest.mark.parametrize("cfg,sample,plan", [(W.C2, [0, 15], "default"), (W.C3, [0], "default"),
@@ -320,7 +371,7 @@ def test_full_size_sampled(hf, cfg, sample, plan):
         hf.pipeline(bufs, cfg["filt"], seeds)
         torch.cuda.synchronize()
     finally:
-        hf.plan_set(dims, len(seeds), bins, [0] * 12)
+        hf.plan_set(dims, len(seeds), bins, [0] * 13)
     hf.check_degenerate(bufs.stats)
     N = int(np.prod(dims))
     for i in sample:

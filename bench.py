@@ -99,7 +99,8 @@ def adjoint_bytes(dims):
 
 # the sources that define the pipeline's kernels and their launch shapes
 PIPELINE_SOURCES = ("hu_device.hpp", "hu_common.hpp", "hu_internal.hpp", "hu_host.hpp", "hu_rows.hip", "hu_cols.hip",
-                    "hu_filter.hip", "hu_bin.hip", "hu_host.hip", "hu_adjoint.hip", "hu_api.hip")
+                    "hu_filter.hip", "hu_bin.hip", "hu_host.hip", "hu_adjoint.hip", "hu_api.hip", "hu_small.hip",
+                    "hu_plane.hip")
 
 
 def field_bytes_min(dims):
@@ -638,6 +639,10 @@ def kernel_family(name):
         return "rows_c2r_thresh" if args[1] == "true" else "rows_c2r"
     if k == "k_cols":
         return "cols_y_inv" if args[1] == "true" else "cols_y_fwd"
+    if k == "k_plane_inv":
+        return "plane_inv_thresh" if args[2] == "true" else "plane_inv"
+    if k in ("k_field_lds", "k_plane_fwd"):
+        return k[2:]
     return {"k_cols_filter": "cols_filter", "k_cols_bin": "cols_bin", "k_cols_bin_tile": "cols_bin"}.get(k)
 
 
@@ -826,8 +831,12 @@ def summarize_c4_trace(td, replays=10):
             n, d = int(a[0]), int(a[1])
         elif k in ("cols", "cols_bin"):
             n, d = int(a[0]), 3
-        elif k == "cols_bin_tile":
+        elif k == "cols_bin_tile":                 # 2D by default (see the table's caption)
             n, d = int(a[0]), 2
+        elif k == "field_lds":                     # <n_x / 2, n0, GEN>: the C4 grids are square
+            n, d = int(a[1]), 2
+        elif k in ("plane_fwd", "plane_inv"):      # <n_x / 2, n_y, ...>: cubes
+            n, d = int(a[1]), 3
         else:
             return None
         return "%dD %d^%d" % (d, n, d)
@@ -837,8 +846,11 @@ def summarize_c4_trace(td, replays=10):
             c = shape_class(r["Kernel_Name"])
             if c:
                 cls[c] = cls.get(c, 0.0) + (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
-    md += ["", "Summed kernel time per shape class (the five axis passes; finalize and the final "
-           "reduction left out):", "", "| class | summed us per launch |", "|---|---|"]
+    md += ["", "Summed kernel time per shape class (the axis passes and the whole-field and plane kernels; "
+           "finalize and the final reduction left out).  The one-item-per-workgroup binning kernel's "
+           "template arguments do not name the dimension: its dispatches count as 2D, so a 3D class "
+           "tuned to it (bin_schedule) shows part of its time under a 2D row of the same length "
+           "(here 96 and 128).", "", "| class | summed us per launch |", "|---|---|"]
     for c, t in sorted(cls.items(), key=lambda kv: -kv[1]):
         md.append("| %s | %.1f |" % (c, t / replays))
     with open(os.path.join(ROOT, "profiles", "batch_kernels_c4_uneven_512.md"), "w") as fh:

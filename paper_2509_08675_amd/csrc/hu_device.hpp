@@ -435,6 +435,34 @@ __device__ __forceinline__ void stage_load(float2 (&v)[E], const float* lds, int
   }
 }
 
+// In-place exchange through a strided column: element i of the transform at float2 index i * S
+// of the base (a column of a matrix held row by row in LDS, the column's own storage serving as
+// its exchange region).
+template <int S>
+struct Strided {
+  float2 v;
+};
+
+template <int L, int R, int NS, int P, int E, int S>
+__device__ __forceinline__ void stage_store(const float2 (&v)[E], Strided<S>* lds, int p) {
+  float2* base = reinterpret_cast<float2*>(lds);
+#pragma unroll
+  for (int b = 0; b < E / R; ++b) {
+    const int j0 = StoreMap<R, NS, P, E>::base(p + P * b);
+#pragma unroll
+    for (int r = 0; r < R; ++r) base[(j0 + r * NS) * S] = v[b * R + r];
+  }
+}
+
+template <int L, int R, int P, int E, int S>
+__device__ __forceinline__ void stage_load(float2 (&v)[E], const Strided<S>* lds, int p) {
+  const float2* base = reinterpret_cast<const float2*>(lds);
+#pragma unroll
+  for (int b = 0; b < E / R; ++b)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[b * R + r] = base[(p + P * b + r * (L / R)) * S];
+}
+
 template <int L, int R, int P, int E>
 __device__ __forceinline__ void slot_store(const float2 (&v)[E], float2* lds, int p) {
   using M = LoadMap<L, R, P, E>;
@@ -503,7 +531,8 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[E], X* lds, int p, const 
 // list that reads the same both ways uses the forward rows for both directions (they are the same
 // rows).  WAVE: the P threads of each transform lie in one wave and the region `lds` is theirs
 // alone (row passes with P dividing 64), so the exchanges synchronise the wave only.  `lds` is a
-// complex region (X = float2) or, for the split exchange, a float region of the same positions.
+// complex region (X = float2), for the split exchange a float region of the same positions, or a
+// strided column exchanged in place (X = Strided<S>).
 template <int L, int P, int E, bool INV, bool WAVE = false, int RV = 0, class X = float2, int... Rs>
 __device__ __forceinline__ void fft_run(Radices<Rs...>, float2 (&v)[E], X* lds, int p,
                                         const float2* __restrict__ tw) {

@@ -1,6 +1,6 @@
 // The x-row and y-column transforms of one z-plane of a 3D field in one workgroup, for grids whose
-// plane (n_y rows of n_x/2 + 1 modes) fits in LDS.  Two kernels take the place of four passes of
-// the 3D sequence:
+// plane (n_y rows of n_x/2 + 1 modes, padded) fits in LDS; the y transforms exchange in place.
+// Two kernels take the place of five passes of the 3D sequence:
 //   plane_fwd: noise -> R2C rows -> forward y transform -> the plane's half spectrum to HBM
 //              (replaces rows_r2c_noise and the first y pass);
 //   plane_inv: the plane from HBM -> inverse y transform -> C2R rows, normalisation (Eq. (15)),
@@ -20,11 +20,12 @@ struct PlaneShape {
   static constexpr int PC = Plan<NY>::P, EC = Plan<NY>::E;      // y columns
   static constexpr int NC = LR + 1;                             // half-spectrum columns
   static constexpr int RSR = Region<LR>::value;                 // a row's slot: exchange region, then modes
-  static constexpr int RSC = Region<NY>::value;                 // a column's exchange region
-  static constexpr int TA = NY * PR, TB = NC * PC;
+  // LR column tasks: column t, and task 0 also column LR (the two real y sequences packed into one
+  // complex transform)
+  static constexpr int TA = NY * PR, TB = LR * PC;
   static constexpr int T = ((TA > TB ? TA : TB) + 63) / 64 * 64;
   static_assert(RSR >= LR + 1 && T <= 1024, "plane shape");
-  static constexpr size_t lds_bytes = (size_t)(NY * RSR + NC * RSC) * 8;
+  static constexpr size_t lds_bytes = (size_t)NY * RSR * 8;      // the plane only: columns exchange in place
 };
 
 #define HU_PLANE_SHAPES(X)                                                                          \
@@ -62,23 +63,70 @@ __device__ __forceinline__ void plane_twist(float2* lz, const float2* __restrict
   xchg_sync<true>();
 }
 
-// the y transform (forward, or inverse with the forward radix list as the y passes do) of every
-// column of the plane held in LDS, in place, natural order in and out
+// The y transforms (forward, or inverse with the forward radix list as the y passes do) of the
+// plane held in LDS, natural order in and out, each exchanged in place inside its own column.
+// Columns 0 and LR (k_x = 0 and the x Nyquist index) carry y sequences that are real before the
+// forward transform (the row twist makes X[0] and X[LR] real) and real after the inverse one (the
+// C2R rows use their real parts only): they share one complex transform, z = col_0 + i col_LR,
+// separated afterwards by Hermitian symmetry.  So the plane needs LR column tasks, not LR + 1.
 template <int LR, int NY, bool INV>
-__device__ __forceinline__ void plane_cols(float2* plane, float2* xr, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void plane_cols(float2* plane, const float2* __restrict__ tw, int tid) {
   using S = PlaneShape<LR, NY>;
-  constexpr int PC = S::PC, EC = S::EC, RSR = S::RSR, RSC = S::RSC;
+  constexpr int PC = S::PC, EC = S::EC, RSR = S::RSR;
   using Rad = typename Plan<NY>::fwd;
   constexpr int R1 = RadInfo<Rad>::first, RL = RadInfo<Rad>::last;
-  const int g = tid / PC, pc = tid % PC;
-  if (g < S::NC) {
-    float2 v[EC];
+  const int t = tid / PC, pc = tid % PC;
+  if (t >= LR) return;
+  float2* col = plane + t;
+  float2* colL = plane + LR;
+  float2 v[EC];
 #pragma unroll
-    for (int s = 0; s < EC; ++s) v[s] = plane[slot_index<NY, R1, PC>(s, pc) * RSR + g];
-    fft_run<NY, PC, EC, INV, true>(Rad{}, v, xr + g * RSC, pc, tw);
+  for (int s = 0; s < EC; ++s) {
+    const int e = slot_index<NY, R1, PC>(s, pc);
+    if (t == 0) {
+      const float2 y0 = col[e * RSR], yl = colL[e * RSR];
+      // forward: the real sequences a + i c; inverse: Y0 + i YL
+      v[s] = INV ? make_float2(y0.x - yl.y, y0.y + yl.x) : make_float2(y0.x, yl.x);
+    } else {
+      v[s] = col[e * RSR];
+    }
+  }
+  fft_run<NY, PC, EC, INV, true>(Rad{}, v, reinterpret_cast<Strided<RSR>*>(col), pc, tw);
+  xchg_sync<true>();
+  if (t != 0) {
+#pragma unroll
+    for (int s = 0; s < EC; ++s) col[slot_index<NY, RL, PC>(s, pc) * RSR] = v[s];
+    return;
+  }
+  if constexpr (INV) {
+    // y0 + i yL: both real
+#pragma unroll
+    for (int s = 0; s < EC; ++s) {
+      const int e = slot_index<NY, RL, PC>(s, pc);
+      col[e * RSR] = make_float2(v[s].x, 0.0f);
+      colL[e * RSR] = make_float2(v[s].y, 0.0f);
+    }
+  } else {
+    // Z = A + i C with A, C Hermitian: A[k] = (Z[k] + conj Z[-k]) / 2, C[k] = -i (Z[k] - conj Z[-k]) / 2
+#pragma unroll
+    for (int s = 0; s < EC; ++s) col[slot_index<NY, RL, PC>(s, pc) * RSR] = v[s];
+    xchg_sync<true>();
+    float2 a0[EC], cl[EC];
+#pragma unroll
+    for (int s = 0; s < EC; ++s) {
+      const int k = slot_index<NY, RL, PC>(s, pc);
+      const float2 zk = col[k * RSR];
+      const float2 zm = cconj(col[(k == 0 ? 0 : NY - k) * RSR]);
+      a0[s] = cscale(cadd(zk, zm), 0.5f);
+      cl[s] = cscale(mul_mi<false>(csub(zk, zm)), 0.5f);
+    }
     xchg_sync<true>();
 #pragma unroll
-    for (int s = 0; s < EC; ++s) plane[slot_index<NY, RL, PC>(s, pc) * RSR + g] = v[s];
+    for (int s = 0; s < EC; ++s) {
+      const int k = slot_index<NY, RL, PC>(s, pc);
+      col[k * RSR] = a0[s];
+      colL[k * RSR] = cl[s];
+    }
   }
 }
 
@@ -103,7 +151,6 @@ __global__ void __launch_bounds__((PlaneShape<LR, NY>::T)) k_plane_fwd(RowsArgs 
   constexpr int R1R = RadInfo<RadR>::first, RLR = RadInfo<RadR>::last;
   extern __shared__ float2 lds[];
   float2* plane = lds;
-  float2* xr = lds + NY * RSR;
   const int tid = threadIdx.x, z = blockIdx.x, b = blockIdx.y;
   if (z == 0) {                                  // the first row pass's set-up duties for this field
     if (b == 0)
@@ -153,7 +200,7 @@ __global__ void __launch_bounds__((PlaneShape<LR, NY>::T)) k_plane_fwd(RowsArgs 
     plane_twist<LR, PR, ER>(lrow, a.tw2, pr);
   }
   __syncthreads();
-  plane_cols<LR, NY, false>(plane, xr, a.tw_y, tid);
+  plane_cols<LR, NY, false>(plane, a.tw_y, tid);
   __syncthreads();
   plane_copy<LR, NY>(a.spec + (long long)b * a.Nh + (long long)z * NY * S::NC, nullptr, plane, tid, false);
 }
@@ -168,12 +215,11 @@ __global__ void __launch_bounds__((PlaneShape<LR, NY>::T)) k_plane_inv(RowsZArgs
   extern __shared__ float2 lds[];
   __shared__ unsigned red_u[2][T / 64];
   float2* plane = lds;
-  float2* xr = lds + NY * RSR;
   const int tid = threadIdx.x, z = blockIdx.x, b = blockIdx.y;
   float2* sp = a.spec + (long long)b * a.Nh + (long long)z * NY * S::NC;
   plane_copy<LR, NY>(nullptr, sp, plane, tid, true);
   __syncthreads();
-  plane_cols<LR, NY, true>(plane, xr, a.tw_y, tid);
+  plane_cols<LR, NY, true>(plane, a.tw_y, tid);
   __syncthreads();
   // rows: C2R, normalisation, field, sign map, counts, R2C of the +-1 row
   const double* fs = a.fstats + (long long)b * 8;
@@ -244,7 +290,7 @@ __global__ void __launch_bounds__((PlaneShape<LR, NY>::T)) k_plane_inv(RowsZArgs
     reinterpret_cast<uint2*>(a.cpart)[(long long)b * gridDim.x + z] = make_uint2(np, nn);
   }
   if (!(THRESH && a.pm1_spec)) return;            // uniform over the workgroup
-  plane_cols<LR, NY, false>(plane, xr, a.tw_y, tid);
+  plane_cols<LR, NY, false>(plane, a.tw_y, tid);
   __syncthreads();
   plane_copy<LR, NY>(sp, nullptr, plane, tid, false);
 }

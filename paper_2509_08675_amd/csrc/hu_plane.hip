@@ -107,25 +107,22 @@ __device__ __forceinline__ void plane_cols(float2* plane, const float2* __restri
       colL[e * RSR] = make_float2(v[s].y, 0.0f);
     }
   } else {
-    // Z = A + i C with A, C Hermitian: A[k] = (Z[k] + conj Z[-k]) / 2, C[k] = -i (Z[k] - conj Z[-k]) / 2
+    // Z = A + i C with A, C Hermitian: A[k] = (Z[k] + conj Z[-k]) / 2, C[k] = -i (Z[k] - conj Z[-k]) / 2,
+    // and A[-k] = conj A[k], C[-k] = conj C[k]: each thread takes the pairs (k, NY - k), k <= NY / 2,
+    // reading and writing only their own positions (no barrier, no register arrays)
 #pragma unroll
     for (int s = 0; s < EC; ++s) col[slot_index<NY, RL, PC>(s, pc) * RSR] = v[s];
     xchg_sync<true>();
-    float2 a0[EC], cl[EC];
-#pragma unroll
-    for (int s = 0; s < EC; ++s) {
-      const int k = slot_index<NY, RL, PC>(s, pc);
+    for (int k = pc; k <= NY / 2; k += PC) {
+      const int m = k == 0 ? 0 : NY - k;
       const float2 zk = col[k * RSR];
-      const float2 zm = cconj(col[(k == 0 ? 0 : NY - k) * RSR]);
-      a0[s] = cscale(cadd(zk, zm), 0.5f);
-      cl[s] = cscale(mul_mi<false>(csub(zk, zm)), 0.5f);
-    }
-    xchg_sync<true>();
-#pragma unroll
-    for (int s = 0; s < EC; ++s) {
-      const int k = slot_index<NY, RL, PC>(s, pc);
-      col[k * RSR] = a0[s];
-      colL[k * RSR] = cl[s];
+      const float2 zm = cconj(col[m * RSR]);
+      const float2 ak = cscale(cadd(zk, zm), 0.5f);
+      const float2 ck = cscale(mul_mi<false>(csub(zk, zm)), 0.5f);
+      col[k * RSR] = ak;
+      colL[k * RSR] = ck;
+      col[m * RSR] = cconj(ak);
+      colL[m * RSR] = cconj(ck);
     }
   }
 }

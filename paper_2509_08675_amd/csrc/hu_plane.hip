@@ -179,13 +179,12 @@ __global__ void __launch_bounds__((PlaneShape<LR, NY>::T)) k_plane_fwd(RowsArgs 
     seed = uniform_u64(seed);
     float2* lrow = plane + r * RSR;
     const uint64_t m0 = ((uint64_t)z * NY + (uint64_t)r) * (NX / 4);
-    if constexpr ((NX % 4) == 0) {
-      for (int j = pr; j < NX / 4; j += PR) {
-        float zz[4];
-        noise4(m0 + (uint64_t)j, seed, zz);
-        lrow[lidx(2 * j)] = make_float2(zz[0], zz[1]);
-        lrow[lidx(2 * j + 1)] = make_float2(zz[2], zz[3]);
-      }
+    static_assert((NX % 4) == 0, "a row holds whole Philox blocks");
+    for (int j = pr; j < NX / 4; j += PR) {
+      float zz[4];
+      noise4(m0 + (uint64_t)j, seed, zz);
+      lrow[lidx(2 * j)] = make_float2(zz[0], zz[1]);
+      lrow[lidx(2 * j + 1)] = make_float2(zz[2], zz[3]);
     }
     xchg_sync<true>();
     float2 v[ER];

@@ -20,8 +20,9 @@ field within tolerance):
 * +-1 bins rtol 1e-5 when no site flips; with m flipped sites each mode's |T(k)|^2 / N moves by
   at most (4 m |T(k)| + 4 m^2) / N, so a bin may move by its multiplicity-weighted sum of that.
 
-Every comparison appends one JSON line with the measured errors to
-``gpurun_out/parity_report.jsonl`` (relative to the repository root): field err/RMS, flips,
+Every comparison appends one JSON line with the measured errors to the file that the environment
+variable HU_PARITY_REPORT names, when it is set (a relative path is taken from the repository
+root): field err/RMS, flips,
 near-zero sites, mean and variance errors, and for each spectrum the largest relative bin error
 in three bands of bin magnitude (>= 1e-3 of the largest bin, 1e-9 .. 1e-3, below 1e-9).
 """
@@ -35,7 +36,7 @@ import numpy as np
 import oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-REPORT = os.path.join(ROOT, "gpurun_out", "parity_report.jsonl")
+REPORT = os.path.join(ROOT, os.environ["HU_PARITY_REPORT"]) if os.environ.get("HU_PARITY_REPORT") else None
 
 FIELD_TOL = 1e-5
 NEAR_TOL = 1e-5
@@ -45,7 +46,9 @@ UNDERFLOW_FLOOR = 1e-30
 
 
 def record(kind, name, **kw):
-    """Append one line of measured errors to the parity report."""
+    """Append one line of measured errors to the parity report (when one is named)."""
+    if REPORT is None:
+        return
     try:
         os.makedirs(os.path.dirname(REPORT), exist_ok=True)
         with open(REPORT, "a") as fh:

@@ -387,6 +387,39 @@ def test_full_size_sampled(hf, cfg, sample, plan):
 
 @pytest.mark.slow
 @pytest.mark.timeout(600)
+def test_largest_accepted_grid_properties(hf):
+    """The largest 3D grid the library accepts, 768 x 1024 x 1024 (805M voxels), one field: its
+    3.2 GB half spectrum takes the passes' unsigned 32-bit byte offsets past 2^31.  The oracle
+    cannot run at this size, so the test checks properties that hold at any size: the moments of
+    Eq. (15), the sign map against the sign of the field at every voxel, the positive count
+    against the sign map, and Parseval for both spectra (their bins sum to N, as do their
+    counts)."""
+    dims, bins = (768, 1024, 1024), (64, 1)
+    free, _ = torch.cuda.mem_get_info()
+    if free < (24 << 30):
+        pytest.skip("needs 24 GB of free device memory")
+    N = int(np.prod(dims))
+    _say("largest grid", dims)
+    bufs = hf.PipelineBuffers(dims, 1, bins)
+    hf.pipeline(bufs, W.C3["filt"], [5])
+    torch.cuda.synchronize()
+    hf.check_degenerate(bufs.stats)
+    f = bufs.field[0]
+    mean = f.double().mean().item()
+    var = f.double().var(unbiased=False).item()
+    _say("   mean %.3e var - 1 %.3e" % (mean, var - 1.0))
+    assert abs(mean) < 1e-5 and abs(var - 1.0) < 1e-5
+    pos = f >= 0
+    assert torch.equal(bufs.pm1[0] > 0, pos) and torch.equal(bufs.pm1[0] != 0, torch.ones_like(pos))
+    assert int(bufs.counts[0, 0].item()) == int(pos.sum().item())
+    del pos
+    for s_, c_ in ((bufs.cont_sum[0], bufs.cont_cnt[0]), (bufs.pm1_sum[0], bufs.pm1_cnt[0])):
+        assert abs(s_.sum().item() - N) <= 1e-5 * N
+        assert int(c_.sum().item()) == N
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
 def test_full_size_512cube_forward(hf):
     """The 512^3 forward field with its 128-bin continuous spectrum (the adjoint workload's forward
     half, one field) against the oracle: every voxel, the raw moments and every bin."""

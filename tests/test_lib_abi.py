@@ -65,8 +65,13 @@ def test_workspace_sizes(hf):
         hf.workspace_size(hf.HU_OP_PIPELINE, (64, 64), 64, (8, 1))
 
 
+# the largest accepted grids: each side at most 2048 (2^k) or 768 (3 * 2^k), and one field's FP32
+# half spectrum below 4 GiB (the passes address it with unsigned 32-bit byte offsets): 768 x 1024^2
+# (3.2 GB) passes, 1024^3 and 2048 x 1024 x 512 (4.3 GB) do not
 @pytest.mark.parametrize("dims,code", [((100, 128), -2), ((4096, 64), -2), ((64, 2), -2), ((64,), -1),
-                                       ((8, 8, 8, 8), -1), ((1536, 64), -2), ((64, 96), 0), ((768, 12), 0)])
+                                       ((8, 8, 8, 8), -1), ((1536, 64), -2), ((64, 96), 0), ((768, 12), 0),
+                                       ((2048, 2048), 0), ((768, 1024, 1024), 0), ((1024, 1024, 768), 0),
+                                       ((1024, 1024, 1024), -2), ((2048, 1024, 512), -2), ((4, 4), 0)])
 def test_size_validation(hf, dims, code):
     out = ctypes.c_size_t()
     d = hf.hu_dims()

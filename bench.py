@@ -351,6 +351,23 @@ def time_window_variance(hf, torch, cfg, steps, radii=(1.0, 2.0, 4.0, 8.0, 16.0,
                                                                                    prof["cols_wvar"][0] * 1e-3), 1))
 
 
+def small_k_after_threshold(hf, torch, cfg, nfit=8):
+    """The small-k exponent (Sec. II.A) of the continuous spectrum and of the +-1 map's spectrum of
+    the workload's fields (bins pooled over the fields), each with its class of Eqs. (6)-(7): how
+    far the threshold refills the low-k hole of the spectrum.  Over a narrow band the continuous
+    spectrum's log-slope at the first radial bins exceeds alpha, since the band's Gaussian factor
+    adds K (k0 - K) / w^2 to it."""
+    dims, bins, seeds = cfg["dims"], cfg["bins"], cfg["seeds"]
+    bufs = hf.PipelineBuffers(dims, len(seeds), bins)
+    hf.pipeline(bufs, cfg["filt"], seeds)
+    torch.cuda.synchronize()
+    out = dict(fields=len(seeds), nfit_radial_bins=nfit, filter_alpha=cfg["filt"]["alpha"])
+    for name, s, c in (("continuous", bufs.cont_sum, bufs.cont_cnt), ("pm1", bufs.pm1_sum, bufs.pm1_cnt)):
+        a = hf.small_k_exponent(s.sum(0), c.sum(0), bins, nfit)
+        out[name] = dict(exponent=round(a, 3), hyperuniformity_class=hf.hyperuniformity_class(a, len(dims), tol=0.05))
+    return out
+
+
 def time_two_point(hf, torch, cfg, steps, phi=0.35):
     """Level cut of the workload's fields at volume fraction phi and the two-point function S_2 of
     the resulting maps (fields generated by the pipeline beforehand, resident in HBM)."""
@@ -942,6 +959,8 @@ def main():
         line["also"]["level_cut_and_two_point_256cube_x4"] = time_two_point(hf, torch, C3, max(args.steps // 5, 5))
         line["also"]["mask_variants_2048sq_x16"] = time_mask_variants(hf, torch, C2, max(args.steps // 5, 5))
         line["also"]["small_2d_fields"] = time_small_fields(hf, torch, max(args.steps // 5, 5))
+        line["also"]["small_k_exponent_after_threshold"] = {c["name"]: small_k_after_threshold(hf, torch, c)
+                                                            for c in (C2, C3)}
     line["parity"] = parity_c1(hf, torch)
     line["paper_context"] = paper_context(hf, torch)
     if not args.no_cpu_baseline:
